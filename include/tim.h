@@ -1,0 +1,242 @@
+/*
+ * tim.h — C ABI of the MI355X (gfx950) TIM / TIM+ engine.
+ *
+ * Paper: Tang, Xiao, Shi, "Influence Maximization: Near-Optimal Time
+ * Complexity Meets Practical Efficiency", SIGMOD 2014.
+ *
+ * The library computes, on one GPU, the data-parallel hot path of TIM/TIM+:
+ * random reverse-reachable (RR) sets (Definitions 1-2), their widths and
+ * kappa values (Equation (1), Equation (8)), KptEstimation (Algorithm 2),
+ * RefineKPT (Algorithm 3) and greedy maximum-coverage NodeSelection
+ * (Algorithm 1), assembled into TIM (Section 3.3) and TIM+ (Section 4.1).
+ *
+ * Results are deterministic functions of (graph, model, k, eps, ell, seed):
+ * every random number is a Philox4x32-10 block keyed by the seed and
+ * addressed by (phase, kind, index, set id), so a set can be regenerated
+ * anywhere and the output does not depend on launch geometry or timing.
+ *   key     = (seed & 0xFFFFFFFF, seed >> 32)
+ *   counter = (idx & 0xFFFFFFFF, phase<<24 | kind<<16 | (idx>>32 & 0xFFFF),
+ *              set & 0xFFFFFFFF, set >> 32)
+ *   kind 0: root of the set (idx 0); root = floor(X64 * n / 2^64) with
+ *           X64 = word1<<32 | word0
+ *   kind 1: IC coins, idx = e >> 2 for in-CSR edge e; word e & 3 decides e:
+ *           live iff word <= t(e) (t(e) = uint32 threshold; weighted cascade:
+ *           t = floor(2^32 / indeg(dst)) - 1)
+ *   kind 2: LT pick at node v (idx = v); in-edge off[v] + floor(X64*indeg/2^64)
+ *   phase i in [1, 62]: KptEstimation round i; 63: RefineKPT's fresh sets;
+ *   64: NodeSelection's sets.  Set ids start at 0 in every phase.
+ *
+ * Conventions for every call:
+ *   - Status codes only; nothing is thrown across the ABI.  On failure,
+ *     tim_last_error() returns a message for the calling thread.
+ *   - "host" pointers are ordinary CPU memory owned by the caller and only
+ *     read or written during the call.  "device" pointers are GPU memory
+ *     owned by the caller (for example torch tensors on the ROCm device).
+ *   - All GPU work is ordered on the context's stream; every call returns
+ *     after that work has finished (results are final on return).
+ *   - One context per host thread; calls on one context must not overlap.
+ *   - Node ids are int32 (n < 2^31), CSR offsets int64.
+ */
+#ifndef TIM_H_
+#define TIM_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define TIM_ABI_VERSION 1
+
+typedef enum {
+  TIM_OK = 0,
+  TIM_EINVAL = 1,    /* an argument is out of range or a graph is malformed */
+  TIM_ENOMEM = 2,    /* a host or device allocation failed */
+  TIM_EBUDGET = 3,   /* the work does not fit the context's device-memory budget */
+  TIM_EDEVICE = 4,   /* a HIP runtime call or kernel launch failed */
+  TIM_ECAPACITY = 5  /* a caller-provided output buffer is too small */
+} tim_status;
+
+typedef enum {
+  TIM_MODEL_IC = 0, /* independent cascade (Section 2.1) */
+  TIM_MODEL_LT = 1  /* linear threshold with in-weights 1/indeg(v): a triggering
+                       model whose triggering set is one uniform in-neighbour
+                       (Section 4.2; Section 7.1) */
+} tim_model;
+
+enum { TIM_PHASE_REFINE = 63, TIM_PHASE_SELECT = 64 };
+
+enum {
+  TIM_FLAG_PLAIN = 1u,      /* TIM (Section 3.3): skip RefineKPT, theta = lambda/KPT* */
+  TIM_FLAG_ELL_ADJUST = 2u  /* scale ell by 1 + ln2/ln n (TIM) or 1 + ln3/ln n (TIM+)
+                               so that the overall success probability is 1 - n^-ell
+                               (Sections 3.3 and 4.1) */
+};
+
+#define TIM_MAX_ROUNDS 64
+
+typedef struct tim_ctx tim_ctx;
+typedef struct tim_graph tim_graph;
+
+/* Per-launch totals of a batch of RR sets. */
+typedef struct {
+  uint64_t count;        /* sets generated */
+  uint64_t kappa_sum_lo; /* sum over sets of kappa(R) * 2^53, low 64 bits (exact) */
+  uint64_t kappa_sum_hi; /* ... high 64 bits */
+  uint64_t width_sum;    /* sum of w(R) = edges examined (Equation (1)) */
+  uint64_t node_sum;     /* sum of |R| */
+  uint64_t covered;      /* sets that meet the seed set (coverage mode only) */
+  uint64_t deferred;     /* sets finished by the large-set pass */
+} tim_batch_stats;
+
+/* KptEstimation (Algorithm 2). */
+typedef struct {
+  int32_t i_max;   /* number of rounds allowed: floor(log2 n) - 1 */
+  int32_t i_last;  /* round that stopped (i_max if none did) */
+  uint64_t c_last; /* c_i of that round */
+  double kpt_star; /* KPT*; 1.0 if no round stopped */
+  uint64_t round_c[TIM_MAX_ROUNDS];      /* indexed by round i (entry 0 unused) */
+  uint64_t round_sum_lo[TIM_MAX_ROUNDS]; /* exact sum of kappa * 2^53, low/high words */
+  uint64_t round_sum_hi[TIM_MAX_ROUNDS];
+  uint64_t round_width[TIM_MAX_ROUNDS];
+  uint64_t round_nodes[TIM_MAX_ROUNDS];
+} tim_kpt_result;
+
+/* RefineKPT (Algorithm 3). */
+typedef struct {
+  double eps_prime;       /* 5 * cbrt(ell * eps^2 / (k + ell)) */
+  double lambda_prime;    /* (2 + eps') * ell * n * ln n / eps'^2 */
+  uint64_t theta_prime;   /* ceil(lambda' / KPT*) */
+  uint64_t covered_prime; /* fresh sets that meet S'_k */
+  double kpt_prime;       /* (covered'/theta') * n / (1 + eps') */
+  double kpt_plus;        /* max(KPT', KPT*) */
+} tim_refine_result;
+
+/* NodeSelection (Algorithm 1). */
+typedef struct {
+  uint64_t theta;     /* sets generated */
+  uint64_t nodes;     /* total size of the RR collection */
+  uint64_t width;     /* total width (edges examined) */
+  uint64_t covered;   /* sets covered by the k seeds = sum of gains */
+  uint64_t store_bytes; /* device bytes of the RR collection and its index */
+} tim_select_result;
+
+/* Everything tim_run computes, with per-phase GPU times in milliseconds. */
+typedef struct {
+  double ell_used;
+  double lambda;
+  tim_kpt_result kpt;
+  tim_refine_result refine;
+  tim_select_result select;
+  int32_t s_prime[128]; /* S'_k of RefineKPT (first min(k,128) entries) */
+  double ms_kpt, ms_refine, ms_select_sample, ms_select_index, ms_select_greedy, ms_total;
+  uint64_t sets_total;  /* RR sets generated over all phases */
+  uint64_t width_total; /* edges examined over all phases */
+} tim_report;
+
+/* ---- context ------------------------------------------------------------ */
+
+/* Creates a context on HIP device `device`.  `stream` is a hipStream_t to
+ * order work on (NULL: the library creates its own).  `hbm_budget_bytes`
+ * caps the device memory the library allocates for RR sets and their index
+ * (0: no cap).  Returns TIM_EDEVICE if the device cannot be used. */
+tim_status tim_ctx_create(int device, void *stream, uint64_t hbm_budget_bytes, tim_ctx **out);
+void tim_ctx_destroy(tim_ctx *ctx);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *tim_last_error(void);
+
+/* Bytes of device memory currently held by the context (graphs excluded). */
+uint64_t tim_ctx_device_bytes(const tim_ctx *ctx);
+
+/* ---- graph (Table 1: G^T as in-edge CSR) --------------------------------- */
+
+/* Copies a directed graph to the device.
+ *   in_off  host int64[n+1]: in-edges of v are positions in_off[v]..in_off[v+1]-1
+ *   in_src  host int32[m]:   source of each in-edge, sorted by (dst, src),
+ *                            no self-loops, no repeated edges
+ *   ic_thr  host uint32[m] or NULL: IC threshold t(e) = floor(p(e)*2^32) - 1 of
+ *           each edge (p(e) = (t+1)/2^32).  NULL selects the weighted cascade
+ *           p(e) = 1/indeg(dst) of Section 7.1.  LT ignores it.
+ * Requires 2 <= n < 2^31, 1 <= m.  TIM_EINVAL names the first violation. */
+tim_status tim_graph_upload(tim_ctx *ctx, int64_t n, int64_t m, const int64_t *in_off, const int32_t *in_src,
+                            const uint32_t *ic_thr, tim_graph **out);
+void tim_graph_free(tim_graph *g);
+
+/* ---- RR sets (Definitions 1-2; Section 3.1; Section 4.2) ---------------- */
+
+/* Generates sets [first, first+count) of (seed, phase) and writes them as a
+ * CSR in caller device memory:
+ *   d_set_off  device int64[count+1]: set j is d_nodes[d_set_off[j] .. d_set_off[j+1])
+ *   d_nodes    device int32[nodes_capacity]: the nodes of each set (order
+ *              within a set unspecified)
+ *   d_widths   device uint64[count] or NULL: w(R) of each set (Equation (1))
+ * *total_nodes (host) receives the total size.  If it exceeds nodes_capacity,
+ * nothing is written to d_nodes and TIM_ECAPACITY is returned; call again with
+ * a buffer of *total_nodes entries.  stats (host, nullable) receives totals. */
+tim_status tim_sample_rr(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, uint32_t phase, uint64_t first,
+                         uint64_t count, int64_t *d_set_off, int32_t *d_nodes, uint64_t nodes_capacity,
+                         uint64_t *d_widths, uint64_t *total_nodes, tim_batch_stats *stats);
+
+/* Generates sets [first, first+count) of (seed, phase) without storing them,
+ * and accumulates kappa(R) = 1 - (1 - w(R)/m)^k (Equation (8)) as the exact
+ * integer sum of kappa * 2^53 (kappa in binary64: q = 1 - w/m, q^k by binary
+ * exponentiation, no fused multiply-add).  d_widths / d_sizes (device
+ * uint64[count] / uint32[count], nullable) receive w(R) and |R| per set. */
+tim_status tim_sample_widths(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, uint32_t phase,
+                             uint64_t first, uint64_t count, int k, uint64_t *d_widths, uint32_t *d_sizes,
+                             tim_batch_stats *stats);
+
+/* Generates sets [first, first+count) of (seed, phase) and counts those that
+ * contain at least one of the nodes seeds[0..nseeds) (host int32), as in
+ * Algorithm 3 lines 9-10.  The count is in stats->covered. */
+tim_status tim_sample_cover(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, uint32_t phase,
+                            uint64_t first, uint64_t count, const int32_t *seeds, int nseeds,
+                            tim_batch_stats *stats);
+
+/* ---- greedy maximum coverage (Algorithm 1 lines 3-7) -------------------- */
+
+/* Runs the greedy on a caller-supplied collection of nsets sets over nodes
+ * [0, n) (d_set_off device int64[nsets+1], d_nodes device int32; sets must not
+ * repeat a node).  Each step takes the unselected node that covers the most
+ * remaining sets (ties: lowest id) and removes the sets it covers; seeds and
+ * gains (host int32[k] / uint64[k]) receive the nodes in selection order and
+ * the number of sets each one newly covered. */
+tim_status tim_max_coverage(tim_ctx *ctx, int64_t n, uint64_t nsets, const int64_t *d_set_off, const int32_t *d_nodes,
+                            int k, int32_t *seeds, uint64_t *gains);
+
+/* ---- the three phases ---------------------------------------------------- */
+
+/* KptEstimation (Algorithm 2): rounds i = 1 .. floor(log2 n)-1 of
+ * c_i = ceil((6*ell*ln n + 6*ln(log2 n)) * 2^i) sets (Equation (9)); stops at
+ * the first round whose exact kappa sum S satisfies S * 2^i > c_i * 2^53 and
+ * returns KPT* = (S * 2^-53) * n / (2 * c_i); KPT* = 1 if no round stops.
+ * Requires 1 <= k <= n, ell >= 0.5. */
+tim_status tim_kpt_estimate(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, int k, double ell,
+                            tim_kpt_result *out);
+
+/* RefineKPT (Algorithm 3): greedy on the sets of round i_last (regenerated
+ * from their keys) gives S'_k (s_prime, host int32[k]); theta' fresh sets of
+ * phase 63 estimate KPT' and KPT+ = max(KPT', KPT*).  Requires 0 < eps <= 1
+ * (the range the paper gives for its eps' rule). */
+tim_status tim_refine_kpt(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, int k, double eps, double ell,
+                          double kpt_star, int i_last, uint64_t c_last, int32_t *s_prime, tim_refine_result *out);
+
+/* NodeSelection (Algorithm 1): theta sets of phase 64, then k greedy steps.
+ * seeds / gains: host int32[k] / uint64[k].  out (host) may be NULL. */
+tim_status tim_node_select(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, int k, uint64_t theta,
+                           int32_t *seeds, uint64_t *gains, tim_select_result *out);
+
+/* TIM+ (default) or TIM (TIM_FLAG_PLAIN): KptEstimation, [RefineKPT],
+ * theta = ceil(lambda / KPT+ (or KPT*)) with lambda of Equation (4), then
+ * NodeSelection.  Requires 1 <= k <= n, 0 < eps <= 1, ell >= 0.5.
+ * seeds / gains: host int32[k] / uint64[k] (gains nullable); rep nullable. */
+tim_status tim_run(tim_ctx *ctx, const tim_graph *g, int model, int k, double eps, double ell, uint64_t seed,
+                   uint32_t flags, int32_t *seeds, uint64_t *gains, tim_report *rep);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* TIM_H_ */

@@ -1,0 +1,210 @@
+/*
+ * Exhaustive checker for the CPU oracle — test infrastructure only.
+ *
+ * For graphs with at most 24 edges (IC) or a small product of in-degrees
+ * (LT), every live-edge world is enumerated with its exact probability, so the
+ * quantities the paper's lemmas talk about are computed exactly, with no
+ * sampling and without the oracle's random-number stream:
+ *   - E[I(S)] for every seed set S (the live-edge view of Section 2.2: the
+ *     spread is the expected number of nodes reachable from S when each edge
+ *     is kept with its probability);
+ *   - Pr[u in R], E[w(R)] and E[kappa(R)] of a random RR set (Definition 2,
+ *     Equation (1), Equation (8)).
+ * IC edge e is kept with probability (t(e) + 1) / 2^32, the probability that
+ * a uniform 32-bit word is <= its uint32 threshold t(e); under the weighted
+ * cascade t = floor(2^32/indeg) - 1.  LT: every node of in-degree d >= 1 keeps
+ * exactly one in-edge, each with probability 1/d.
+ * Node sets are bit masks, so n <= 20.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+typedef struct {
+  int n, m;
+  int eu[64], ev[64]; /* edge e: eu[e] -> ev[e] */
+  int indeg[32];
+  long double p[64];  /* IC keep probability */
+  int first_in[33];   /* in-edges of v are [first_in[v], first_in[v+1]) in CSR order */
+} bgraph;
+
+static int load(bgraph *g, int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr) {
+  if (n < 1 || n > 20 || m < 0 || m > 63) return -1;
+  g->n = (int)n;
+  g->m = (int)m;
+  for (int v = 0; v < n; ++v) {
+    g->first_in[v] = (int)off[v];
+    g->indeg[v] = (int)(off[v + 1] - off[v]);
+    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+      g->eu[e] = src[e];
+      g->ev[e] = v;
+      uint64_t t;
+      if (thr) t = thr[e];
+      else t = (((uint64_t)1 << 32) / (uint64_t)g->indeg[v]) - 1;
+      g->p[e] = ((long double)t + 1.0L) / 4294967296.0L;
+    }
+  }
+  g->first_in[n] = (int)m;
+  return 0;
+}
+
+/* Nodes reachable from each node along live edges (reach[u] includes u). */
+static void forward_reach(const bgraph *g, uint64_t live, uint32_t *reach) {
+  for (int u = 0; u < g->n; ++u) reach[u] = 1u << u;
+  int changed = 1;
+  while (changed) {
+    changed = 0;
+    for (int e = 0; e < g->m; ++e) {
+      if (!((live >> e) & 1u)) continue;
+      /* u -> v live: everything v reaches, u reaches */
+      uint32_t before = reach[g->eu[e]];
+      uint32_t after = before | reach[g->ev[e]];
+      if (after != before) { reach[g->eu[e]] = after; changed = 1; }
+    }
+  }
+}
+
+typedef void (*world_fn)(const bgraph *g, uint64_t live, long double prob, void *ctx);
+
+/* Calls fn once per live-edge world.  Returns the number of worlds, or -1. */
+static int64_t for_each_world(const bgraph *g, int model, world_fn fn, void *ctx) {
+  if (model == 0) {
+    if (g->m > 24) return -1;
+    uint64_t worlds = (uint64_t)1 << g->m;
+    for (uint64_t live = 0; live < worlds; ++live) {
+      long double prob = 1.0L;
+      for (int e = 0; e < g->m; ++e) prob *= ((live >> e) & 1u) ? g->p[e] : (1.0L - g->p[e]);
+      if (prob == 0.0L) continue;
+      fn(g, live, prob, ctx);
+    }
+    return (int64_t)worlds;
+  }
+  /* LT: a mixed-radix counter over the in-edge choice of each node */
+  int choice[32];
+  int64_t worlds = 1;
+  for (int v = 0; v < g->n; ++v) {
+    choice[v] = 0;
+    if (g->indeg[v] > 0) worlds *= g->indeg[v];
+    if (worlds > ((int64_t)1 << 26)) return -1;
+  }
+  for (int64_t w = 0; w < worlds; ++w) {
+    uint64_t live = 0;
+    long double prob = 1.0L;
+    for (int v = 0; v < g->n; ++v) {
+      if (g->indeg[v] == 0) continue;
+      live |= (uint64_t)1 << (g->first_in[v] + choice[v]);
+      prob /= (long double)g->indeg[v];
+    }
+    fn(g, live, prob, ctx);
+    for (int v = 0; v < g->n; ++v) {
+      if (g->indeg[v] == 0) continue;
+      if (++choice[v] < g->indeg[v]) break;
+      choice[v] = 0;
+    }
+  }
+  return worlds;
+}
+
+/* ---- E[I(S)] for every S ---- */
+typedef struct {
+  long double *acc; /* 2^n entries */
+  uint32_t *reach;
+  uint32_t *uni;
+} spread_ctx;
+
+static void spread_world(const bgraph *g, uint64_t live, long double prob, void *vctx) {
+  spread_ctx *c = (spread_ctx *)vctx;
+  forward_reach(g, live, c->reach);
+  uint32_t full = 1u << g->n;
+  c->uni[0] = 0;
+  for (uint32_t mask = 1; mask < full; ++mask) {
+    int low = __builtin_ctz(mask);
+    c->uni[mask] = c->uni[mask & (mask - 1)] | c->reach[low];
+    c->acc[mask] += prob * (long double)__builtin_popcount(c->uni[mask]);
+  }
+}
+
+int brute_all_spreads(int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr, int model,
+                      double *out) {
+  bgraph g;
+  if (load(&g, n, m, off, src, thr) || n > 16) return -1;
+  uint32_t full = 1u << n;
+  spread_ctx c;
+  c.acc = (long double *)calloc(full, sizeof(long double));
+  c.reach = (uint32_t *)calloc(32, sizeof(uint32_t));
+  c.uni = (uint32_t *)calloc(full, sizeof(uint32_t));
+  if (!c.acc || !c.reach || !c.uni) { free(c.acc); free(c.reach); free(c.uni); return -2; }
+  int64_t w = for_each_world(&g, model, spread_world, &c);
+  for (uint32_t mask = 0; mask < full; ++mask) out[mask] = (double)c.acc[mask];
+  free(c.acc); free(c.reach); free(c.uni);
+  return w < 0 ? -1 : 0;
+}
+
+/* ---- random RR set statistics ---- */
+typedef struct {
+  int k;
+  long double p_in[32];  /* Pr[u in R] */
+  long double ew;        /* E[w(R)] */
+  long double ekappa;    /* E[kappa(R)], kappa = 1 - (1 - w/m)^k in long double */
+  long double esize;     /* E[|R|] */
+  uint32_t reach[32];
+} rr_ctx;
+
+static void rr_world(const bgraph *g, uint64_t live, long double prob, void *vctx) {
+  rr_ctx *c = (rr_ctx *)vctx;
+  forward_reach(g, live, c->reach);
+  long double pr = prob / (long double)g->n; /* uniform root */
+  for (int root = 0; root < g->n; ++root) {
+    /* R = the nodes that reach the root */
+    uint32_t r = 0;
+    for (int u = 0; u < g->n; ++u)
+      if ((c->reach[u] >> root) & 1u) r |= 1u << u;
+    long w = 0;
+    for (int u = 0; u < g->n; ++u)
+      if ((r >> u) & 1u) { c->p_in[u] += pr; w += g->indeg[u]; }
+    c->ew += pr * (long double)w;
+    c->esize += pr * (long double)__builtin_popcount(r);
+    long double q = 1.0L - (long double)w / (long double)g->m;
+    c->ekappa += pr * (1.0L - powl(q, (long double)c->k));
+  }
+}
+
+int brute_rr_stats(int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr, int model, int k,
+                   double *p_in, double *ew, double *ekappa, double *esize) {
+  bgraph g;
+  if (load(&g, n, m, off, src, thr) || m < 1) return -1;
+  rr_ctx c;
+  memset(&c, 0, sizeof(c));
+  c.k = k;
+  if (for_each_world(&g, model, rr_world, &c) < 0) return -1;
+  for (int u = 0; u < n; ++u) p_in[u] = (double)c.p_in[u];
+  *ew = (double)c.ew;
+  *ekappa = (double)c.ekappa;
+  *esize = (double)c.esize;
+  return 0;
+}
+
+/* ---- optimum coverage of a set collection by k nodes (n <= 20) ---- */
+int64_t brute_max_coverage(int64_t n, uint64_t nsets, const int64_t *set_off, const int32_t *set_nodes, int k,
+                           uint32_t *best_mask) {
+  if (n > 20 || k < 0) return -1;
+  uint32_t *sm = (uint32_t *)malloc(sizeof(uint32_t) * (size_t)(nsets ? nsets : 1));
+  if (!sm) return -2;
+  for (uint64_t s = 0; s < nsets; ++s) {
+    sm[s] = 0;
+    for (int64_t i = set_off[s]; i < set_off[s + 1]; ++i) sm[s] |= 1u << set_nodes[i];
+  }
+  int64_t best = -1;
+  uint32_t bm = 0;
+  uint32_t full = 1u << n;
+  for (uint32_t mask = 0; mask < full; ++mask) {
+    if (__builtin_popcount(mask) != k) continue;
+    int64_t cov = 0;
+    for (uint64_t s = 0; s < nsets; ++s) cov += (sm[s] & mask) != 0;
+    if (cov > best) { best = cov; bm = mask; }
+  }
+  free(sm);
+  if (best_mask) *best_mask = bm;
+  return best;
+}

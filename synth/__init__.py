@@ -1,0 +1,120 @@
+"""Seeded synthetic inputs shared by the HIP path and the CPU oracle.
+
+Only input data is produced here: graphs as canonical in-edge CSR arrays
+(int64 offsets, int32 sources sorted by (dst, src)), small hand-made graphs,
+and per-edge threshold arrays drawn at random.  Nothing here computes RR sets,
+coins, widths or any other step of the influence-maximisation method.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libsynth.so")
+_lib = None
+
+
+def build() -> str:
+    """Compile the Chung-Lu generator into synth/libsynth.so (gcc)."""
+    src = os.path.join(_HERE, "chunglu.c")
+    tmp = _LIB_PATH + ".tmp"
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, src, "-lm"])
+    os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        lib.synth_chung_lu.restype = ctypes.c_int
+        lib.synth_chung_lu.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        _lib = lib
+    return _lib
+
+
+@dataclass
+class Graph:
+    """In-edge CSR of a directed graph: in-edges of v are src[off[v]:off[v+1]]."""
+    n: int
+    m: int
+    off: np.ndarray  # int64[n+1]
+    src: np.ndarray  # int32[m]
+    name: str = ""
+
+    def indeg(self) -> np.ndarray:
+        return np.diff(self.off)
+
+
+def chung_lu(n: int, m: int, alpha: float = 2.1, seed: int = 1, name: str = "") -> Graph:
+    """Directed Chung-Lu power-law graph with exactly m distinct edges, no self-loops."""
+    lib = _load()
+    off = np.empty(n + 1, dtype=np.int64)
+    src = np.empty(m, dtype=np.int32)
+    i0 = ctypes.c_int64(0)
+    rc = lib.synth_chung_lu(n, m, float(alpha), seed & 0xFFFFFFFFFFFFFFFF, off.ctypes.data, src.ctypes.data,
+                            ctypes.byref(i0))
+    if rc != 0:
+        raise RuntimeError(f"synth_chung_lu(n={n}, m={m}) failed with code {rc}")
+    return Graph(n, m, off, src, name or f"chunglu_n{n}_m{m}_s{seed}")
+
+
+def from_edges(n: int, edges, name: str = "") -> Graph:
+    """Canonical in-CSR from a list of directed (u, v) edges; rejects self-loops and repeats."""
+    e = np.asarray(list(edges), dtype=np.int64).reshape(-1, 2)
+    if e.size and (e.min() < 0 or e.max() >= n):
+        raise ValueError("node id out of range")
+    if np.any(e[:, 0] == e[:, 1]):
+        raise ValueError("self-loop")
+    order = np.lexsort((e[:, 0], e[:, 1]))
+    e = e[order]
+    if len(e) > 1 and np.any(np.all(e[1:] == e[:-1], axis=1)):
+        raise ValueError("repeated edge")
+    off = np.zeros(n + 1, dtype=np.int64)
+    np.add.at(off, e[:, 1] + 1, 1)
+    off = np.cumsum(off).astype(np.int64)
+    return Graph(n, len(e), off, e[:, 0].astype(np.int32).copy(), name)
+
+
+def edge_list(g: Graph) -> np.ndarray:
+    """(m, 2) array of (src, dst) in CSR order."""
+    dst = np.repeat(np.arange(g.n, dtype=np.int64), np.diff(g.off))
+    return np.stack([g.src.astype(np.int64), dst], axis=1)
+
+
+def random_thresholds(m: int, seed: int, choices=None) -> np.ndarray:
+    """Per-edge uint32 thresholds drawn from `choices` (or uniformly over uint32)."""
+    rng = np.random.default_rng(seed)
+    if choices is None:
+        return rng.integers(0, 2**32, size=m, dtype=np.uint64).astype(np.uint32)
+    c = np.asarray(choices, dtype=np.uint32)
+    return c[rng.integers(0, len(c), size=m)]
+
+
+def random_small_graph(n: int, m: int, seed: int) -> Graph:
+    """Uniform random simple digraph with exactly m edges (tiny sizes, for exhaustive tests)."""
+    rng = np.random.default_rng(seed)
+    pairs = [(u, v) for u in range(n) for v in range(n) if u != v]
+    pick = rng.choice(len(pairs), size=m, replace=False)
+    return from_edges(n, [pairs[i] for i in pick], name=f"small_n{n}_m{m}_s{seed}")
+
+
+# Configurations of the synthetic workloads (graph part only).
+CONFIGS = {
+    "cfg1": dict(n=15_000, m=60_000, alpha=2.1, seed=1),
+    "cfg2": dict(n=1_000_000, m=10_000_000, alpha=2.1, seed=2),
+    "cfg5": dict(n=41_600_000, m=1_470_000_000, alpha=2.1, seed=5),
+}
+
+
+def config_graph(name: str) -> Graph:
+    c = CONFIGS[name]
+    return chung_lu(c["n"], c["m"], c["alpha"], c["seed"], name=name)
