@@ -1,0 +1,773 @@
+// Host driver of the TIM / TIM+ engine: the C ABI declared in include/tim.h.
+//
+// The phases follow the paper: KptEstimation (Algorithm 2), RefineKPT
+// (Algorithm 3) and NodeSelection (Algorithm 1), assembled as TIM
+// (Section 3.3) and TIM+ (Section 4.1).  Every RR set is produced on the GPU
+// by the samplers in sample.hip and every coverage step by coverage.hip; the
+// host only evaluates the scalar formulas (Equations (4) and (9), epsilon',
+// lambda', theta', KPT', KPT+) in binary64 with a fixed evaluation order, and
+// reads back per-launch totals.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "engine.hpp"
+#include "tim.h"
+
+using tim::SampleArgs;
+
+namespace {
+
+typedef unsigned __int128 u128;
+
+thread_local std::string g_error;
+
+tim_status fail(tim_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                        \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(TIM_EDEVICE, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+#define TIM_TRY(expr)                  \
+  do {                                 \
+    tim_status s_ = (expr);            \
+    if (s_ != TIM_OK) return s_;       \
+  } while (0)
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  template <typename T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Sets per sampling launch: bounds the deferred-set list of one launch.
+constexpr uint64_t kMaxLaunchSets = 1ull << 26;
+
+}  // namespace
+
+struct tim_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  uint64_t budget = 0;
+  uint64_t held = 0;
+  int num_cu = 0;
+  int grid_ic[3][2] = {};
+  int grid_lt[3] = {};
+  unsigned long long* ctr = nullptr;       // device counters of the current launch
+  unsigned long long* ctr_host = nullptr;  // pinned mirror
+  DevBuf deferred, pool, set_start, set_len;
+  DevBuf big_stamp, big_queue, big_epoch;
+  int big_slots = 0;
+  int64_t big_n = -1;
+  DevBuf rr_off, rr_nodes, sizes, cnt, fill, inv_off, inv_sets, covered, selected, best, scan_tmp, seed_bits;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+};
+
+struct tim_graph {
+  tim_ctx* ctx = nullptr;
+  int64_t n = 0, m = 0;
+  int64_t* off = nullptr;
+  int32_t* src = nullptr;
+  uint32_t* thr = nullptr;
+};
+
+namespace {
+
+tim_status ensure(tim_ctx* c, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes == 0) bytes = 16;
+  if (b.bytes >= bytes) return TIM_OK;
+  size_t want = std::max(bytes, b.bytes + b.bytes / 2);
+  want = (want + 255) & ~(size_t)255;
+  const uint64_t others = c->held - b.bytes;
+  if (c->budget && others + want > c->budget) {
+    want = (bytes + 255) & ~(size_t)255;
+    if (others + want > c->budget)
+      return fail(TIM_EBUDGET, "%s needs %zu bytes; %llu of the %llu-byte budget are in use", what, bytes,
+                  (unsigned long long)others, (unsigned long long)c->budget);
+  }
+  if (b.p) (void)hipFree(b.p);
+  c->held = others;
+  b.p = nullptr;
+  b.bytes = 0;
+  if (hipMalloc(&b.p, want) != hipSuccess) {
+    b.p = nullptr;
+    return fail(TIM_ENOMEM, "hipMalloc of %zu bytes for %s failed", want, what);
+  }
+  b.bytes = want;
+  c->held += want;
+  return TIM_OK;
+}
+
+void release(tim_ctx* c, DevBuf& b) {
+  if (b.p) (void)hipFree(b.p);
+  c->held -= b.bytes;
+  b = DevBuf();
+}
+
+tim_graph const* check_graph(const tim_ctx* c, const tim_graph* g) {
+  return (c && g && g->ctx == c) ? g : nullptr;
+}
+
+// Per-slot visited stamps and queues of the large-set pass, sized for n.
+tim_status ensure_big(tim_ctx* c, int64_t n) {
+  if (c->big_n == n) return TIM_OK;
+  release(c, c->big_stamp);
+  release(c, c->big_queue);
+  release(c, c->big_epoch);
+  c->big_n = -1;
+  int slots = 64;
+  if (c->budget) {
+    const uint64_t room = c->budget > c->held ? (c->budget - c->held) / 4 : 0;
+    const uint64_t per = (uint64_t)n * 8;
+    slots = (int)std::min<uint64_t>(64, room / per);
+    if (slots < 1) return fail(TIM_EBUDGET, "budget too small for the large-set pass (needs %llu bytes)",
+                               (unsigned long long)per * 4);
+  }
+  TIM_TRY(ensure(c, c->big_stamp, (size_t)slots * (size_t)n * 4, "large-set stamps"));
+  TIM_TRY(ensure(c, c->big_queue, (size_t)slots * (size_t)n * 4, "large-set queues"));
+  TIM_TRY(ensure(c, c->big_epoch, (size_t)slots * 4, "large-set epochs"));
+  HIP_TRY(hipMemsetAsync(c->big_stamp.p, 0, c->big_stamp.bytes, c->stream));
+  HIP_TRY(hipMemsetAsync(c->big_epoch.p, 0, c->big_epoch.bytes, c->stream));
+  c->big_slots = slots;
+  c->big_n = n;
+  return TIM_OK;
+}
+
+struct Totals {
+  uint64_t count = 0, deferred = 0, width = 0, nodes = 0, covered = 0, pool_used = 0;
+  u128 kappa = 0;
+};
+
+// One sampling launch pair (wave/lane-level pass, then the large-set pass)
+// over sets [first, first+count) with count <= kMaxLaunchSets.
+tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, uint64_t seed, uint32_t phase,
+                         uint64_t first, uint64_t count, int k, uint64_t* widths, uint32_t* sizes,
+                         uint64_t set_offset, Totals* t) {
+  TIM_TRY(ensure_big(c, g->n));
+  TIM_TRY(ensure(c, c->deferred, count * 8, "deferred-set list"));
+  SampleArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g.off = g->off;
+  a.g.src = g->src;
+  a.g.thr = g->thr;
+  a.g.n = g->n;
+  a.g.m = g->m;
+  a.seed = seed;
+  a.phase = phase;
+  a.first = first;
+  a.count = count;
+  a.k = k;
+  a.ctr = c->ctr;
+  a.widths = widths;
+  a.sizes = sizes;
+  if (mode == tim::kModeEmit) {
+    a.pool = c->pool.as<int32_t>();
+    a.pool_cap = c->pool.bytes / 4;
+    a.set_start = c->set_start.as<uint64_t>() + set_offset;
+    a.set_len = c->set_len.as<uint32_t>() + set_offset;
+  }
+  a.seed_bits = c->seed_bits.as<uint32_t>();
+  a.deferred = c->deferred.as<uint64_t>();
+  a.deferred_cap = count;
+  a.big_stamp = c->big_stamp.as<uint32_t>();
+  a.big_queue = c->big_queue.as<int32_t>();
+  a.big_epoch = c->big_epoch.as<uint32_t>();
+  a.big_slots = c->big_slots;
+  const bool wc = g->thr == nullptr;
+  int per_cu = model == TIM_MODEL_IC ? c->grid_ic[mode][wc ? 1 : 0] : c->grid_lt[mode];
+  const uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 : 128;
+  uint64_t grid = (uint64_t)per_cu * (uint64_t)c->num_cu;
+  grid = std::min<uint64_t>(grid, (count + sets_per_block - 1) / sets_per_block);
+  if (grid < 1) grid = 1;
+  tim::launch_clear_counters(c->ctr, c->stream);
+  tim::launch_sample(model, mode, a, (int)grid, c->stream);
+  tim::launch_sample_large(model, mode, a, c->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->ctr_host, c->ctr, tim::kCtrCount * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const unsigned long long* h = c->ctr_host;
+  if (h[tim::kCtrDeferred] > count) return fail(TIM_EDEVICE, "deferred-set list overflow");
+  t->count += count;
+  t->deferred += h[tim::kCtrDeferred];
+  t->kappa += ((u128)h[tim::kCtrKappaHi] << 64) | (u128)h[tim::kCtrKappaLo];
+  t->width += h[tim::kCtrWidth];
+  t->nodes += h[tim::kCtrNodes];
+  t->covered += h[tim::kCtrCovered];
+  t->pool_used = h[tim::kCtrPoolCursor];
+  return TIM_OK;
+}
+
+// Width or coverage mode over any number of sets, in launches of bounded size.
+tim_status sample_counts(tim_ctx* c, const tim_graph* g, int model, int mode, uint64_t seed, uint32_t phase,
+                         uint64_t first, uint64_t count, int k, uint64_t* widths, uint32_t* sizes, Totals* t) {
+  for (uint64_t done = 0; done < count;) {
+    const uint64_t part = std::min(count - done, kMaxLaunchSets);
+    TIM_TRY(sample_launch(c, g, model, mode, seed, phase, first + done, part, k, widths ? widths + done : nullptr,
+                          sizes ? sizes + done : nullptr, 0, t));
+    done += part;
+  }
+  return TIM_OK;
+}
+
+// Emit mode: sets [first, first+count) into c->rr_off / c->rr_nodes (CSR in
+// set order).  expect_nodes sizes the node pool; a short pool is regrown to
+// the exact need and the sets regenerated.
+tim_status sample_store(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
+                        uint64_t count, uint64_t expect_nodes, uint64_t* widths, Totals* t_out) {
+  TIM_TRY(ensure(c, c->set_start, count * 8, "set offsets"));
+  TIM_TRY(ensure(c, c->set_len, count * 4, "set sizes"));
+  TIM_TRY(ensure(c, c->pool, std::max<uint64_t>(expect_nodes, 1024) * 4, "RR node pool"));
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    Totals t;
+    for (uint64_t done = 0; done < count;) {
+      const uint64_t part = std::min(count - done, kMaxLaunchSets);
+      TIM_TRY(sample_launch(c, g, model, tim::kModeEmit, seed, phase, first + done, part, 0,
+                            widths ? widths + done : nullptr, nullptr, done, &t));
+      done += part;
+    }
+    if (t.pool_used * 4 <= c->pool.bytes) {
+      TIM_TRY(ensure(c, c->rr_off, (count + 1) * 8, "RR set offsets"));
+      TIM_TRY(ensure(c, c->rr_nodes, t.nodes * 4, "RR nodes"));
+      TIM_TRY(ensure(c, c->scan_tmp, tim::scan_temp_bytes(std::max<uint64_t>(count, (uint64_t)g->n + 1)), "scan"));
+      tim::launch_scan_u32_to_i64(c->set_len.as<uint32_t>(), c->rr_off.as<int64_t>(), count, c->scan_tmp.p,
+                                  c->stream);
+      tim::launch_compact(c->pool.as<int32_t>(), c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
+                          c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), count, c->stream);
+      HIP_TRY(hipGetLastError());
+      *t_out = t;
+      return TIM_OK;
+    }
+    TIM_TRY(ensure(c, c->pool, t.pool_used * 4, "RR node pool"));
+  }
+  return fail(TIM_EDEVICE, "node pool still short after regrowing");
+}
+
+// Greedy maximum coverage over a CSR collection in device memory.
+tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off, const int32_t* nodes,
+                  uint64_t total, int k, int32_t* seeds, uint64_t* gains) {
+  if (nsets >= 0xFFFFFFFFull) return fail(TIM_EINVAL, "more than 2^32-1 sets in one collection");
+  TIM_TRY(ensure(c, c->cnt, (size_t)n * 4, "coverage counts"));
+  TIM_TRY(ensure(c, c->fill, (size_t)n * 4, "index cursors"));
+  TIM_TRY(ensure(c, c->inv_off, (size_t)(n + 1) * 8, "index offsets"));
+  TIM_TRY(ensure(c, c->inv_sets, total * 4, "index entries"));
+  TIM_TRY(ensure(c, c->covered, nsets, "covered marks"));
+  TIM_TRY(ensure(c, c->selected, (size_t)n, "selected marks"));
+  TIM_TRY(ensure(c, c->best, (size_t)k * 8, "argmax keys"));
+  TIM_TRY(ensure(c, c->scan_tmp, tim::scan_temp_bytes((uint64_t)n + 1), "scan"));
+  tim::GreedyArgs a;
+  a.n = n;
+  a.nsets = nsets;
+  a.set_off = set_off;
+  a.nodes = nodes;
+  a.cnt = c->cnt.as<uint32_t>();
+  a.fill = c->fill.as<uint32_t>();
+  a.inv_off = c->inv_off.as<int64_t>();
+  a.inv_sets = c->inv_sets.as<uint32_t>();
+  a.covered = c->covered.as<uint8_t>();
+  a.selected = c->selected.as<uint8_t>();
+  a.best = c->best.as<unsigned long long>();
+  a.scan_temp = c->scan_tmp.p;
+  tim::launch_index(a, c->stream);
+  tim::launch_greedy(a, k, c->stream);
+  HIP_TRY(hipGetLastError());
+  std::vector<unsigned long long> keys((size_t)k);
+  HIP_TRY(hipMemcpyAsync(keys.data(), a.best, (size_t)k * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int j = 0; j < k; ++j) {
+    seeds[j] = (int32_t)(0xFFFFFFFFull - (keys[j] & 0xFFFFFFFFull));
+    if (gains) gains[j] = keys[j] >> 32;
+  }
+  return TIM_OK;
+}
+
+// ---- scalar formulas (binary64, fixed evaluation order) ----
+double ln_binom(int64_t n, int k) {
+  double s = 0.0;
+  for (int i = 0; i < k; ++i) s = s + (std::log((double)(n - i)) - std::log((double)(i + 1)));
+  return s;
+}
+
+double lambda_eq4(int64_t n, int k, double eps, double ell) {
+  const double nd = (double)n;
+  return ((8.0 + 2.0 * eps) * nd * ((ell * std::log(nd) + ln_binom(n, k)) + std::log(2.0))) / (eps * eps);
+}
+
+int rounds_of(int64_t n) {
+  int bits = 0;
+  for (uint64_t x = (uint64_t)n; x; x >>= 1) ++bits;
+  return bits - 2;
+}
+
+uint64_t round_size(int64_t n, double ell, int i) {
+  const double nd = (double)n;
+  const double a = 6.0 * ell * std::log(nd) + 6.0 * std::log(std::log2(nd));
+  return (uint64_t)std::ceil(std::ldexp(a, i));
+}
+
+tim_status check_phase_args(const tim_ctx* c, const tim_graph* g, int model, int k) {
+  if (!c) return fail(TIM_EINVAL, "null context");
+  if (!check_graph(c, g)) return fail(TIM_EINVAL, "graph does not belong to this context");
+  if (model != TIM_MODEL_IC && model != TIM_MODEL_LT) return fail(TIM_EINVAL, "unknown model %d", model);
+  if (k < 1 || (int64_t)k > g->n) return fail(TIM_EINVAL, "k=%d outside [1, n=%lld]", k, (long long)g->n);
+  return TIM_OK;
+}
+
+tim_status upload_seed_bits(tim_ctx* c, int64_t n, const int32_t* seeds, int nseeds) {
+  const size_t words = (size_t)(n + 31) / 32;
+  std::vector<uint32_t> bits(words, 0u);
+  for (int j = 0; j < nseeds; ++j) {
+    if (seeds[j] < 0 || seeds[j] >= n) return fail(TIM_EINVAL, "seed %d outside [0, n)", seeds[j]);
+    bits[(uint32_t)seeds[j] >> 5] |= 1u << ((uint32_t)seeds[j] & 31u);
+  }
+  TIM_TRY(ensure(c, c->seed_bits, words * 4, "seed bitmap"));
+  HIP_TRY(hipMemcpyAsync(c->seed_bits.p, bits.data(), words * 4, hipMemcpyHostToDevice, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TIM_OK;
+}
+
+float elapsed_ms(tim_ctx* c) {
+  float ms = 0.f;
+  (void)hipEventSynchronize(c->ev[1]);
+  (void)hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+  return ms;
+}
+
+tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double ell,
+                             tim_kpt_result* out, uint64_t* sets, uint64_t* width) {
+  memset(out, 0, sizeof(*out));
+  const int imax = rounds_of(g->n);
+  out->i_max = imax;
+  out->i_last = imax;
+  out->c_last = imax >= 1 ? round_size(g->n, ell, imax) : 0;
+  out->kpt_star = 1.0;
+  for (int i = 1; i <= imax; ++i) {
+    const uint64_t ci = round_size(g->n, ell, i);
+    Totals t;
+    TIM_TRY(sample_counts(c, g, model, tim::kModeWidth, seed, (uint32_t)i, 0, ci, k, nullptr, nullptr, &t));
+    out->round_c[i] = ci;
+    out->round_sum_lo[i] = (uint64_t)t.kappa;
+    out->round_sum_hi[i] = (uint64_t)(t.kappa >> 64);
+    out->round_width[i] = t.width;
+    out->round_nodes[i] = t.nodes;
+    if (sets) *sets += ci;
+    if (width) *width += t.width;
+    // sum/c_i > 2^-i with sum = S * 2^-53 exactly: S * 2^i > c_i * 2^53
+    if ((t.kappa << i) > ((u128)ci << 53)) {
+      const double sum = std::ldexp((double)t.kappa, -53);
+      out->kpt_star = (sum * (double)g->n) / (2.0 * (double)ci);
+      out->i_last = i;
+      out->c_last = ci;
+      break;
+    }
+  }
+  return TIM_OK;
+}
+
+tim_status refine_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double eps, double ell,
+                       double kpt_star, int i_last, uint64_t c_last, uint64_t expect_nodes, int32_t* s_prime,
+                       tim_refine_result* out, uint64_t* sets, uint64_t* width) {
+  memset(out, 0, sizeof(*out));
+  // lines 1-6: greedy on the sets of the last round of Algorithm 2
+  Totals t;
+  if (c_last > 0) {
+    TIM_TRY(sample_store(c, g, model, seed, (uint32_t)i_last, 0, c_last, expect_nodes, nullptr, &t));
+    TIM_TRY(greedy(c, g->n, c_last, c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), t.nodes, k, s_prime,
+                   nullptr));
+  } else {
+    for (int j = 0; j < k; ++j) s_prime[j] = j;
+  }
+  if (sets) *sets += c_last;
+  if (width) *width += t.width;
+  // lines 7-10
+  const double nd = (double)g->n;
+  const double eps_p = 5.0 * std::cbrt(ell * eps * eps / ((double)k + ell));
+  const double lambda_p = ((2.0 + eps_p) * ell * nd * std::log(nd)) / (eps_p * eps_p);
+  const uint64_t theta_p = (uint64_t)std::ceil(lambda_p / kpt_star);
+  TIM_TRY(upload_seed_bits(c, g->n, s_prime, k));
+  Totals tc;
+  TIM_TRY(sample_counts(c, g, model, tim::kModeCover, seed, TIM_PHASE_REFINE, 0, theta_p, 0, nullptr, nullptr, &tc));
+  if (sets) *sets += theta_p;
+  // lines 11-13
+  const double f = (double)tc.covered / (double)theta_p;
+  const double kpt_p = f * nd / (1.0 + eps_p);
+  out->eps_prime = eps_p;
+  out->lambda_prime = lambda_p;
+  out->theta_prime = theta_p;
+  out->covered_prime = tc.covered;
+  out->kpt_prime = kpt_p;
+  out->kpt_plus = kpt_p > kpt_star ? kpt_p : kpt_star;
+  return TIM_OK;
+}
+
+struct SelectTimes {
+  float sample = 0.f, index_greedy = 0.f;
+};
+
+tim_status node_select_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, uint64_t theta,
+                            uint64_t expect_nodes, int32_t* seeds, uint64_t* gains, tim_select_result* out,
+                            SelectTimes* times) {
+  Totals t;
+  if (times) HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+  TIM_TRY(sample_store(c, g, model, seed, TIM_PHASE_SELECT, 0, theta, expect_nodes, nullptr, &t));
+  if (times) {
+    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+    times->sample = elapsed_ms(c);
+    HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+  }
+  std::vector<uint64_t> g_local((size_t)k);
+  uint64_t* gp = gains ? gains : g_local.data();
+  TIM_TRY(greedy(c, g->n, theta, c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), t.nodes, k, seeds, gp));
+  if (times) {
+    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+    times->index_greedy = elapsed_ms(c);
+  }
+  if (out) {
+    out->theta = theta;
+    out->nodes = t.nodes;
+    out->width = t.width;
+    uint64_t cov = 0;
+    for (int j = 0; j < k; ++j) cov += gp[j];
+    out->covered = cov;
+    out->store_bytes = (theta + 1) * 8 + t.nodes * 4 + t.nodes * 4 + ((uint64_t)g->n + 1) * 8;
+  }
+  return TIM_OK;
+}
+
+}  // namespace
+
+// =========================================================================
+// C ABI
+// =========================================================================
+extern "C" {
+
+const char* tim_last_error(void) { return g_error.c_str(); }
+
+tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, tim_ctx** out) {
+  if (!out) return fail(TIM_EINVAL, "out is null");
+  *out = nullptr;
+  int ndev = 0;
+  HIP_TRY(hipGetDeviceCount(&ndev));
+  if (device < 0 || device >= ndev) return fail(TIM_EDEVICE, "device %d not present (%d devices)", device, ndev);
+  HIP_TRY(hipSetDevice(device));
+  tim_ctx* c = new tim_ctx();
+  c->device = device;
+  c->budget = hbm_budget_bytes;
+  hipDeviceProp_t prop;
+  if (hipGetDeviceProperties(&prop, device) != hipSuccess) {
+    delete c;
+    return fail(TIM_EDEVICE, "hipGetDeviceProperties failed");
+  }
+  c->num_cu = prop.multiProcessorCount;
+  if (stream) {
+    c->stream = static_cast<hipStream_t>(stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return fail(TIM_EDEVICE, "hipStreamCreate failed");
+    }
+    c->own_stream = true;
+  }
+  for (int mode = 0; mode < 3; ++mode) {
+    c->grid_ic[mode][0] = tim::ic_wave_blocks_per_cu(mode, false);
+    c->grid_ic[mode][1] = tim::ic_wave_blocks_per_cu(mode, true);
+    c->grid_lt[mode] = tim::lt_lane_blocks_per_cu(mode);
+  }
+  if (hipMalloc(&c->ctr, tim::kCtrCount * sizeof(unsigned long long)) != hipSuccess ||
+      hipHostMalloc(&c->ctr_host, tim::kCtrCount * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
+      hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+    tim_ctx_destroy(c);
+    return fail(TIM_EDEVICE, "context allocation failed");
+  }
+  *out = c;
+  return TIM_OK;
+}
+
+void tim_ctx_destroy(tim_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  DevBuf* bufs[] = {&c->deferred, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
+                    &c->rr_off, &c->rr_nodes, &c->sizes, &c->cnt, &c->fill, &c->inv_off, &c->inv_sets, &c->covered,
+                    &c->selected, &c->best, &c->scan_tmp, &c->seed_bits};
+  for (DevBuf* b : bufs) release(c, *b);
+  if (c->ctr) (void)hipFree(c->ctr);
+  if (c->ctr_host) (void)hipHostFree(c->ctr_host);
+  for (hipEvent_t e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+uint64_t tim_ctx_device_bytes(const tim_ctx* c) { return c ? c->held : 0; }
+
+tim_status tim_graph_upload(tim_ctx* c, int64_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
+                            const uint32_t* ic_thr, tim_graph** out) {
+  if (!c || !out || !in_off || !in_src) return fail(TIM_EINVAL, "null argument");
+  *out = nullptr;
+  if (n < 2 || n > 0x7FFFFFFFLL) return fail(TIM_EINVAL, "n=%lld outside [2, 2^31)", (long long)n);
+  if (m < 1 || m >= (1LL << 33)) return fail(TIM_EINVAL, "m=%lld outside [1, 2^33)", (long long)m);
+  if (in_off[0] != 0 || in_off[n] != m) return fail(TIM_EINVAL, "in_off[0] must be 0 and in_off[n] must be m");
+  for (int64_t v = 0; v < n; ++v) {
+    if (in_off[v + 1] < in_off[v]) return fail(TIM_EINVAL, "in_off decreases at node %lld", (long long)v);
+    for (int64_t e = in_off[v]; e < in_off[v + 1]; ++e) {
+      const int32_t u = in_src[e];
+      if (u < 0 || u >= n) return fail(TIM_EINVAL, "source of edge %lld out of range", (long long)e);
+      if (u == v) return fail(TIM_EINVAL, "self-loop at node %lld", (long long)v);
+      if (e > in_off[v] && in_src[e - 1] >= u)
+        return fail(TIM_EINVAL, "in-edges of node %lld not strictly increasing by source", (long long)v);
+    }
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  tim_graph* g = new tim_graph();
+  g->ctx = c;
+  g->n = n;
+  g->m = m;
+  const size_t mpad = (size_t)((m + 3) / 4 * 4 + 4);
+  bool ok = hipMalloc(&g->off, (size_t)(n + 1) * 8) == hipSuccess && hipMalloc(&g->src, mpad * 4) == hipSuccess &&
+            (!ic_thr || hipMalloc(&g->thr, mpad * 4) == hipSuccess);
+  if (ok) {
+    ok = hipMemcpyAsync(g->off, in_off, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         hipMemsetAsync(g->src, 0, mpad * 4, c->stream) == hipSuccess &&
+         hipMemcpyAsync(g->src, in_src, (size_t)m * 4, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+    if (ok && ic_thr)
+      ok = hipMemsetAsync(g->thr, 0, mpad * 4, c->stream) == hipSuccess &&
+           hipMemcpyAsync(g->thr, ic_thr, (size_t)m * 4, hipMemcpyHostToDevice, c->stream) == hipSuccess;
+    ok = ok && hipStreamSynchronize(c->stream) == hipSuccess;
+  }
+  if (!ok) {
+    tim_graph_free(g);
+    return fail(TIM_ENOMEM, "graph upload failed");
+  }
+  *out = g;
+  return TIM_OK;
+}
+
+void tim_graph_free(tim_graph* g) {
+  if (!g) return;
+  if (g->off) (void)hipFree(g->off);
+  if (g->src) (void)hipFree(g->src);
+  if (g->thr) (void)hipFree(g->thr);
+  delete g;
+}
+
+tim_status tim_sample_rr(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
+                         uint64_t count, int64_t* d_set_off, int32_t* d_nodes, uint64_t nodes_capacity,
+                         uint64_t* d_widths, uint64_t* total_nodes, tim_batch_stats* stats) {
+  TIM_TRY(check_phase_args(c, g, model, 1));
+  if (!d_set_off || phase > 255) return fail(TIM_EINVAL, "bad output offsets pointer or phase");
+  HIP_TRY(hipSetDevice(c->device));
+  Totals t;
+  TIM_TRY(ensure(c, c->set_start, count * 8, "set offsets"));
+  TIM_TRY(ensure(c, c->set_len, count * 4, "set sizes"));
+  TIM_TRY(ensure(c, c->pool, std::max<uint64_t>(count * 16, 1024) * 4, "RR node pool"));
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    t = Totals();
+    for (uint64_t done = 0; done < count;) {
+      const uint64_t part = std::min(count - done, kMaxLaunchSets);
+      TIM_TRY(sample_launch(c, g, model, tim::kModeEmit, seed, phase, first + done, part, 0,
+                            d_widths ? d_widths + done : nullptr, nullptr, done, &t));
+      done += part;
+    }
+    if (t.pool_used * 4 <= c->pool.bytes) break;
+    TIM_TRY(ensure(c, c->pool, t.pool_used * 4, "RR node pool"));
+  }
+  if (total_nodes) *total_nodes = t.nodes;
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->count = count;
+    stats->width_sum = t.width;
+    stats->node_sum = t.nodes;
+    stats->deferred = t.deferred;
+  }
+  TIM_TRY(ensure(c, c->scan_tmp, tim::scan_temp_bytes(count), "scan"));
+  tim::launch_scan_u32_to_i64(c->set_len.as<uint32_t>(), d_set_off, count, c->scan_tmp.p, c->stream);
+  if (t.nodes > nodes_capacity) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    return fail(TIM_ECAPACITY, "%llu nodes do not fit a buffer of %llu", (unsigned long long)t.nodes,
+                (unsigned long long)nodes_capacity);
+  }
+  if (t.nodes && !d_nodes) return fail(TIM_EINVAL, "d_nodes is null");
+  tim::launch_compact(c->pool.as<int32_t>(), c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(), d_set_off,
+                      d_nodes, count, c->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  return TIM_OK;
+}
+
+tim_status tim_sample_widths(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
+                             uint64_t count, int k, uint64_t* d_widths, uint32_t* d_sizes, tim_batch_stats* stats) {
+  TIM_TRY(check_phase_args(c, g, model, k));
+  if (phase > 255) return fail(TIM_EINVAL, "phase %u > 255", phase);
+  HIP_TRY(hipSetDevice(c->device));
+  Totals t;
+  TIM_TRY(sample_counts(c, g, model, tim::kModeWidth, seed, phase, first, count, k, d_widths, d_sizes, &t));
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->count = count;
+    stats->kappa_sum_lo = (uint64_t)t.kappa;
+    stats->kappa_sum_hi = (uint64_t)(t.kappa >> 64);
+    stats->width_sum = t.width;
+    stats->node_sum = t.nodes;
+    stats->deferred = t.deferred;
+  }
+  return TIM_OK;
+}
+
+tim_status tim_sample_cover(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
+                            uint64_t count, const int32_t* seeds, int nseeds, tim_batch_stats* stats) {
+  TIM_TRY(check_phase_args(c, g, model, 1));
+  if (phase > 255 || nseeds < 0 || (nseeds > 0 && !seeds)) return fail(TIM_EINVAL, "bad phase or seed list");
+  HIP_TRY(hipSetDevice(c->device));
+  TIM_TRY(upload_seed_bits(c, g->n, seeds, nseeds));
+  Totals t;
+  TIM_TRY(sample_counts(c, g, model, tim::kModeCover, seed, phase, first, count, 0, nullptr, nullptr, &t));
+  if (stats) {
+    memset(stats, 0, sizeof(*stats));
+    stats->count = count;
+    stats->covered = t.covered;
+    stats->deferred = t.deferred;
+  }
+  return TIM_OK;
+}
+
+tim_status tim_max_coverage(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* d_set_off, const int32_t* d_nodes,
+                            int k, int32_t* seeds, uint64_t* gains) {
+  if (!c || !seeds || (nsets && (!d_set_off || !d_nodes))) return fail(TIM_EINVAL, "null argument");
+  if (n < 1 || n > 0x7FFFFFFFLL || k < 1 || k > n) return fail(TIM_EINVAL, "bad n or k");
+  HIP_TRY(hipSetDevice(c->device));
+  int64_t total = 0;
+  if (nsets) {
+    HIP_TRY(hipMemcpyAsync(&total, d_set_off + nsets, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  if (total < 0) return fail(TIM_EINVAL, "negative collection size");
+  if (total) {
+    TIM_TRY(ensure(c, c->fill, 16, "id check flag"));
+    tim::launch_check_ids(d_nodes, (uint64_t)total, n, c->fill.as<unsigned int>(), c->stream);
+    unsigned int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, c->fill.p, 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (bad) return fail(TIM_EINVAL, "a node id of the collection lies outside [0, n)");
+  }
+  int64_t zero_off = 0;
+  const int64_t* off = d_set_off;
+  if (!nsets) {
+    TIM_TRY(ensure(c, c->rr_off, 8, "empty offsets"));
+    HIP_TRY(hipMemcpyAsync(c->rr_off.p, &zero_off, 8, hipMemcpyHostToDevice, c->stream));
+    off = c->rr_off.as<int64_t>();
+  }
+  return greedy(c, n, nsets, off, d_nodes, (uint64_t)total, k, seeds, gains);
+}
+
+tim_status tim_kpt_estimate(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double ell,
+                            tim_kpt_result* out) {
+  TIM_TRY(check_phase_args(c, g, model, k));
+  if (!out || !(ell >= 0.5)) return fail(TIM_EINVAL, "ell must be >= 0.5");
+  HIP_TRY(hipSetDevice(c->device));
+  return kpt_estimate_impl(c, g, model, seed, k, ell, out, nullptr, nullptr);
+}
+
+tim_status tim_refine_kpt(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double eps, double ell,
+                          double kpt_star, int i_last, uint64_t c_last, int32_t* s_prime, tim_refine_result* out) {
+  TIM_TRY(check_phase_args(c, g, model, k));
+  if (!s_prime || !out) return fail(TIM_EINVAL, "null output");
+  if (!(eps > 0.0 && eps <= 1.0)) return fail(TIM_EINVAL, "eps must be in (0, 1]");
+  if (!(ell >= 0.5) || !(kpt_star >= 1.0) || i_last < 0 || i_last > 62)
+    return fail(TIM_EINVAL, "bad ell, KPT* or round");
+  HIP_TRY(hipSetDevice(c->device));
+  return refine_impl(c, g, model, seed, k, eps, ell, kpt_star, i_last, c_last, c_last * 16, s_prime, out, nullptr,
+                     nullptr);
+}
+
+tim_status tim_node_select(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, uint64_t theta,
+                           int32_t* seeds, uint64_t* gains, tim_select_result* out) {
+  TIM_TRY(check_phase_args(c, g, model, k));
+  if (!seeds) return fail(TIM_EINVAL, "seeds is null");
+  HIP_TRY(hipSetDevice(c->device));
+  return node_select_impl(c, g, model, seed, k, theta, theta * 16, seeds, gains, out, nullptr);
+}
+
+tim_status tim_run(tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell, uint64_t seed,
+                   uint32_t flags, int32_t* seeds, uint64_t* gains, tim_report* rep) {
+  TIM_TRY(check_phase_args(c, g, model, k));
+  if (!seeds) return fail(TIM_EINVAL, "seeds is null");
+  if (!(eps > 0.0 && eps <= 1.0)) return fail(TIM_EINVAL, "eps must be in (0, 1]");
+  if (!(ell >= 0.5)) return fail(TIM_EINVAL, "ell must be >= 0.5");
+  HIP_TRY(hipSetDevice(c->device));
+  tim_report local;
+  tim_report* r = rep ? rep : &local;
+  memset(r, 0, sizeof(*r));
+  const bool plain = (flags & TIM_FLAG_PLAIN) != 0;
+  double ell_used = ell;
+  if (flags & TIM_FLAG_ELL_ADJUST) ell_used = ell * (1.0 + std::log(plain ? 2.0 : 3.0) / std::log((double)g->n));
+  r->ell_used = ell_used;
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  auto lap = [&](double* slot) {
+    (void)hipEventRecord(t1, c->stream);
+    (void)hipEventSynchronize(t1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    *slot = ms;
+    (void)hipEventRecord(t0, c->stream);
+  };
+  (void)hipEventRecord(t0, c->stream);
+  tim_status st = kpt_estimate_impl(c, g, model, seed, k, ell_used, &r->kpt, &r->sets_total, &r->width_total);
+  if (st == TIM_OK) lap(&r->ms_kpt);
+  // mean set size of the stopping round sizes the node pools
+  const int il = r->kpt.i_last;
+  const double mean_nodes =
+      (il >= 1 && r->kpt.round_c[il]) ? (double)r->kpt.round_nodes[il] / (double)r->kpt.round_c[il] : 16.0;
+  double lb = r->kpt.kpt_star;
+  std::vector<int32_t> sp((size_t)k);
+  if (st == TIM_OK && !plain) {
+    st = refine_impl(c, g, model, seed, k, eps, ell_used, r->kpt.kpt_star, r->kpt.i_last, r->kpt.c_last,
+                     (uint64_t)(mean_nodes * 1.25 * (double)r->kpt.c_last) + 4096, sp.data(), &r->refine,
+                     &r->sets_total, &r->width_total);
+    if (st == TIM_OK) {
+      lap(&r->ms_refine);
+      lb = r->refine.kpt_plus;
+      for (int j = 0; j < k && j < 128; ++j) r->s_prime[j] = sp[(size_t)j];
+    }
+  }
+  if (st == TIM_OK) {
+    r->lambda = lambda_eq4(g->n, k, eps, ell_used);
+    const uint64_t theta = (uint64_t)std::ceil(r->lambda / lb);
+    SelectTimes times;
+    st = node_select_impl(c, g, model, seed, k, theta, (uint64_t)(mean_nodes * 1.25 * (double)theta) + 4096, seeds,
+                          gains, &r->select, &times);
+    if (st == TIM_OK) {
+      r->ms_select_sample = times.sample;
+      r->ms_select_index = 0.0;
+      r->ms_select_greedy = times.index_greedy;
+      r->sets_total += theta;
+      r->width_total += r->select.width;
+      r->ms_total = r->ms_kpt + r->ms_refine + r->ms_select_sample + r->ms_select_greedy;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return st;
+}
+
+}  // extern "C"
