@@ -1,0 +1,165 @@
+#!/usr/bin/env python3
+"""Benchmark of the TIM+ hot path on one MI355X.
+
+Workload: a directed Chung-Lu power-law graph with n = 1,000,000 nodes and
+m = 10,000,000 edges (alpha = 2.1, seed 2), independent cascade with
+p(u,v) = 1/indeg(v), TIM+ with eps = 0.2, ell = 1.  One step runs TIM+ for
+k = 1, 10 and 50 (KptEstimation, RefineKPT, NodeSelection: every RR set is
+generated on the GPU).  The graph is resident in device memory before timing.
+
+Prints one JSON line: RR sets per second over the timed steps (value), edges
+examined per second, TIM+ seconds per k, the roofline of the dominant sampler
+kernel (algorithmic bytes over its event-timed duration), and the CPU oracle
+timed on the host on one TIM+ run of the same graph (k = 50).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+KS = (1, 10, 50)
+EPS, ELL, SEED = 0.2, 1.0, 2
+HBM_PEAK_GBS = 8000.0
+MODES = ("widths", "store", "cover")
+
+
+def kernel_name(model, mode):
+    """Tier-0 sampler kernel of (model, mode) as rocprofv3 lists it (template arguments: mode, WC, S, Q, log2 H)."""
+    if model == 1:
+        return f"lt_lane_kernel<{mode}> ({MODES[mode]})"
+    lanes = int(os.environ.get("TIM_IC_SEG_LANES", "8"))
+    lanes = lanes if lanes in (8, 16, 32, 64) else 8
+    q = {8: 64, 16: 128, 32: 256, 64: 512}[lanes]
+    hlog = {8: 7, 16: 8, 32: 9, 64: 10}[lanes]
+    return f"ic_seg_kernel<{mode}, true, {lanes}, {q}, {hlog}> ({MODES[mode]})"
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1404_0900_amd as tim
+    import synth
+
+    log("generating the 1M-node / 10M-edge Chung-Lu graph")
+    g = synth.config_graph("cfg2")
+    eng = tim.Engine(0)
+    dg = eng.upload(g)
+    log(f"graph resident: n={g.n} m={g.m}")
+
+    def step():
+        out = []
+        for k in KS:
+            t0 = time.perf_counter()
+            seeds, gains, rep = eng.run(dg, tim.IC, k, EPS, ELL, SEED)
+            out.append((k, time.perf_counter() - t0, rep))
+        return out
+
+    for i in range(args.warmup):
+        step()
+        log(f"warmup {i + 1}/{args.warmup} done")
+    torch.cuda.synchronize()
+    eng.profile(True)
+    sets = width = 0
+    per_k = {k: 0.0 for k in KS}
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        for k, dt, rep in step():
+            sets += rep.sets_total
+            width += rep.width_total
+            per_k[k] += dt
+        log(f"step {i + 1}/{args.steps} done")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    prof = eng.read_profile()
+    eng.profile(False)
+
+    # dominant sampler kernel: the one with the most GPU time in the timed steps
+    best = None
+    for model in (0, 1):
+        for mode in (0, 1, 2):
+            kp = prof.sampler[model][mode]
+            if kp.launches and (best is None or kp.kernel_ms > best[2].kernel_ms):
+                best = (model, mode, kp)
+    model, mode, kp = best
+    achieved = kp.bytes / (kp.kernel_ms * 1e-3) / 1e9
+    sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
+    roofline = {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "kernel": kernel_name(model, mode), "launches": int(kp.launches),
+        "avg_launch_us": round(kp.kernel_ms * 1e3 / kp.launches, 3),
+        "bytes_per_launch": int(kp.bytes // kp.launches),
+        "edges_per_s": round(kp.edges / (kp.kernel_ms * 1e-3), 1),
+    }
+
+    line = {
+        "metric": "RR sets/s (IC, 1 GPU, TIM+ on 1M-node Chung-Lu, k in {1,10,50})",
+        "value": round(sets / elapsed, 1),
+        "unit": "RR sets/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(elapsed * 1e3 / args.steps, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 integer, f64 kappa",
+        "data": "synthetic (seeded directed Chung-Lu, alpha=2.1)",
+        "config": {"workload": "chunglu_n1e6_m1e7_ic_wc_timplus_k1_10_50", "n": g.n, "m": g.m, "alpha": 2.1,
+                   "graph_seed": 2, "model": "IC p=1/indeg", "k": list(KS), "eps": EPS, "ell": ELL, "seed": SEED},
+        "edges_per_s": round(width / elapsed, 1),
+        "tim_plus_s": {str(k): round(per_k[k] / args.steps, 6) for k in KS},
+        "sets_per_step": sets // args.steps,
+        "sampler_gpu_ms_per_step": round(sampler_ms / args.steps, 3),
+        "index_greedy_gpu_ms_per_step": round((prof.index_ms + prof.greedy_ms) / args.steps, 3),
+        "roofline": roofline,
+    }
+
+    # the same TIM+ runs under LT (one uniform in-edge per node), outside the timed steps
+    lt_sets, t0 = 0, time.perf_counter()
+    lt_per_k = {}
+    for k in KS:
+        t1 = time.perf_counter()
+        _, _, rep = eng.run(dg, tim.LT, k, EPS, ELL, SEED)
+        lt_per_k[str(k)] = round(time.perf_counter() - t1, 6)
+        lt_sets += rep.sets_total
+    line["lt"] = {"sets_per_s": round(lt_sets / (time.perf_counter() - t0), 1), "tim_plus_s": lt_per_k}
+
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the CPU oracle: one TIM+ run, IC, k=50")
+        t0 = time.perf_counter()
+        r = oracle.tim_run(g, 0, 50, EPS, ELL, SEED)
+        dt = time.perf_counter() - t0
+        osets = sum(r["round_c"].values()) + r["c_last"] + r["theta_prime"] + r["theta"]
+        line["cpu_baseline"] = {
+            "value": round(osets / dt, 1), "unit": "RR sets/s", "cores": 1, "kind": "oracle",
+            "sample": f"one oracle TIM+ run (IC, k=50) on the same graph: {osets} RR sets in {dt:.2f} s",
+        }
+    eng.close()
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

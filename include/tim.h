@@ -150,6 +150,36 @@ const char *tim_last_error(void);
 /* Bytes of device memory currently held by the context (graphs excluded). */
 uint64_t tim_ctx_device_bytes(const tim_ctx *ctx);
 
+/* ---- profile ------------------------------------------------------------ */
+
+/* Work and GPU time of one sampler kernel (one model, one mode), summed over
+ * its launches since profiling was enabled.  Times come from HIP events
+ * recorded on the context's stream around each launch.  "bytes" are the
+ * algorithmic bytes of the sets the kernel finished itself (sets deferred to
+ * the large-set pass are excluded).  IC: per node 16 (its two CSR offsets),
+ * per examined in-edge 4 (its source; +4 for its threshold when the graph
+ * carries per-edge thresholds).  LT: per node 16 + 4 (offsets and the one
+ * picked source).  Both: when sets are stored, 4 per node plus 12 per set. */
+typedef struct {
+  uint64_t launches;
+  double kernel_ms;
+  uint64_t sets, nodes, edges, bytes;
+  uint64_t large_launches; /* large-set pass launches and time */
+  double large_ms;
+  uint64_t deferred;       /* sets it finished */
+} tim_kernel_profile;
+
+typedef struct {
+  tim_kernel_profile sampler[2][3]; /* [model][0: widths, 1: stored sets, 2: coverage] */
+  uint64_t index_calls;             /* inverted-index builds + greedy runs */
+  double index_ms, greedy_ms;
+} tim_profile;
+
+/* Turns per-launch timing on (on != 0) or off, and clears the counters. */
+tim_status tim_profile_enable(tim_ctx *ctx, int on);
+/* Copies the counters (host out). */
+tim_status tim_profile_read(const tim_ctx *ctx, tim_profile *out);
+
 /* ---- graph (Table 1: G^T as in-edge CSR) --------------------------------- */
 
 /* Copies a directed graph to the device.

@@ -27,7 +27,8 @@ _STATUS = {1: "TIM_EINVAL", 2: "TIM_ENOMEM", 3: "TIM_EBUDGET", 4: "TIM_EDEVICE",
 
 EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_device_bytes", "tim_graph_upload",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
-            "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run")
+            "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
+            "tim_profile_read")
 
 U64, I64, U32, I32, DBL, P = (ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
                               ctypes.c_void_p)
@@ -73,6 +74,18 @@ class Report(ctypes.Structure):
                 ("ms_select_greedy", DBL), ("ms_total", DBL), ("sets_total", U64), ("width_total", U64)]
 
 
+class KernelProfile(ctypes.Structure):
+    _fields_ = [("launches", U64), ("kernel_ms", DBL), ("sets", U64), ("nodes", U64), ("edges", U64),
+                ("bytes", U64), ("large_launches", U64), ("large_ms", DBL), ("deferred", U64)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("sampler", (KernelProfile * 3) * 2), ("index_calls", U64), ("index_ms", DBL), ("greedy_ms", DBL)]
+
+
+MODE_NAMES = ("widths", "store", "cover")
+MODEL_NAMES = ("ic", "lt")
+
 _lib = None
 
 
@@ -106,6 +119,8 @@ def load_library():
                                            ctypes.POINTER(SelectResult)]),
         "tim_run": (ctypes.c_int, [P, P, ctypes.c_int, ctypes.c_int, DBL, DBL, U64, U32, P, P,
                                    ctypes.POINTER(Report)]),
+        "tim_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
+        "tim_profile_read": (ctypes.c_int, [P, ctypes.POINTER(Profile)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -170,6 +185,15 @@ class Engine:
 
     def device_bytes(self) -> int:
         return int(self.lib.tim_ctx_device_bytes(self.ctx))
+
+    def profile(self, on: bool = True):
+        """Turns per-kernel timing on/off and clears the counters."""
+        _check(self.lib.tim_profile_enable(self.ctx, 1 if on else 0))
+
+    def read_profile(self) -> Profile:
+        p = Profile()
+        _check(self.lib.tim_profile_read(self.ctx, ctypes.byref(p)))
+        return p
 
     def _sync_torch(self):
         self._torch.cuda.current_stream(self.device).synchronize()

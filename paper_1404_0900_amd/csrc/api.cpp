@@ -69,16 +69,21 @@ struct tim_ctx {
   uint64_t budget = 0;
   uint64_t held = 0;
   int num_cu = 0;
+  int seg_lanes = 8;
   int grid_ic[3][2] = {};
+  int grid_ic64[3][2] = {};
   int grid_lt[3] = {};
   unsigned long long* ctr = nullptr;       // device counters of the current launch
   unsigned long long* ctr_host = nullptr;  // pinned mirror
-  DevBuf deferred, pool, set_start, set_len;
+  DevBuf list1, list2, pool, set_start, set_len;
   DevBuf big_stamp, big_queue, big_epoch;
   int big_slots = 0;
   int64_t big_n = -1;
   DevBuf rr_off, rr_nodes, sizes, cnt, fill, inv_off, inv_sets, covered, selected, best, scan_tmp, seed_bits;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  bool prof_on = false;
+  hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
+  tim_profile prof = {};
 };
 
 struct tim_graph {
@@ -133,14 +138,21 @@ tim_status ensure_big(tim_ctx* c, int64_t n) {
   release(c, c->big_queue);
   release(c, c->big_epoch);
   c->big_n = -1;
-  int slots = 64;
+  // one slot per CU where memory allows (8 bytes per node per slot); at
+  // most a quarter of the budget, or of the free device memory without one
+  const uint64_t per = (uint64_t)n * 8;
+  uint64_t room = 0;
   if (c->budget) {
-    const uint64_t room = c->budget > c->held ? (c->budget - c->held) / 4 : 0;
-    const uint64_t per = (uint64_t)n * 8;
-    slots = (int)std::min<uint64_t>(64, room / per);
-    if (slots < 1) return fail(TIM_EBUDGET, "budget too small for the large-set pass (needs %llu bytes)",
-                               (unsigned long long)per * 4);
+    room = c->budget > c->held ? (c->budget - c->held) / 4 : 0;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    room = free_b / 4;
   }
+  const int slots = (int)std::min<uint64_t>((uint64_t)std::max(c->num_cu, 64), room / per);
+  if (slots < 1)
+    return fail(TIM_EBUDGET, "budget too small for the large-set pass (needs %llu bytes)",
+                (unsigned long long)per * 4);
   TIM_TRY(ensure(c, c->big_stamp, (size_t)slots * (size_t)n * 4, "large-set stamps"));
   TIM_TRY(ensure(c, c->big_queue, (size_t)slots * (size_t)n * 4, "large-set queues"));
   TIM_TRY(ensure(c, c->big_epoch, (size_t)slots * 4, "large-set epochs"));
@@ -156,13 +168,37 @@ struct Totals {
   u128 kappa = 0;
 };
 
+// Blocks of the tier-0 sampler over `count` sets (and its wavefronts).
+uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t count, uint64_t* waves) {
+  const int per_cu = model == TIM_MODEL_IC ? c->grid_ic[mode][wc ? 1 : 0] : c->grid_lt[mode];
+  const uint64_t waves_per_block = model == TIM_MODEL_IC ? 4 : 2;
+  const uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)c->seg_lanes) : 128;
+  uint64_t grid = (uint64_t)per_cu * (uint64_t)c->num_cu;
+  grid = std::min<uint64_t>(grid, (count + sets_per_block - 1) / sets_per_block);
+  if (grid < 1) grid = 1;
+  if (waves) *waves = grid * waves_per_block;
+  return grid;
+}
+
+// Node-pool entries that per-wavefront slices can leave unused in one launch.
+uint64_t pool_slack(const tim_ctx* c, int model) {
+  uint64_t waves = 0;
+  sample_grid(c, model, tim::kModeEmit, true, ~0ull >> 1, &waves);
+  uint64_t w2 = 0;
+  sample_grid(c, model, tim::kModeEmit, false, ~0ull >> 1, &w2);
+  return std::max(waves, w2) * tim::kPoolChunk;
+}
+
 // One sampling launch pair (wave/lane-level pass, then the large-set pass)
-// over sets [first, first+count) with count <= kMaxLaunchSets.
+// over sets [first, first+count) with count <= kMaxLaunchSets.  Emit mode
+// writes into the node pool from entry pool_base on and records set offsets
+// at set_start[set_offset ..].
 tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, uint64_t seed, uint32_t phase,
                          uint64_t first, uint64_t count, int k, uint64_t* widths, uint32_t* sizes,
-                         uint64_t set_offset, Totals* t) {
+                         uint64_t set_offset, uint64_t pool_base, Totals* t) {
   TIM_TRY(ensure_big(c, g->n));
-  TIM_TRY(ensure(c, c->deferred, count * 8, "deferred-set list"));
+  TIM_TRY(ensure(c, c->list1, count * 8, "deferred-set list"));
+  if (model == TIM_MODEL_IC) TIM_TRY(ensure(c, c->list2, count * 8, "deferred-set list"));
   SampleArgs a;
   memset(&a, 0, sizeof(a));
   a.g.off = g->off;
@@ -179,40 +215,66 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   a.widths = widths;
   a.sizes = sizes;
   if (mode == tim::kModeEmit) {
-    a.pool = c->pool.as<int32_t>();
-    a.pool_cap = c->pool.bytes / 4;
+    const uint64_t cap = c->pool.bytes / 4;
+    a.pool = c->pool.as<int32_t>() + std::min(pool_base, cap);
+    a.pool_cap = pool_base < cap ? cap - pool_base : 0;
+    a.pool_base = pool_base;
     a.set_start = c->set_start.as<uint64_t>() + set_offset;
     a.set_len = c->set_len.as<uint32_t>() + set_offset;
   }
   a.seed_bits = c->seed_bits.as<uint32_t>();
-  a.deferred = c->deferred.as<uint64_t>();
-  a.deferred_cap = count;
+  a.list1 = c->list1.as<uint64_t>();
+  a.list2 = c->list2.as<uint64_t>();
   a.big_stamp = c->big_stamp.as<uint32_t>();
   a.big_queue = c->big_queue.as<int32_t>();
   a.big_epoch = c->big_epoch.as<uint32_t>();
   a.big_slots = c->big_slots;
   const bool wc = g->thr == nullptr;
-  int per_cu = model == TIM_MODEL_IC ? c->grid_ic[mode][wc ? 1 : 0] : c->grid_lt[mode];
-  const uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 : 128;
-  uint64_t grid = (uint64_t)per_cu * (uint64_t)c->num_cu;
-  grid = std::min<uint64_t>(grid, (count + sets_per_block - 1) / sets_per_block);
-  if (grid < 1) grid = 1;
+  const uint64_t grid0 = sample_grid(c, model, mode, wc, count, nullptr);
+  const uint64_t grid1 = (uint64_t)c->grid_ic64[mode][wc ? 1 : 0] * (uint64_t)c->num_cu;
   tim::launch_clear_counters(c->ctr, c->stream);
-  tim::launch_sample(model, mode, a, (int)grid, c->stream);
-  tim::launch_sample_large(model, mode, a, c->stream);
+  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
+  tim::launch_sample(model, mode, a, c->seg_lanes, (int)grid0, (int)grid1, c->stream,
+                     c->prof_on ? c->pev[1] : nullptr);
+  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[2], c->stream));
   HIP_TRY(hipGetLastError());
   HIP_TRY(hipMemcpyAsync(c->ctr_host, c->ctr, tim::kCtrCount * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                          c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
   const unsigned long long* h = c->ctr_host;
-  if (h[tim::kCtrDeferred] > count) return fail(TIM_EDEVICE, "deferred-set list overflow");
+  if (h[tim::kCtrList1] > count || h[tim::kCtrList2] > count) return fail(TIM_EDEVICE, "deferred-set list overflow");
   t->count += count;
-  t->deferred += h[tim::kCtrDeferred];
-  t->kappa += ((u128)h[tim::kCtrKappaHi] << 64) | (u128)h[tim::kCtrKappaLo];
-  t->width += h[tim::kCtrWidth];
-  t->nodes += h[tim::kCtrNodes];
-  t->covered += h[tim::kCtrCovered];
-  t->pool_used = h[tim::kCtrPoolCursor];
+  t->deferred += h[tim::kCtrList1];
+  for (int tier = 0; tier < 3; ++tier) {
+    const unsigned long long* acc = h + tim::kCtrAcc + tim::kAccStride * tier;
+    t->kappa += ((u128)acc[tim::kAccKappaHi] << 64) | (u128)acc[tim::kAccKappaLo];
+    t->width += acc[tim::kAccWidth];
+    t->nodes += acc[tim::kAccNodes];
+    t->covered += acc[tim::kAccCovered];
+  }
+  t->pool_used += h[tim::kCtrPoolCursor];
+  if (c->prof_on) {
+    float ms_main = 0.f, ms_big = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms_main, c->pev[0], c->pev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms_big, c->pev[1], c->pev[2]));
+    tim_kernel_profile& p = c->prof.sampler[model][mode];
+    const unsigned long long* acc0 = h + tim::kCtrAcc;
+    const uint64_t sets = count - h[tim::kCtrList1];
+    const uint64_t nodes = acc0[tim::kAccNodes], edges = acc0[tim::kAccWidth];
+    uint64_t bytes;
+    if (model == TIM_MODEL_IC) bytes = 16 * nodes + (g->thr ? 8 : 4) * edges;
+    else bytes = 20 * nodes;
+    if (mode == tim::kModeEmit) bytes += 4 * nodes + 12 * sets;
+    p.launches += 1;
+    p.kernel_ms += ms_main;
+    p.sets += sets;
+    p.nodes += nodes;
+    p.edges += edges;
+    p.bytes += bytes;
+    p.large_launches += 1;
+    p.large_ms += ms_big;
+    p.deferred += h[tim::kCtrList1];
+  }
   return TIM_OK;
 }
 
@@ -222,43 +284,52 @@ tim_status sample_counts(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   for (uint64_t done = 0; done < count;) {
     const uint64_t part = std::min(count - done, kMaxLaunchSets);
     TIM_TRY(sample_launch(c, g, model, mode, seed, phase, first + done, part, k, widths ? widths + done : nullptr,
-                          sizes ? sizes + done : nullptr, 0, t));
+                          sizes ? sizes + done : nullptr, 0, 0, t));
     done += part;
   }
   return TIM_OK;
 }
 
-// Emit mode: sets [first, first+count) into c->rr_off / c->rr_nodes (CSR in
-// set order).  expect_nodes sizes the node pool; a short pool is regrown to
-// the exact need and the sets regenerated.
-tim_status sample_store(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
-                        uint64_t count, uint64_t expect_nodes, uint64_t* widths, Totals* t_out) {
+// Emit mode: sets [first, first+count) into the node pool (set_start /
+// set_len per set).  expect_nodes sizes the pool; a short pool is regrown to
+// the exact need (nodes plus per-wavefront slack) and the sets regenerated.
+tim_status emit_sets(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
+                     uint64_t count, uint64_t expect_nodes, uint64_t* widths, Totals* t_out) {
   TIM_TRY(ensure(c, c->set_start, count * 8, "set offsets"));
   TIM_TRY(ensure(c, c->set_len, count * 4, "set sizes"));
-  TIM_TRY(ensure(c, c->pool, std::max<uint64_t>(expect_nodes, 1024) * 4, "RR node pool"));
+  const uint64_t slack = pool_slack(c, model) * ((count + kMaxLaunchSets - 1) / kMaxLaunchSets);
+  TIM_TRY(ensure(c, c->pool, (std::max<uint64_t>(expect_nodes, 1024) + slack) * 4, "RR node pool"));
   for (int attempt = 0; attempt < 2; ++attempt) {
     Totals t;
     for (uint64_t done = 0; done < count;) {
       const uint64_t part = std::min(count - done, kMaxLaunchSets);
       TIM_TRY(sample_launch(c, g, model, tim::kModeEmit, seed, phase, first + done, part, 0,
-                            widths ? widths + done : nullptr, nullptr, done, &t));
+                            widths ? widths + done : nullptr, nullptr, done, t.pool_used, &t));
       done += part;
     }
     if (t.pool_used * 4 <= c->pool.bytes) {
-      TIM_TRY(ensure(c, c->rr_off, (count + 1) * 8, "RR set offsets"));
-      TIM_TRY(ensure(c, c->rr_nodes, t.nodes * 4, "RR nodes"));
-      TIM_TRY(ensure(c, c->scan_tmp, tim::scan_temp_bytes(std::max<uint64_t>(count, (uint64_t)g->n + 1)), "scan"));
-      tim::launch_scan_u32_to_i64(c->set_len.as<uint32_t>(), c->rr_off.as<int64_t>(), count, c->scan_tmp.p,
-                                  c->stream);
-      tim::launch_compact(c->pool.as<int32_t>(), c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
-                          c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), count, c->stream);
-      HIP_TRY(hipGetLastError());
       *t_out = t;
       return TIM_OK;
     }
-    TIM_TRY(ensure(c, c->pool, t.pool_used * 4, "RR node pool"));
+    TIM_TRY(ensure(c, c->pool, (t.nodes + slack) * 4, "RR node pool"));
   }
   return fail(TIM_EDEVICE, "node pool still short after regrowing");
+}
+
+// Emit mode into c->rr_off / c->rr_nodes: a flat CSR of the sets in id order.
+tim_status sample_store(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
+                        uint64_t count, uint64_t expect_nodes, uint64_t* widths, Totals* t_out) {
+  Totals t;
+  TIM_TRY(emit_sets(c, g, model, seed, phase, first, count, expect_nodes, widths, &t));
+  TIM_TRY(ensure(c, c->rr_off, (count + 1) * 8, "RR set offsets"));
+  TIM_TRY(ensure(c, c->rr_nodes, t.nodes * 4, "RR nodes"));
+  TIM_TRY(ensure(c, c->scan_tmp, tim::scan_temp_bytes(std::max<uint64_t>(count, (uint64_t)g->n + 1)), "scan"));
+  tim::launch_scan_u32_to_i64(c->set_len.as<uint32_t>(), c->rr_off.as<int64_t>(), count, c->scan_tmp.p, c->stream);
+  tim::launch_compact(c->pool.as<int32_t>(), c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
+                      c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), count, c->stream);
+  HIP_TRY(hipGetLastError());
+  *t_out = t;
+  return TIM_OK;
 }
 
 // Greedy maximum coverage over a CSR collection in device memory.
@@ -276,6 +347,7 @@ tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off,
   tim::GreedyArgs a;
   a.n = n;
   a.nsets = nsets;
+  a.total = total;
   a.set_off = set_off;
   a.nodes = nodes;
   a.cnt = c->cnt.as<uint32_t>();
@@ -286,12 +358,23 @@ tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off,
   a.selected = c->selected.as<uint8_t>();
   a.best = c->best.as<unsigned long long>();
   a.scan_temp = c->scan_tmp.p;
+  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
   tim::launch_index(a, c->stream);
+  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[1], c->stream));
   tim::launch_greedy(a, k, c->stream);
+  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[2], c->stream));
   HIP_TRY(hipGetLastError());
   std::vector<unsigned long long> keys((size_t)k);
   HIP_TRY(hipMemcpyAsync(keys.data(), a.best, (size_t)k * 8, hipMemcpyDeviceToHost, c->stream));
   HIP_TRY(hipStreamSynchronize(c->stream));
+  if (c->prof_on) {
+    float ms_index = 0.f, ms_greedy = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms_index, c->pev[0], c->pev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms_greedy, c->pev[1], c->pev[2]));
+    c->prof.index_calls += 1;
+    c->prof.index_ms += ms_index;
+    c->prof.greedy_ms += ms_greedy;
+  }
   for (int j = 0; j < k; ++j) {
     seeds[j] = (int32_t)(0xFFFFFFFFull - (keys[j] & 0xFFFFFFFFull));
     if (gains) gains[j] = keys[j] >> 32;
@@ -486,14 +569,19 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
     }
     c->own_stream = true;
   }
+  c->seg_lanes = tim::ic_seg_lanes();
   for (int mode = 0; mode < 3; ++mode) {
-    c->grid_ic[mode][0] = tim::ic_wave_blocks_per_cu(mode, false);
-    c->grid_ic[mode][1] = tim::ic_wave_blocks_per_cu(mode, true);
+    for (int wc = 0; wc < 2; ++wc) {
+      c->grid_ic[mode][wc] = tim::ic_blocks_per_cu(mode, wc != 0, c->seg_lanes);
+      c->grid_ic64[mode][wc] = tim::ic_tier1_blocks_per_cu(mode, wc != 0);
+    }
     c->grid_lt[mode] = tim::lt_lane_blocks_per_cu(mode);
   }
   if (hipMalloc(&c->ctr, tim::kCtrCount * sizeof(unsigned long long)) != hipSuccess ||
       hipHostMalloc(&c->ctr_host, tim::kCtrCount * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
-      hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess) {
+      hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
+      hipEventCreate(&c->pev[0]) != hipSuccess || hipEventCreate(&c->pev[1]) != hipSuccess ||
+      hipEventCreate(&c->pev[2]) != hipSuccess) {
     tim_ctx_destroy(c);
     return fail(TIM_EDEVICE, "context allocation failed");
   }
@@ -505,7 +593,7 @@ void tim_ctx_destroy(tim_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  DevBuf* bufs[] = {&c->deferred, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
+  DevBuf* bufs[] = {&c->list1, &c->list2, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
                     &c->rr_off, &c->rr_nodes, &c->sizes, &c->cnt, &c->fill, &c->inv_off, &c->inv_sets, &c->covered,
                     &c->selected, &c->best, &c->scan_tmp, &c->seed_bits};
   for (DevBuf* b : bufs) release(c, *b);
@@ -513,11 +601,26 @@ void tim_ctx_destroy(tim_ctx* c) {
   if (c->ctr_host) (void)hipHostFree(c->ctr_host);
   for (hipEvent_t e : c->ev)
     if (e) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->pev)
+    if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 
 uint64_t tim_ctx_device_bytes(const tim_ctx* c) { return c ? c->held : 0; }
+
+tim_status tim_profile_enable(tim_ctx* c, int on) {
+  if (!c) return fail(TIM_EINVAL, "null context");
+  c->prof_on = on != 0;
+  memset(&c->prof, 0, sizeof(c->prof));
+  return TIM_OK;
+}
+
+tim_status tim_profile_read(const tim_ctx* c, tim_profile* out) {
+  if (!c || !out) return fail(TIM_EINVAL, "null argument");
+  *out = c->prof;
+  return TIM_OK;
+}
 
 tim_status tim_graph_upload(tim_ctx* c, int64_t n, int64_t m, const int64_t* in_off, const int32_t* in_src,
                             const uint32_t* ic_thr, tim_graph** out) {
@@ -576,20 +679,7 @@ tim_status tim_sample_rr(tim_ctx* c, const tim_graph* g, int model, uint64_t see
   if (!d_set_off || phase > 255) return fail(TIM_EINVAL, "bad output offsets pointer or phase");
   HIP_TRY(hipSetDevice(c->device));
   Totals t;
-  TIM_TRY(ensure(c, c->set_start, count * 8, "set offsets"));
-  TIM_TRY(ensure(c, c->set_len, count * 4, "set sizes"));
-  TIM_TRY(ensure(c, c->pool, std::max<uint64_t>(count * 16, 1024) * 4, "RR node pool"));
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    t = Totals();
-    for (uint64_t done = 0; done < count;) {
-      const uint64_t part = std::min(count - done, kMaxLaunchSets);
-      TIM_TRY(sample_launch(c, g, model, tim::kModeEmit, seed, phase, first + done, part, 0,
-                            d_widths ? d_widths + done : nullptr, nullptr, done, &t));
-      done += part;
-    }
-    if (t.pool_used * 4 <= c->pool.bytes) break;
-    TIM_TRY(ensure(c, c->pool, t.pool_used * 4, "RR node pool"));
-  }
+  TIM_TRY(emit_sets(c, g, model, seed, phase, first, count, count * 16, d_widths, &t));
   if (total_nodes) *total_nodes = t.nodes;
   if (stats) {
     memset(stats, 0, sizeof(*stats));

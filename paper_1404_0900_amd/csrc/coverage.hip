@@ -9,6 +9,8 @@
 // that a single atomicMax selects the largest count with ties to the lowest
 // id, and one cover kernel marks the chosen node's uncovered sets and
 // decrements the counts of their members.
+#include <algorithm>
+
 #include "engine.hpp"
 
 namespace tim {
@@ -142,21 +144,103 @@ __global__ void zero_u64(unsigned long long* p, uint64_t len) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0ull;
 }
 
-// cnt[u] = number of sets containing u (sets never repeat a node).
-__global__ void hist_kernel(const int64_t* set_off, const int32_t* nodes, uint64_t nsets, uint32_t* cnt) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nsets; s += stride)
-    for (int64_t i = set_off[s]; i < set_off[s + 1]; ++i) atomicAdd(&cnt[nodes[i]], 1u);
+// ---- per-tile aggregation of node updates in LDS ----
+// A tile's updates to the same node (hub nodes recur in many RR sets) are
+// summed in an LDS open-addressing table and reach device memory as one
+// atomic per distinct node per tile.  Nodes that find the table full fall
+// back to direct atomics.
+constexpr int kAggLog = 11;
+constexpr int kAgg = 1 << kAggLog;
+constexpr int kTileSets = 128;   // sets per tile (scatter and cover)
+constexpr int kTileEntries = 2048;  // entries per tile (histogram)
+
+__device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert) {
+  const uint32_t key = u + 1u;
+  uint32_t pos = (u * 0x9E3779B1u) >> (32 - kAggLog);
+  for (int i = 0; i < kAgg; ++i) {
+    const uint32_t cur = keys[pos];
+    if (cur == key) return (int)pos;
+    if (cur == 0u) {
+      if (!insert) return -1;
+      const uint32_t old = atomicCAS(&keys[pos], 0u, key);
+      if (old == 0u || old == key) return (int)pos;
+    }
+    pos = (pos + 1u) & (kAgg - 1u);
+  }
+  return -1;
 }
 
-__global__ void scatter_kernel(const int64_t* set_off, const int32_t* nodes, uint64_t nsets, const int64_t* inv_off,
-                               uint32_t* fill, uint32_t* inv_sets) {
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; s < nsets; s += stride)
-    for (int64_t i = set_off[s]; i < set_off[s + 1]; ++i) {
-      const int32_t u = nodes[i];
-      inv_sets[inv_off[u] + atomicAdd(&fill[u], 1u)] = (uint32_t)s;
+__device__ __forceinline__ void agg_clear(uint32_t* a, uint32_t* b) {
+  for (int i = threadIdx.x; i < kAgg; i += blockDim.x) {
+    a[i] = 0u;
+    if (b) b[i] = 0u;
+  }
+}
+
+// cnt[u] = number of sets containing u (sets never repeat a node).
+__global__ __launch_bounds__(kThreads) void hist_kernel(const int32_t* nodes, uint64_t total, uint32_t* cnt) {
+  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
+  for (uint64_t t0 = (uint64_t)blockIdx.x * kTileEntries; t0 < total; t0 += (uint64_t)gridDim.x * kTileEntries) {
+    agg_clear(s_key, s_cnt);
+    __syncthreads();
+    const uint64_t t1 = min(t0 + (uint64_t)kTileEntries, total);
+    for (uint64_t e = t0 + threadIdx.x; e < t1; e += kThreads) {
+      const uint32_t u = (uint32_t)nodes[e];
+      const int slot = agg_slot(s_key, u, true);
+      if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
+      else atomicAdd(&cnt[u], 1u);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAgg; i += kThreads)
+      if (s_key[i]) atomicAdd(&cnt[s_key[i] - 1u], s_cnt[i]);
+    __syncthreads();
+  }
+}
+
+// Position of entry e among the tile's sets: the set j with off[j] <= e < off[j+1].
+__device__ __forceinline__ int tile_set_of(const int64_t* s_off, int ns, int64_t e) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_off[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+// inv_sets[inv_off[u] ..] = the sets containing u, in no particular order.
+__global__ __launch_bounds__(kThreads) void scatter_kernel(const int64_t* set_off, const int32_t* nodes, uint64_t nsets,
+                                                           const int64_t* inv_off, uint32_t* fill,
+                                                           uint32_t* inv_sets) {
+  __shared__ int64_t s_off[kTileSets + 1];
+  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg], s_base[kAgg];
+  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
+    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
+    agg_clear(s_key, s_cnt);
+    for (int i = threadIdx.x; i <= ns; i += kThreads) s_off[i] = set_off[s0 + i];
+    __syncthreads();
+    const int64_t e0 = s_off[0], e1 = s_off[ns];
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+      const int slot = agg_slot(s_key, (uint32_t)nodes[e], true);
+      if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAgg; i += kThreads) {
+      if (s_key[i]) s_base[i] = atomicAdd(&fill[s_key[i] - 1u], s_cnt[i]);
+      s_cnt[i] = 0u;
+    }
+    __syncthreads();
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+      const uint32_t u = (uint32_t)nodes[e];
+      const uint32_t s = (uint32_t)(s0 + (uint64_t)tile_set_of(s_off, ns, e));
+      const int slot = agg_slot(s_key, u, false);
+      uint64_t pos;
+      if (slot >= 0) pos = (uint64_t)inv_off[u] + s_base[slot] + atomicAdd(&s_cnt[slot], 1u);
+      else pos = (uint64_t)inv_off[u] + atomicAdd(&fill[u], 1u);
+      inv_sets[pos] = s;
+    }
+    __syncthreads();
+  }
 }
 
 // Key of node u: 0 if selected, else count<<32 | (0xFFFFFFFF - u), so the
@@ -180,26 +264,70 @@ __global__ __launch_bounds__(kThreads) void argmax_kernel(const uint32_t* cnt, c
   if (lane == 0) red[wv] = key;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int w = 1; w < kThreads / 64; ++w) key = red[w] > key ? red[w] : key;
-    key = red[0] > key ? red[0] : key;
+    for (int w = 0; w < kThreads / 64; ++w) key = red[w] > key ? red[w] : key;
     if (key) atomicMax(best, key);
   }
 }
 
-__global__ void cover_kernel(const unsigned long long* best, const int64_t* inv_off, const uint32_t* inv_sets,
-                             const int64_t* set_off, const int32_t* nodes, uint8_t* covered, uint8_t* selected,
-                             uint32_t* cnt) {
+// The chosen node v covers the sets listed in inv_sets[inv_off[v] ..]: mark
+// those not covered yet and take them out of the counts of their members
+// (v's own count is left alone: v is never chosen again).
+__global__ __launch_bounds__(kThreads) void cover_kernel(const unsigned long long* best, const int64_t* inv_off,
+                                                         const uint32_t* inv_sets, const int64_t* set_off,
+                                                         const int32_t* nodes, uint8_t* covered, uint8_t* selected,
+                                                         uint32_t* cnt) {
+  __shared__ int64_t s_start[kTileSets];
+  __shared__ int64_t s_pre[kTileSets + 1];  // prefix sums of the new sets' sizes
+  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
+  __shared__ uint32_t s_wtot[kThreads / 64];
   if (*best == 0ull) return;  // no unselected node (cannot happen for k <= n)
   const int64_t v = (int64_t)(0xFFFFFFFFull - (*best & 0xFFFFFFFFull));
-  const uint64_t gid = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (gid == 0) selected[v] = 1u;
+  if (blockIdx.x == 0 && threadIdx.x == 0) selected[v] = 1u;
   const int64_t lo = inv_off[v], hi = inv_off[v + 1];
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = lo + (int64_t)gid; i < hi; i += stride) {
-    const uint32_t s = inv_sets[i];
-    if (covered[s]) continue;
-    covered[s] = 1u;
-    for (int64_t t = set_off[s]; t < set_off[s + 1]; ++t) atomicSub(&cnt[nodes[t]], 1u);
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  for (int64_t i0 = lo + (int64_t)blockIdx.x * kTileSets; i0 < hi; i0 += (int64_t)gridDim.x * kTileSets) {
+    const int ni = (int)min((int64_t)kTileSets, hi - i0);
+    agg_clear(s_key, s_cnt);
+    // newly covered sets of this tile and their sizes
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < ni) {
+      const uint32_t sid = inv_sets[i0 + threadIdx.x];
+      if (!covered[sid]) {
+        covered[sid] = 1u;
+        start = set_off[sid];
+        len = (uint32_t)(set_off[sid + 1] - start);
+      }
+    }
+    uint32_t incl = len;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t y = __shfl_up(incl, o, 64);
+      if (lane >= o) incl += y;
+    }
+    if (lane == 63) s_wtot[wv] = incl;
+    __syncthreads();
+    uint32_t carry = 0;
+    for (int w = 0; w < wv; ++w) carry += s_wtot[w];
+    if (threadIdx.x < kTileSets) {
+      s_start[threadIdx.x] = start;
+      s_pre[threadIdx.x + 1] = carry + incl;
+    }
+    if (threadIdx.x == 0) s_pre[0] = 0;
+    __syncthreads();
+    const int64_t tot = s_pre[kTileSets];
+    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+      const int j = tile_set_of(s_pre, kTileSets, e);
+      const int32_t u = nodes[s_start[j] + (e - s_pre[j])];
+      if (u == v) continue;
+      const int slot = agg_slot(s_key, (uint32_t)u, true);
+      if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
+      else atomicSub(&cnt[u], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAgg; i += kThreads)
+      if (s_key[i]) atomicSub(&cnt[s_key[i] - 1u], s_cnt[i]);
+    __syncthreads();
   }
 }
 
@@ -243,13 +371,17 @@ void launch_index(const GreedyArgs& a, hipStream_t s) {
   const uint64_t n = (uint64_t)a.n;
   hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.cnt, n);
   hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.fill, n);
-  if (a.nsets)
-    hipLaunchKernelGGL(hist_kernel, dim3(grid_for(a.nsets, 8192)), dim3(kThreads), 0, s, a.set_off, a.nodes, a.nsets,
-                       a.cnt);
+  if (a.total) {
+    const uint64_t tiles = (a.total + kTileEntries - 1) / kTileEntries;
+    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s, a.nodes,
+                       a.total, a.cnt);
+  }
   launch_scan_u32_to_i64(a.cnt, a.inv_off, n, a.scan_temp, s);
-  if (a.nsets)
-    hipLaunchKernelGGL(scatter_kernel, dim3(grid_for(a.nsets, 8192)), dim3(kThreads), 0, s, a.set_off, a.nodes,
-                       a.nsets, a.inv_off, a.fill, a.inv_sets);
+  if (a.nsets) {
+    const uint64_t tiles = (a.nsets + kTileSets - 1) / kTileSets;
+    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s,
+                       a.set_off, a.nodes, a.nsets, a.inv_off, a.fill, a.inv_sets);
+  }
 }
 
 void launch_greedy(const GreedyArgs& a, int k, hipStream_t s) {
@@ -260,8 +392,10 @@ void launch_greedy(const GreedyArgs& a, int k, hipStream_t s) {
   const unsigned gmax = grid_for(n, 2048);
   for (int j = 0; j < k; ++j) {
     hipLaunchKernelGGL(argmax_kernel, dim3(gmax), dim3(kThreads), 0, s, a.cnt, a.selected, a.n, a.best + j);
-    hipLaunchKernelGGL(cover_kernel, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets, a.set_off,
-                       a.nodes, a.covered, a.selected, a.cnt);
+    // the last choice changes no later step: its cover pass is skipped
+    if (j + 1 < k)
+      hipLaunchKernelGGL(cover_kernel, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
+                         a.set_off, a.nodes, a.covered, a.selected, a.cnt);
   }
 }
 

@@ -14,19 +14,41 @@ enum SampleMode : int {
   kModeCover = 2   // does R meet a seed set? (Algorithm 3, lines 9-10)
 };
 
-// Device counters of one sampling launch (zeroed before it).
+// Device counters of one sampling launch (zeroed before it).  Sets flow
+// through up to three tiers: tier 0 takes the launch's range of set ids and
+// hands sets that outgrow its on-chip structures to list 1; tier 1 (IC only)
+// takes list 1 and hands the rest to list 2; the last tier (device-memory
+// visited stamps) finishes list 2 (IC) or list 1 (LT).  Each tier has its own
+// block of accumulators at kCtrAcc + kAccStride * tier.
 enum Counter : int {
-  kCtrNextSet = 0,    // next set (relative id) for the wave-level pass
-  kCtrDeferred = 1,   // sets handed to the large-set pass
-  kCtrPoolCursor = 2, // entries reserved in the node pool
-  kCtrNextBig = 3,    // next deferred set for the large-set pass
-  kCtrKappaLo = 4,    // exact sum of kappa * 2^53 (128 bits)
-  kCtrKappaHi = 5,
-  kCtrWidth = 6,      // sum of w(R)
-  kCtrNodes = 7,      // sum of |R|
-  kCtrCovered = 8,    // sets meeting the seed set
-  kCtrCount = 16
+  kCtrNext0 = 0,       // tier-0 cursor over the range
+  kCtrList1 = 1,       // length of list 1
+  kCtrNext1 = 2,       // tier-1 cursor over list 1
+  kCtrList2 = 3,       // length of list 2
+  kCtrNext2 = 4,       // last-tier cursor
+  kCtrPoolCursor = 5,  // node-pool entries reserved
+  kCtrAcc = 8,
+  kAccKappaLo = 0,     // exact sum of kappa * 2^53 (128 bits)
+  kAccKappaHi = 1,
+  kAccWidth = 2,       // sum of w(R): edges examined
+  kAccNodes = 3,       // sum of |R| (coverage mode: nodes reached before the first seed)
+  kAccCovered = 4,     // sets meeting the seed set
+  kAccStride = 8,
+  kCtrCount = kCtrAcc + 3 * kAccStride
 };
+
+// Where one tier reads its sets and where it sends the ones it defers.
+struct TierIO {
+  const uint64_t* in_list;  // relative set ids, or nullptr for the range [0, count)
+  int in_len_ctr;           // counter holding the length of in_list
+  int next_ctr;             // work cursor
+  uint64_t* out_list;       // deferred sets (relative ids), capacity = count
+  int out_len_ctr;
+  int acc;                  // accumulator block (tier number)
+};
+
+// Node-pool entries a wavefront reserves at a time when it stores sets.
+constexpr uint64_t kPoolChunk = 2048;
 
 struct GraphView {
   const int64_t* off;   // n+1
@@ -44,14 +66,15 @@ struct SampleArgs {
   unsigned long long* ctr;        // kCtrCount counters
   uint64_t* widths;               // per set, nullable
   uint32_t* sizes;                // per set, nullable
-  int32_t* pool;                  // emit: node pool
-  uint64_t pool_cap;
+  int32_t* pool;                  // emit: this launch's part of the node pool
+  uint64_t pool_cap;              // entries in it
+  uint64_t pool_base;             // its offset in the whole pool (added to set_start)
   uint64_t* set_start;            // emit: pool offset of each set
   uint32_t* set_len;              // emit: size of each set
   const uint32_t* seed_bits;      // cover: n-bit membership of the seed set
-  uint64_t* deferred;             // relative ids of sets for the large-set pass
-  uint64_t deferred_cap;
-  // large-set pass: per-slot visited stamps and queues (n entries each)
+  uint64_t* list1;                // deferred lists (capacity count each)
+  uint64_t* list2;
+  // last tier: per-slot visited stamps and queues (n entries each)
   uint32_t* big_stamp;
   int32_t* big_queue;
   uint32_t* big_epoch;
@@ -60,10 +83,17 @@ struct SampleArgs {
 
 // ---- sample.hip ----
 void launch_clear_counters(unsigned long long* ctr, hipStream_t s);
-int ic_wave_blocks_per_cu(int mode, bool wc);
+// Lanes per set of the IC tier-0 kernel: 8, 16, 32 or 64 (environment
+// variable TIM_IC_SEG_LANES, read when a context is created; default 8).
+int ic_seg_lanes();
+int ic_blocks_per_cu(int mode, bool wc, int seg_lanes);
+int ic_tier1_blocks_per_cu(int mode, bool wc);
 int lt_lane_blocks_per_cu(int mode);
-void launch_sample(int model, int mode, const SampleArgs& a, int grid_small, hipStream_t s);
-void launch_sample_large(int model, int mode, const SampleArgs& a, hipStream_t s);
+// Tier 0 (grid0 blocks; IC with seg_lanes lanes per set), then the deferral
+// tiers (IC tier 1 with grid1 blocks).  after_tier0, if given, is recorded
+// between tier 0 and the rest.
+void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int grid0, int grid1, hipStream_t s,
+                   hipEvent_t after_tier0);
 
 // ---- coverage.hip ----
 // out[0..len] = exclusive prefix sums of in[0..len), out[len] = total.
@@ -77,6 +107,7 @@ void launch_set_sizes(const int64_t* set_off, uint32_t* sizes, uint64_t nsets, h
 struct GreedyArgs {
   int64_t n;
   uint64_t nsets;
+  uint64_t total;      // entries of the collection (set_off[nsets])
   const int64_t* set_off;
   const int32_t* nodes;
   uint32_t* cnt;       // n: coverage counts

@@ -1,26 +1,30 @@
 // RR-set samplers for gfx950 (Definitions 1-2; Section 3.1; Section 4.2).
 //
-// IC, wave-level pass: one 64-wide wavefront builds one RR set at a time by
-// reverse BFS.  The set's nodes live in an LDS queue (which is also the
-// output list) and an LDS open-addressing hash marks visited nodes.  Each BFS
-// step takes up to 64 queued nodes, prefix-sums the number of 4-edge groups
-// of their in-edge lists, and spreads the groups over the lanes: a lane loads
-// 4 consecutive sources with one 16-byte load, draws one Philox block for the
-// group and decides the 4 edges with its 4 words.  Live edges into unvisited
-// nodes are appended to the queue.  Sets that outgrow the LDS structures are
-// handed to the large-set pass (deterministic: a set is a pure function of its
-// keys, so restarting it elsewhere gives the same set).
+// IC (reverse BFS over in-edges), tier 0: a wavefront is split into segments
+// of S lanes and every segment builds its own RR set, so one wavefront keeps
+// 64/S sets in flight and their memory latencies overlap.  A set's nodes live
+// in an LDS queue (which is also its output list) and an LDS open-addressing
+// hash marks visited nodes.  Each iteration of the loop, every segment either
+// loads its next batch of up to S queued nodes (two CSR offsets per lane, a
+// segmented prefix sum of their 4-edge groups) or processes S groups of the
+// current batch: a lane loads 4 consecutive sources with one 16-byte load,
+// draws one Philox block for the group and decides the 4 edges with its 4
+// words; live edges into unvisited nodes are appended to the queue.  Sets
+// that outgrow the segment's LDS structures are deferred: a set is a pure
+// function of its keys, so restarting it in another tier gives the same set.
+// Tier 1 is the same kernel with one set per wavefront and 8x the LDS
+// capacity; the last tier is a 256-thread block per set with visited stamps
+// and a queue of n entries in device memory.
 //
-// LT, lane-level pass: each lane walks one set's chain (one live in-edge per
-// node); the chain sits in LDS with a 64-bit membership signature in a
-// register; longer chains go to the large-set pass.
+// LT (one live in-edge per node): each lane walks one set's chain, kept in LDS
+// with a 64-bit membership signature in a register; longer chains go to the
+// last tier (one lane per set, stamps in device memory).
 //
-// Large-set pass: a 256-thread block per IC set (lane per set for LT) with a
-// visited-stamp array and a queue of n entries per slot in device memory.
-//
-// Each launch also reduces what the phase needs: the exact 128-bit sum of
+// Every launch also reduces what the phase needs: the exact 128-bit sum of
 // kappa(R) * 2^53 (Equation (8)), the widths (Equation (1)), the set sizes,
 // and the number of sets meeting a seed set (Algorithm 3, line 10).
+#include <stdlib.h>
+
 #include "engine.hpp"
 #include "rng.hpp"
 
@@ -28,13 +32,10 @@ namespace tim {
 namespace {
 
 constexpr int kWave = 64;
-constexpr int kIcWaves = 4;        // wavefronts per block, IC wave-level pass
-constexpr int kQCap = 512;         // nodes of one set held in LDS
-constexpr int kHLog = 10;
-constexpr int kHCap = 1 << kHLog;  // LDS hash slots per wavefront
+constexpr int kSegThreads = 256;   // block size of the IC segment kernels
 constexpr int kLtWaves = 2;        // wavefronts per block, LT lane-level pass
 constexpr int kChain = 64;         // LT chain length held in LDS
-constexpr int kBigThreads = 256;   // IC large-set pass block size
+constexpr int kBigThreads = 512;   // IC last-tier block size
 
 typedef unsigned __int128 u128;
 
@@ -44,19 +45,29 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-__device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x, int lane) {
+// Inclusive prefix sum within segments of W lanes.
+template <int W>
+__device__ __forceinline__ uint32_t seg_incl_scan(uint32_t x, int sl) {
 #pragma unroll
-  for (int o = 1; o < kWave; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, kWave);
-    if (lane >= o) x += y;
+  for (int o = 1; o < W; o <<= 1) {
+    const uint32_t y = __shfl_up(x, o, W);
+    if (sl >= o) x += y;
   }
   return x;
 }
 
-__device__ __forceinline__ unsigned long long wave_sum(unsigned long long x) {
+template <int W>
+__device__ __forceinline__ unsigned long long seg_sum(unsigned long long x) {
 #pragma unroll
-  for (int o = kWave / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
   return x;
+}
+
+// The W bits of a 64-lane ballot that belong to segment sw.
+template <int W>
+__device__ __forceinline__ uint64_t seg_bits(uint64_t m, int sw) {
+  if (W == 64) return m;
+  return (m >> (sw * W)) & ((1ull << (W & 63)) - 1ull);
 }
 
 // kappa(R) * 2^53 (Equation (8)): q = 1 - w/m, q^k by binary exponentiation,
@@ -99,11 +110,14 @@ __device__ __forceinline__ bool edge_live(uint32_t x, uint32_t t, int64_t d) {
   }
 }
 
-// Open addressing in LDS, key u+1 (0 = empty).  1: inserted, 0: present, -1: full.
+// Open addressing in LDS over 2^HLOG slots, key u+1 (0 = empty).
+// Returns 1: inserted, 0: already present, -1: table full.
+template <int HLOG>
 __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
+  constexpr uint32_t H = 1u << HLOG;
   const uint32_t key = u + 1u;
-  uint32_t pos = (u * 0x9E3779B1u) >> (32 - kHLog);
-  for (int i = 0; i < kHCap; ++i) {
+  uint32_t pos = (u * 0x9E3779B1u) >> (32 - HLOG);
+  for (uint32_t i = 0; i < H; ++i) {
     const uint32_t cur = h[pos];
     if (cur == key) return 0;
     if (cur == 0u) {
@@ -111,7 +125,7 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
       if (old == 0u) return 1;
       if (old == key) return 0;
     }
-    pos = (pos + 1u) & (kHCap - 1u);
+    pos = (pos + 1u) & (H - 1u);
   }
   return -1;
 }
@@ -121,170 +135,321 @@ struct Acc {
   unsigned long long width = 0, nodes = 0, covered = 0;
 };
 
-__device__ __forceinline__ void flush(const SampleArgs& a, const Acc& acc) {
-  add_u128(&a.ctr[kCtrKappaLo], acc.kappa);
-  if (acc.width) atomicAdd(&a.ctr[kCtrWidth], acc.width);
-  if (acc.nodes) atomicAdd(&a.ctr[kCtrNodes], acc.nodes);
-  if (acc.covered) atomicAdd(&a.ctr[kCtrCovered], acc.covered);
+// Sum of every lane's accumulators, added to the counters by lane 0.
+__device__ __forceinline__ void wave_flush(const SampleArgs& a, const Acc& acc, int tier, int lane) {
+  const unsigned long long lo = (unsigned long long)acc.kappa, hi = (unsigned long long)(acc.kappa >> 64);
+  const unsigned long long s_hi = seg_sum<kWave>(hi);
+  const unsigned long long s_l0 = seg_sum<kWave>(lo & 0xFFFFFFFFull);
+  const unsigned long long s_l1 = seg_sum<kWave>(lo >> 32);
+  const unsigned long long w = seg_sum<kWave>(acc.width);
+  const unsigned long long nd = seg_sum<kWave>(acc.nodes);
+  const unsigned long long cv = seg_sum<kWave>(acc.covered);
+  if (lane == 0) {
+    unsigned long long* c = a.ctr + kCtrAcc + kAccStride * tier;
+    add_u128(c + kAccKappaLo, ((u128)s_hi << 64) + ((u128)s_l1 << 32) + (u128)s_l0);
+    if (w) atomicAdd(c + kAccWidth, w);
+    if (nd) atomicAdd(c + kAccNodes, nd);
+    if (cv) atomicAdd(c + kAccCovered, cv);
+  }
 }
 
-__device__ __forceinline__ void defer(const SampleArgs& a, uint64_t rel) {
-  const unsigned long long pos = atomicAdd(&a.ctr[kCtrDeferred], 1ull);
-  if (pos < a.deferred_cap) a.deferred[pos] = rel;
+__device__ __forceinline__ void block_flush(const SampleArgs& a, const Acc& acc, int tier) {
+  unsigned long long* c = a.ctr + kCtrAcc + kAccStride * tier;
+  add_u128(c + kAccKappaLo, acc.kappa);
+  if (acc.width) atomicAdd(c + kAccWidth, acc.width);
+  if (acc.nodes) atomicAdd(c + kAccNodes, acc.nodes);
+  if (acc.covered) atomicAdd(c + kAccCovered, acc.covered);
 }
 
-// ------------------------------------------------------------------------
-// IC, wave-level pass.
-// ------------------------------------------------------------------------
-template <int MODE, bool WC>
-__global__ __launch_bounds__(kIcWaves* kWave) void ic_wave_kernel(SampleArgs a) {
-  __shared__ int32_t s_queue[kIcWaves][kQCap];
-  __shared__ uint32_t s_hash[kIcWaves][kHCap];
-  __shared__ uint32_t s_tail[kIcWaves];
-  const int wv = threadIdx.x / kWave;
-  const int lane = threadIdx.x % kWave;
-  int32_t* q = s_queue[wv];
-  uint32_t* h = s_hash[wv];
-  const GraphView g = a.g;
-  Acc acc;
+__device__ __forceinline__ unsigned long long list_len(const SampleArgs& a, int ctr) {
+  const unsigned long long d = a.ctr[ctr];
+  return d < a.count ? d : a.count;
+}
 
-  unsigned long long rel = 0;
-  if (lane == 0) rel = atomicAdd(&a.ctr[kCtrNextSet], 1ull);
-  rel = __shfl(rel, 0);
-  while (rel < a.count) {
-    unsigned long long next = 0;
-    if (lane == 0) next = atomicAdd(&a.ctr[kCtrNextSet], 1ull);
-    const SetStream st = make_set_stream(a.seed, a.phase, a.first + rel);
+// Wave-uniform reservoir of work items [cur, end), refilled `chunk` at a time.
+struct Reservoir {
+  unsigned long long cur = 0, end = 0, chunk = 1;
+};
 
-    uint4* h4 = reinterpret_cast<uint4*>(h);
-    for (int i = lane; i < kHCap / 4; i += kWave) h4[i] = make_uint4(0u, 0u, 0u, 0u);
-    const int32_t root = draw_root(st, g.n);
-    wave_sync();
-    if (lane == 0) {
-      q[0] = root;
-      s_tail[wv] = 1u;
-      lds_insert(h, (uint32_t)root);
-    }
-    wave_sync();
+// Items per refill: about 8 refills per wavefront over the launch, at least
+// one item per requester, at most 64 per requester.
+__device__ __forceinline__ unsigned long long chunk_for(unsigned long long total, int waves_per_block,
+                                                        int per_wave) {
+  const unsigned long long waves = (unsigned long long)gridDim.x * (unsigned long long)waves_per_block;
+  unsigned long long c = total / (waves * 8ull);
+  c = c < (unsigned long long)per_wave ? (unsigned long long)per_wave : c;
+  return c > 64ull * per_wave ? 64ull * per_wave : c;
+}
 
-    bool hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
-    bool bad = false;
-    int head = 0, tail = 1;
-    unsigned long long wlane = 0;
-    while (head < tail && !hit && !bad) {
-      const int nb = min(tail - head, kWave);
-      int64_t ea = 0;
-      int64_t d = 0;
-      uint32_t ng = 0;
-      if (lane < nb) {
-        const int32_t v = q[head + lane];
-        ea = g.off[v];
-        const int64_t eb = g.off[v + 1];
-        d = eb - ea;
-        ng = d ? (uint32_t)(((eb - 1) >> 2) - (ea >> 2) + 1) : 0u;
+// Hands one work item to every requester (lanes with want && is_leader); all
+// lanes of a segment see their leader's result through below_leader.  Lanes
+// that get nothing because the work is gone set exhausted.
+__device__ __forceinline__ bool take(const SampleArgs& a, int next_ctr, unsigned long long total, Reservoir& r,
+                                     bool want, bool is_leader, uint64_t below_leader, int lane, bool& exhausted,
+                                     unsigned long long& item) {
+  bool got = false;
+  uint64_t wmask = __ballot(want && is_leader);
+  while (wmask) {
+    if (r.cur >= r.end) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(&a.ctr[next_ctr], r.chunk);
+      base = __shfl(base, 0);
+      if (base >= total) {
+        if (want) exhausted = true;
+        break;
       }
-      wlane += (unsigned long long)d;
-      head += nb;
-      const uint32_t incl = wave_incl_scan(ng, lane);
-      const uint32_t excl = incl - ng;
-      const uint32_t total = __shfl(incl, kWave - 1);
-      bool lhit = false, lbad = false;
-      for (uint32_t base = 0; base < total; base += kWave) {
-        const uint32_t item = base + (uint32_t)lane;
-        // owner = number of lanes whose inclusive count is <= item
-        int owner = 0;
-#pragma unroll
-        for (int step = kWave / 2; step > 0; step >>= 1) {
-          const uint32_t c = __shfl(incl, owner + step - 1);
-          if (c <= item) owner += step;
+      r.cur = base;
+      r.end = min(base + r.chunk, total);
+    }
+    const unsigned long long avail = r.end - r.cur;
+    const unsigned long long rank = (unsigned long long)__popcll(wmask & below_leader);
+    if (want && rank < avail) {
+      item = r.cur + rank;
+      got = true;
+      want = false;
+    }
+    const unsigned long long nw = (unsigned long long)__popcll(wmask);
+    r.cur += nw < avail ? nw : avail;
+    wmask = __ballot(want && is_leader);
+  }
+  return got;
+}
+
+// ------------------------------------------------------------------------
+// IC, tiers 0 and 1: S lanes per set.
+// ------------------------------------------------------------------------
+template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX>
+__global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
+  constexpr int H = 1 << HLOG;
+  constexpr int NSEG = kSegThreads / S;
+  __shared__ int32_t s_q[NSEG][Q];
+  __shared__ uint32_t s_h[NSEG][H];
+  __shared__ uint32_t s_tail[NSEG];
+  const int lane = threadIdx.x % kWave;
+  const int sl = threadIdx.x % S;       // lane within the segment
+  const int seg = threadIdx.x / S;      // segment within the block
+  const int sw = lane / S;              // segment within the wavefront
+  const int leader = sw * S;            // wavefront lane of the segment's first lane
+  const bool is_leader = sl == 0;
+  const uint64_t below_leader = leader ? (~0ull >> (64 - leader)) : 0ull;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int32_t* q = s_q[seg];
+  uint32_t* h = s_h[seg];
+  const GraphView g = a.g;
+  const unsigned long long total = io.in_list ? list_len(a, io.in_len_ctr) : a.count;
+  Acc acc;
+  Reservoir res;
+  res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
+  unsigned long long pool_next = 0, pool_end = 0;  // wavefront's slice of the node pool
+
+  // segment state (the same in every lane of a segment)
+  bool has = false, exhausted = false, hit = false, bad = false;
+  unsigned long long rel = 0;
+  SetStream st = make_set_stream(a.seed, a.phase, a.first);
+  int head = 0;
+  uint32_t G = 0, done_items = 0, gsum = 0;  // groups of the current batch / done / of the set so far
+  // lane state: this lane's node of the current batch
+  int64_t ea = 0, d = 0;
+  uint32_t ng = 0, incl = 0;
+  unsigned long long wlane = 0;
+
+  for (;;) {
+    // ---- A: idle segments take their next set
+    {
+      unsigned long long item = 0;
+      const bool want = !has && !exhausted;
+      if (take(a, io.next_ctr, total, res, want, is_leader, below_leader, lane, exhausted, item)) {
+        rel = io.in_list ? io.in_list[item] : item;
+        st = make_set_stream(a.seed, a.phase, a.first + rel);
+        uint4* h4 = reinterpret_cast<uint4*>(h);
+        for (int i = sl; i < H / 4; i += S) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+        const int32_t root = draw_root(st, g.n);
+        wave_sync();
+        if (is_leader) {
+          q[0] = root;
+          s_tail[seg] = 1u;
+          lds_insert<HLOG>(h, (uint32_t)root);
         }
-        owner = min(owner, kWave - 1);
-        const int64_t oa = __shfl(ea, owner);
-        const int64_t od = __shfl(d, owner);
-        const uint32_t oex = __shfl(excl, owner);
-        if (item < total) {
-          const int64_t grp = (oa >> 2) + (int64_t)(item - oex);
-          const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
-          uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
-          if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
-          const uint4 x = draw(st, kKindCoin, (uint64_t)grp);
-          const int32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
-          const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
-          const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
-          const int64_t e0 = grp << 2;
-#pragma unroll
-          for (int w = 0; w < 4; ++w) {
-            const int64_t e = e0 + w;
-            if (e < oa || e >= oa + od) continue;
-            if (!edge_live<WC>(xv[w], tv[w], od)) continue;
-            const int32_t u = sv[w];
-            const int r = lds_insert(h, (uint32_t)u);
-            if (r < 0) {
-              lbad = true;
-            } else if (r == 1) {
-              const uint32_t pos = atomicAdd(&s_tail[wv], 1u);
-              if (pos < (uint32_t)kQCap) q[pos] = u;
-              else lbad = true;
-              if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+        has = true;
+        hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
+        bad = false;
+        head = 0;
+        G = 0;
+        done_items = 0;
+        gsum = 0;
+        wlane = 0;
+      }
+    }
+    if (__ballot(has) == 0) break;
+    wave_sync();
+
+    // ---- B: segments whose batch is done finish the set or load the next batch
+    bool fin = false, defer_now = false;
+    uint32_t fin_len = 0;
+    unsigned long long fin_width = 0;
+    if (has && (done_items >= G || hit || bad)) {
+      const int tail = (int)s_tail[seg];
+      if (bad || tail > Q || hit || head >= tail) {
+        fin_width = seg_sum<S>(wlane);
+        has = false;
+        if (bad || tail > Q) {
+          defer_now = true;
+        } else {
+          fin = true;
+          fin_len = (uint32_t)tail;
+          if (is_leader) {
+            if (MODE == kModeWidth) {
+              acc.kappa += kappa_fixed(fin_width, g.m, a.k);
+              acc.width += fin_width;
+              acc.nodes += fin_len;
+              if (a.widths) a.widths[rel] = fin_width;
+              if (a.sizes) a.sizes[rel] = fin_len;
+            } else if (MODE == kModeCover) {
+              acc.width += fin_width;
+              acc.nodes += fin_len;
+              if (hit) acc.covered += 1;
             }
           }
         }
+      } else {
+        const int nb = min(tail - head, S);
+        ea = 0;
+        d = 0;
+        ng = 0;
+        if (sl < nb) {
+          const int32_t v = q[head + sl];
+          ea = g.off[v];
+          const int64_t eb = g.off[v + 1];
+          d = eb - ea;
+          ng = d ? (uint32_t)(((eb - 1) >> 2) - (ea >> 2) + 1) : 0u;
+        }
+        wlane += (unsigned long long)d;
+        head += nb;
+        incl = seg_incl_scan<S>(ng, sl);
+        G = __shfl(incl, S - 1, S);
+        done_items = 0;
+        gsum += G;
+        if (gsum > (uint32_t)GMAX) {  // too wide for this tier: hand it on
+          bad = true;
+          done_items = G;
+        }
       }
-      wave_sync();
-      tail = (int)min(s_tail[wv], (uint32_t)kQCap + 1u);
-      hit = __any(lhit);
-      bad = __any(lbad);
     }
 
-    if (bad) {
-      if (lane == 0) defer(a, rel);
-    } else {
-      const unsigned long long width = wave_sum(wlane);
-      if (MODE == kModeWidth) {
-        if (lane == 0) {
-          acc.kappa += kappa_fixed(width, g.m, a.k);
-          acc.width += width;
-          acc.nodes += (unsigned long long)tail;
-          if (a.widths) a.widths[rel] = width;
-          if (a.sizes) a.sizes[rel] = (uint32_t)tail;
-        }
-      } else if (MODE == kModeEmit) {
+    // deferred sets go to the next tier's list, one atomic per wavefront
+    {
+      const bool dl = defer_now && is_leader;
+      const uint64_t dm = __ballot(dl);
+      if (dm) {
         unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)tail);
+        if (lane == 0) base = atomicAdd(&a.ctr[io.out_len_ctr], (unsigned long long)__popcll(dm));
         base = __shfl(base, 0);
-        if (base + (unsigned long long)tail <= a.pool_cap)
-          for (int i = lane; i < tail; i += kWave) a.pool[base + i] = q[i];
-        if (lane == 0) {
-          a.set_start[rel] = base;
-          a.set_len[rel] = (uint32_t)tail;
-          if (a.widths) a.widths[rel] = width;
-          acc.width += width;
-          acc.nodes += (unsigned long long)tail;
+        if (dl) {
+          const unsigned long long pos = base + (unsigned long long)__popcll(dm & below);
+          if (pos < a.count) io.out_list[pos] = rel;
         }
-      } else {
-        if (lane == 0 && hit) acc.covered += 1;
       }
     }
-    rel = __shfl(next, 0);
+
+    // stored sets: one reservation in the wavefront's pool slice per iteration
+    if (MODE == kModeEmit) {
+      const uint32_t mine = (fin && is_leader) ? fin_len : 0u;
+      const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
+      const uint32_t tot = __shfl(winc, kWave - 1);
+      if (tot) {
+        if (pool_next + tot > pool_end) {
+          const unsigned long long want_n = max(kPoolChunk, (unsigned long long)tot);
+          unsigned long long got = 0;
+          if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want_n);
+          got = __shfl(got, 0);
+          pool_next = got;
+          pool_end = got + want_n;
+        }
+        const unsigned long long my_base = pool_next + (unsigned long long)(winc - mine);
+        pool_next += tot;
+        const unsigned long long base = __shfl(my_base, leader);
+        if (fin) {
+          if (base + fin_len <= a.pool_cap)
+            for (uint32_t i = sl; i < fin_len; i += S) a.pool[base + i] = q[i];
+          if (is_leader) {
+            a.set_start[rel] = a.pool_base + base;
+            a.set_len[rel] = fin_len;
+            if (a.widths) a.widths[rel] = fin_width;
+            acc.width += fin_width;
+            acc.nodes += fin_len;
+          }
+        }
+      }
+    }
+
+    // ---- C: segments with work process S groups of their batch
+    bool lhit = false, lbad = false;
+    if (has && done_items < G) {
+      const uint32_t item = done_items + (uint32_t)sl;
+      int owner = 0;
+#pragma unroll
+      for (int step = S / 2; step > 0; step >>= 1) {
+        const uint32_t c = __shfl(incl, owner + step - 1, S);
+        if (c <= item) owner += step;
+      }
+      owner = min(owner, S - 1);
+      const int64_t oa = __shfl(ea, owner, S);
+      const int64_t od = __shfl(d, owner, S);
+      const uint32_t oex = __shfl(incl - ng, owner, S);
+      if (item < G) {
+        const int64_t grp = (oa >> 2) + (int64_t)(item - oex);
+        const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
+        uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
+        if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
+        const uint4 x = draw(st, kKindCoin, (uint64_t)grp);
+        const int32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
+        const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+        const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
+        const int64_t e0 = grp << 2;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          const int64_t e = e0 + w;
+          if (e < oa || e >= oa + od) continue;
+          if (!edge_live<WC>(xv[w], tv[w], od)) continue;
+          const int32_t u = sv[w];
+          const int r = lds_insert<HLOG>(h, (uint32_t)u);
+          if (r < 0) {
+            lbad = true;
+          } else if (r == 1) {
+            const uint32_t pos = atomicAdd(&s_tail[seg], 1u);
+            if (pos < (uint32_t)Q) q[pos] = u;
+            else lbad = true;
+            if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+          }
+        }
+      }
+      done_items += (uint32_t)S;
+    }
     wave_sync();
+    const uint64_t hm = __ballot(lhit), bm = __ballot(lbad);
+    hit = hit || seg_bits<S>(hm, sw) != 0ull;
+    bad = bad || seg_bits<S>(bm, sw) != 0ull;
   }
-  if (lane == 0) flush(a, acc);
+  wave_flush(a, acc, io.acc, lane);
 }
 
 // ------------------------------------------------------------------------
-// LT, lane-level pass: one chain per lane.
+// LT, tier 0: one chain per lane.
 // ------------------------------------------------------------------------
 __device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
 
 template <int MODE>
-__global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a) {
+__global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, TierIO io) {
   __shared__ int32_t s_chain[kLtWaves][kChain][kWave];
   const int wv = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
   int32_t(*chain)[kWave] = s_chain[wv];
   const GraphView g = a.g;
-  const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   Acc acc;
+  Reservoir res;
+  res.chunk = chunk_for(a.count, kLtWaves, kWave);
+  unsigned long long pool_next = 0, pool_end = 0;
 
   bool active = false, exhausted = false, hit = false;
   unsigned long long rel = 0, width = 0;
@@ -293,103 +458,125 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a) 
   uint64_t sig = 0;
   SetStream st = make_set_stream(a.seed, a.phase, a.first);
   for (;;) {
-    const bool want = !active && !exhausted;
-    const uint64_t wmask = __ballot(want);
-    if (wmask) {
-      const int leader = __ffsll((unsigned long long)wmask) - 1;
-      unsigned long long base = 0;
-      if (lane == leader) base = atomicAdd(&a.ctr[kCtrNextSet], (unsigned long long)__popcll(wmask));
-      base = __shfl(base, leader);
-      if (want) {
-        rel = base + (unsigned long long)__popcll(wmask & below);
-        if (rel >= a.count) {
-          exhausted = true;
-        } else {
-          st = make_set_stream(a.seed, a.phase, a.first + rel);
-          v = draw_root(st, g.n);
-          chain[0][lane] = v;
-          len = 1;
-          width = 0;
-          sig = sig_bit(v);
-          hit = (MODE == kModeCover) && in_seed(a.seed_bits, v);
-          active = true;
-        }
+    {
+      unsigned long long item = 0;
+      if (take(a, io.next_ctr, a.count, res, !active && !exhausted, true, below, lane, exhausted, item)) {
+        rel = item;
+        st = make_set_stream(a.seed, a.phase, a.first + rel);
+        v = draw_root(st, g.n);
+        chain[0][lane] = v;
+        len = 1;
+        width = 0;
+        sig = sig_bit(v);
+        hit = (MODE == kModeCover) && in_seed(a.seed_bits, v);
+        active = true;
       }
     }
     if (__ballot(active) == 0) break;
-    if (!active) continue;
-    bool done = hit, bad = false;
-    if (!done) {
-      const int64_t ea = g.off[v];
-      const int64_t d = g.off[v + 1] - ea;
-      width += (unsigned long long)d;
-      if (d == 0) {
-        done = true;
-      } else {
-        const uint64_t j = scale64(draw(st, kKindPick, (uint64_t)v), (uint64_t)d);
-        const int32_t u = g.src[ea + (int64_t)j];
-        const uint64_t bit = sig_bit(u);
-        bool seen = false;
-        if (sig & bit) {
-          for (int i = 0; i < len; ++i) {
-            if (chain[i][lane] == u) { seen = true; break; }
-          }
-        }
-        if (seen) {
-          done = true;
-        } else if (len == kChain) {
-          bad = true;
+    bool done = false, bad = false;
+    if (active) {
+      done = hit;
+      if (!done) {
+        const int64_t ea = g.off[v];
+        const int64_t d = g.off[v + 1] - ea;
+        width += (unsigned long long)d;
+        if (d == 0) {
           done = true;
         } else {
-          chain[len][lane] = u;
-          ++len;
-          sig |= bit;
-          v = u;
-          if (MODE == kModeCover && in_seed(a.seed_bits, u)) {
-            hit = true;
-            done = true;
+          const uint64_t j = scale64(draw(st, kKindPick, (uint64_t)v), (uint64_t)d);
+          const int32_t u = g.src[ea + (int64_t)j];
+          const uint64_t bit = sig_bit(u);
+          bool seen = false;
+          if (sig & bit) {
+            for (int i = 0; i < len; ++i) {
+              if (chain[i][lane] == u) {
+                seen = true;
+                break;
+              }
+            }
           }
+          if (seen) {
+            done = true;
+          } else if (len == kChain) {
+            bad = true;
+            done = true;
+          } else {
+            chain[len][lane] = u;
+            ++len;
+            sig |= bit;
+            v = u;
+            if (MODE == kModeCover && in_seed(a.seed_bits, u)) {
+              hit = true;
+              done = true;
+            }
+          }
+        }
+      }
+    }
+    const bool fin = done && !bad;
+    {
+      const uint64_t dm = __ballot(bad);
+      if (dm) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&a.ctr[io.out_len_ctr], (unsigned long long)__popcll(dm));
+        base = __shfl(base, 0);
+        if (bad) {
+          const unsigned long long pos = base + (unsigned long long)__popcll(dm & below);
+          if (pos < a.count) io.out_list[pos] = rel;
+        }
+      }
+    }
+    if (MODE == kModeEmit) {
+      const uint32_t mine = fin ? (uint32_t)len : 0u;
+      const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
+      const uint32_t tot = __shfl(winc, kWave - 1);
+      if (tot) {
+        if (pool_next + tot > pool_end) {
+          const unsigned long long want_n = max(kPoolChunk, (unsigned long long)tot);
+          unsigned long long got = 0;
+          if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want_n);
+          got = __shfl(got, 0);
+          pool_next = got;
+          pool_end = got + want_n;
+        }
+        const unsigned long long base = pool_next + (unsigned long long)(winc - mine);
+        pool_next += tot;
+        if (fin) {
+          if (base + (unsigned long long)len <= a.pool_cap)
+            for (int i = 0; i < len; ++i) a.pool[base + i] = chain[i][lane];
+          a.set_start[rel] = a.pool_base + base;
+          a.set_len[rel] = (uint32_t)len;
+          if (a.widths) a.widths[rel] = width;
+          acc.width += width;
+          acc.nodes += (unsigned long long)len;
         }
       }
     }
     if (done) {
       active = false;
-      if (bad) {
-        defer(a, rel);
-      } else if (MODE == kModeWidth) {
+      if (fin && MODE == kModeWidth) {
         acc.kappa += kappa_fixed(width, g.m, a.k);
         acc.width += width;
         acc.nodes += (unsigned long long)len;
         if (a.widths) a.widths[rel] = width;
         if (a.sizes) a.sizes[rel] = (uint32_t)len;
-      } else if (MODE == kModeEmit) {
-        const unsigned long long base = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)len);
-        if (base + (unsigned long long)len <= a.pool_cap)
-          for (int i = 0; i < len; ++i) a.pool[base + i] = chain[i][lane];
-        a.set_start[rel] = base;
-        a.set_len[rel] = (uint32_t)len;
-        if (a.widths) a.widths[rel] = width;
+      } else if (fin && MODE == kModeCover) {
         acc.width += width;
         acc.nodes += (unsigned long long)len;
-      } else if (hit) {
-        acc.covered += 1;
+        if (hit) acc.covered += 1;
       }
     }
   }
-  flush(a, acc);
+  wave_flush(a, acc, io.acc, lane);
 }
 
 // ------------------------------------------------------------------------
-// Large-set pass.
+// Last tier.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ unsigned long long deferred_count(const SampleArgs& a) {
-  const unsigned long long d = a.ctr[kCtrDeferred];
-  return d < a.deferred_cap ? d : a.deferred_cap;
-}
 
 // IC: one 256-thread block per set, visited stamps and queue in device memory.
 template <int MODE, bool WC>
-__global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a) {
+__global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierIO io) {
   constexpr int T = kBigThreads;
   __shared__ uint32_t s_incl[T];
   __shared__ int64_t s_ea[T];
@@ -405,12 +592,12 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a) {
   const int slot = blockIdx.x;
   uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)g.n;
   int32_t* queue = a.big_queue + (size_t)slot * (size_t)g.n;
-  const unsigned long long ndef = deferred_count(a);
+  const unsigned long long ndef = list_len(a, io.in_len_ctr);
   Acc acc;
 
   for (;;) {
     if (tid == 0) {
-      s_idx = atomicAdd(&a.ctr[kCtrNextBig], 1ull);
+      s_idx = atomicAdd(&a.ctr[io.next_ctr], 1ull);
       s_epoch = a.big_epoch[slot] + 1u;
     }
     __syncthreads();
@@ -421,7 +608,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a) {
       for (int64_t i = tid; i < g.n; i += T) stamp[i] = 0u;
       epoch = 1u;
     }
-    const unsigned long long rel = a.deferred[idx];
+    const unsigned long long rel = io.in_list[idx];
     const SetStream st = make_set_stream(a.seed, a.phase, a.first + rel);
     const int32_t root = draw_root(st, g.n);
     __syncthreads();
@@ -449,7 +636,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a) {
         ng = d ? (uint32_t)(((eb - 1) >> 2) - (ea >> 2) + 1) : 0u;
       }
       wloc += (unsigned long long)d;
-      uint32_t incl = wave_incl_scan(ng, lane);
+      uint32_t incl = seg_incl_scan<kWave>(ng, lane);
       if (lane == kWave - 1) s_wtot[wv] = incl;
       __syncthreads();
       uint32_t carry = 0;
@@ -497,7 +684,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a) {
       }
       __syncthreads();
     }
-    const unsigned long long wsum_w = wave_sum(wloc);
+    const unsigned long long wsum_w = seg_sum<kWave>(wloc);
     if (lane == 0) s_red[wv] = wsum_w;
     __syncthreads();
     const uint32_t len = s_tail;
@@ -507,7 +694,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a) {
         for (int w = 0; w < T / kWave; ++w) width += s_red[w];
         const unsigned long long b = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)len);
         s_base = b;
-        a.set_start[rel] = b;
+        a.set_start[rel] = a.pool_base + b;
         a.set_len[rel] = len;
         if (a.widths) a.widths[rel] = width;
         acc.width += width;
@@ -526,34 +713,36 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a) {
         acc.nodes += len;
         if (a.widths) a.widths[rel] = width;
         if (a.sizes) a.sizes[rel] = len;
-      } else if (s_hit) {
-        acc.covered += 1;
+      } else {
+        acc.width += width;
+        acc.nodes += len;
+        if (s_hit) acc.covered += 1;
       }
     }
     __syncthreads();
   }
-  if (tid == 0) flush(a, acc);
+  if (tid == 0) block_flush(a, acc, io.acc);
 }
 
 // LT: one lane per set, visited stamps and chain in device memory.
 template <int MODE>
-__global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a) {
+__global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) {
   const int slot = blockIdx.x * kWave + threadIdx.x;
   if (slot >= a.big_slots) return;
   const GraphView g = a.g;
   uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)g.n;
   int32_t* chain = a.big_queue + (size_t)slot * (size_t)g.n;
-  const unsigned long long ndef = deferred_count(a);
+  const unsigned long long ndef = list_len(a, io.in_len_ctr);
   uint32_t epoch = a.big_epoch[slot];
   Acc acc;
   for (;;) {
-    const unsigned long long idx = atomicAdd(&a.ctr[kCtrNextBig], 1ull);
+    const unsigned long long idx = atomicAdd(&a.ctr[io.next_ctr], 1ull);
     if (idx >= ndef) break;
     if (++epoch == 0u) {
       for (int64_t i = 0; i < g.n; ++i) stamp[i] = 0u;
       epoch = 1u;
     }
-    const unsigned long long rel = a.deferred[idx];
+    const unsigned long long rel = io.in_list[idx];
     const SetStream st = make_set_stream(a.seed, a.phase, a.first + rel);
     int32_t v = draw_root(st, g.n);
     stamp[v] = epoch;
@@ -584,21 +773,23 @@ __global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a) {
       const unsigned long long b = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)len);
       if (b + (unsigned long long)len <= a.pool_cap)
         for (int64_t i = 0; i < len; ++i) a.pool[b + i] = chain[i];
-      a.set_start[rel] = b;
+      a.set_start[rel] = a.pool_base + b;
       a.set_len[rel] = (uint32_t)len;
       if (a.widths) a.widths[rel] = width;
       acc.width += width;
       acc.nodes += (unsigned long long)len;
-    } else if (hit) {
-      acc.covered += 1;
+    } else {
+      acc.width += width;
+      acc.nodes += (unsigned long long)len;
+      if (hit) acc.covered += 1;
     }
   }
   a.big_epoch[slot] = epoch;
-  flush(a, acc);
+  block_flush(a, acc, io.acc);
 }
 
 __global__ void clear_counters_kernel(unsigned long long* ctr) {
-  if (threadIdx.x < kCtrCount) ctr[threadIdx.x] = 0ull;
+  for (int i = threadIdx.x; i < kCtrCount; i += blockDim.x) ctr[i] = 0ull;
 }
 
 template <typename K>
@@ -608,20 +799,101 @@ int blocks_per_cu(K kernel, int threads) {
   return nb;
 }
 
+// Segment shapes: S lanes per set, Q nodes and 2Q hash slots in LDS per set,
+// and at most GMAX 4-edge groups per set (32 iterations' worth in tier 0,
+// 64 in tier 1) so that wide sets, which contain a hub's long in-list, move
+// on to a tier with more lanes per set instead of forming a long tail.
+template <int MODE, bool WC, int S>
+struct SegKernel;
+template <int MODE, bool WC>
+struct SegKernel<MODE, WC, 8> {
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 8, 64, 7, 32 * 8>;
+};
+template <int MODE, bool WC>
+struct SegKernel<MODE, WC, 16> {
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 16, 128, 8, 32 * 16>;
+};
+template <int MODE, bool WC>
+struct SegKernel<MODE, WC, 32> {
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 32, 256, 9, 32 * 32>;
+};
+template <int MODE, bool WC>
+struct SegKernel<MODE, WC, 64> {
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 32 * 64>;
+};
+// tier 1: one set per wavefront
+template <int MODE, bool WC>
+struct Tier1Kernel {
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 64 * 64>;
+};
+
+template <int MODE, bool WC>
+void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, hipEvent_t after0) {
+  const dim3 blk(kSegThreads);
+  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
+  const TierIO t1 = {a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1};
+  const TierIO t2 = {a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2};
+  switch (S) {
+    case 8: hipLaunchKernelGGL((SegKernel<MODE, WC, 8>::fn), dim3(grid0), blk, 0, s, a, t0); break;
+    case 16: hipLaunchKernelGGL((SegKernel<MODE, WC, 16>::fn), dim3(grid0), blk, 0, s, a, t0); break;
+    case 32: hipLaunchKernelGGL((SegKernel<MODE, WC, 32>::fn), dim3(grid0), blk, 0, s, a, t0); break;
+    default: hipLaunchKernelGGL((SegKernel<MODE, WC, 64>::fn), dim3(grid0), blk, 0, s, a, t0); break;
+  }
+  if (after0) (void)hipEventRecord(after0, s);
+  hipLaunchKernelGGL((Tier1Kernel<MODE, WC>::fn), dim3(grid1), blk, 0, s, a, t1);
+  hipLaunchKernelGGL((ic_big_kernel<MODE, WC>), dim3(a.big_slots), dim3(kBigThreads), 0, s, a, t2);
+}
+
+template <int MODE>
+void launch_lt(const SampleArgs& a, int grid0, hipStream_t s, hipEvent_t after0) {
+  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
+  const TierIO t2 = {a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2};
+  hipLaunchKernelGGL((lt_lane_kernel<MODE>), dim3(grid0), dim3(kLtWaves * kWave), 0, s, a, t0);
+  if (after0) (void)hipEventRecord(after0, s);
+  hipLaunchKernelGGL((lt_big_kernel<MODE>), dim3((a.big_slots + kWave - 1) / kWave), dim3(kWave), 0, s, a, t2);
+}
+
+template <int MODE, bool WC>
+int ic_occupancy(int S) {
+  switch (S) {
+    case 8: return blocks_per_cu((SegKernel<MODE, WC, 8>::fn), kSegThreads);
+    case 16: return blocks_per_cu((SegKernel<MODE, WC, 16>::fn), kSegThreads);
+    case 32: return blocks_per_cu((SegKernel<MODE, WC, 32>::fn), kSegThreads);
+    default: return blocks_per_cu((SegKernel<MODE, WC, 64>::fn), kSegThreads);
+  }
+}
+
 }  // namespace
 
 void launch_clear_counters(unsigned long long* ctr, hipStream_t s) {
   hipLaunchKernelGGL(clear_counters_kernel, dim3(1), dim3(64), 0, s, ctr);
 }
 
-int ic_wave_blocks_per_cu(int mode, bool wc) {
+int ic_seg_lanes() {
+  const char* e = getenv("TIM_IC_SEG_LANES");
+  const int v = e ? atoi(e) : 8;
+  return (v == 8 || v == 16 || v == 32 || v == 64) ? v : 8;
+}
+
+int ic_tier1_blocks_per_cu(int mode, bool wc) {
   switch (mode * 2 + (wc ? 1 : 0)) {
-    case 0: return blocks_per_cu(ic_wave_kernel<kModeWidth, false>, kIcWaves * kWave);
-    case 1: return blocks_per_cu(ic_wave_kernel<kModeWidth, true>, kIcWaves * kWave);
-    case 2: return blocks_per_cu(ic_wave_kernel<kModeEmit, false>, kIcWaves * kWave);
-    case 3: return blocks_per_cu(ic_wave_kernel<kModeEmit, true>, kIcWaves * kWave);
-    case 4: return blocks_per_cu(ic_wave_kernel<kModeCover, false>, kIcWaves * kWave);
-    default: return blocks_per_cu(ic_wave_kernel<kModeCover, true>, kIcWaves * kWave);
+    case 0: return blocks_per_cu((Tier1Kernel<kModeWidth, false>::fn), kSegThreads);
+    case 1: return blocks_per_cu((Tier1Kernel<kModeWidth, true>::fn), kSegThreads);
+    case 2: return blocks_per_cu((Tier1Kernel<kModeEmit, false>::fn), kSegThreads);
+    case 3: return blocks_per_cu((Tier1Kernel<kModeEmit, true>::fn), kSegThreads);
+    case 4: return blocks_per_cu((Tier1Kernel<kModeCover, false>::fn), kSegThreads);
+    default: return blocks_per_cu((Tier1Kernel<kModeCover, true>::fn), kSegThreads);
+  }
+}
+
+int ic_blocks_per_cu(int mode, bool wc, int S) {
+  switch (mode * 2 + (wc ? 1 : 0)) {
+    case 0: return ic_occupancy<kModeWidth, false>(S);
+    case 1: return ic_occupancy<kModeWidth, true>(S);
+    case 2: return ic_occupancy<kModeEmit, false>(S);
+    case 3: return ic_occupancy<kModeEmit, true>(S);
+    case 4: return ic_occupancy<kModeCover, false>(S);
+    default: return ic_occupancy<kModeCover, true>(S);
   }
 }
 
@@ -633,46 +905,24 @@ int lt_lane_blocks_per_cu(int mode) {
   }
 }
 
-void launch_sample(int model, int mode, const SampleArgs& a, int grid, hipStream_t s) {
+void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int grid0, int grid1, hipStream_t s,
+                   hipEvent_t after_tier0) {
   if (model == 0) {
-    const dim3 blk(kIcWaves * kWave);
+    const int S = seg_lanes;
     const bool wc = a.g.thr == nullptr;
     switch (mode * 2 + (wc ? 1 : 0)) {
-      case 0: hipLaunchKernelGGL((ic_wave_kernel<kModeWidth, false>), dim3(grid), blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((ic_wave_kernel<kModeWidth, true>), dim3(grid), blk, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((ic_wave_kernel<kModeEmit, false>), dim3(grid), blk, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((ic_wave_kernel<kModeEmit, true>), dim3(grid), blk, 0, s, a); break;
-      case 4: hipLaunchKernelGGL((ic_wave_kernel<kModeCover, false>), dim3(grid), blk, 0, s, a); break;
-      default: hipLaunchKernelGGL((ic_wave_kernel<kModeCover, true>), dim3(grid), blk, 0, s, a); break;
+      case 0: launch_ic<kModeWidth, false>(a, S, grid0, grid1, s, after_tier0); break;
+      case 1: launch_ic<kModeWidth, true>(a, S, grid0, grid1, s, after_tier0); break;
+      case 2: launch_ic<kModeEmit, false>(a, S, grid0, grid1, s, after_tier0); break;
+      case 3: launch_ic<kModeEmit, true>(a, S, grid0, grid1, s, after_tier0); break;
+      case 4: launch_ic<kModeCover, false>(a, S, grid0, grid1, s, after_tier0); break;
+      default: launch_ic<kModeCover, true>(a, S, grid0, grid1, s, after_tier0); break;
     }
   } else {
-    const dim3 blk(kLtWaves * kWave);
     switch (mode) {
-      case 0: hipLaunchKernelGGL((lt_lane_kernel<kModeWidth>), dim3(grid), blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((lt_lane_kernel<kModeEmit>), dim3(grid), blk, 0, s, a); break;
-      default: hipLaunchKernelGGL((lt_lane_kernel<kModeCover>), dim3(grid), blk, 0, s, a); break;
-    }
-  }
-}
-
-void launch_sample_large(int model, int mode, const SampleArgs& a, hipStream_t s) {
-  if (model == 0) {
-    const dim3 grid(a.big_slots), blk(kBigThreads);
-    const bool wc = a.g.thr == nullptr;
-    switch (mode * 2 + (wc ? 1 : 0)) {
-      case 0: hipLaunchKernelGGL((ic_big_kernel<kModeWidth, false>), grid, blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((ic_big_kernel<kModeWidth, true>), grid, blk, 0, s, a); break;
-      case 2: hipLaunchKernelGGL((ic_big_kernel<kModeEmit, false>), grid, blk, 0, s, a); break;
-      case 3: hipLaunchKernelGGL((ic_big_kernel<kModeEmit, true>), grid, blk, 0, s, a); break;
-      case 4: hipLaunchKernelGGL((ic_big_kernel<kModeCover, false>), grid, blk, 0, s, a); break;
-      default: hipLaunchKernelGGL((ic_big_kernel<kModeCover, true>), grid, blk, 0, s, a); break;
-    }
-  } else {
-    const dim3 grid((a.big_slots + kWave - 1) / kWave), blk(kWave);
-    switch (mode) {
-      case 0: hipLaunchKernelGGL((lt_big_kernel<kModeWidth>), grid, blk, 0, s, a); break;
-      case 1: hipLaunchKernelGGL((lt_big_kernel<kModeEmit>), grid, blk, 0, s, a); break;
-      default: hipLaunchKernelGGL((lt_big_kernel<kModeCover>), grid, blk, 0, s, a); break;
+      case 0: launch_lt<kModeWidth>(a, grid0, s, after_tier0); break;
+      case 1: launch_lt<kModeEmit>(a, grid0, s, after_tier0); break;
+      default: launch_lt<kModeCover>(a, grid0, s, after_tier0); break;
     }
   }
 }

@@ -336,3 +336,36 @@ def test_budget_too_small_is_reported(cfg1):
         with pytest.raises(tim.TimError) as ei:
             e.run(dg, IC, 10, 0.5, 1.0, 1)
         assert ei.value.status == tim.EBUDGET
+
+
+def test_max_coverage_large_tiles_overflow_lds_tables(eng):
+    # tiles with more distinct nodes than the LDS aggregation tables hold, and
+    # a few heavy nodes present in most sets (the hub pattern of RR sets)
+    import torch
+    rng = np.random.default_rng(11)
+    n, nsets = 200_000, 3000
+    hubs = np.arange(5)
+    sets = []
+    for _ in range(nsets):
+        size = int(rng.integers(1, 400))
+        body = rng.choice(n - 5, size=size, replace=False) + 5
+        h = hubs[rng.random(5) < 0.6]
+        sets.append(np.concatenate([h, body]))
+    off = np.zeros(nsets + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(s) for s in sets])
+    nodes = np.concatenate(sets).astype(np.int32)
+    for k in (1, 7, 40):
+        seeds, gains = eng.max_coverage(n, _dev(off, torch.int64), _dev(nodes, torch.int32), k)
+        ws, wg = oracle.greedy(n, off, nodes, k)
+        assert np.array_equal(seeds, ws) and np.array_equal(gains, wg), k
+
+
+@pytest.mark.parametrize("lanes", ["16", "32", "64"])
+def test_segment_width_does_not_change_results(cfg1, cfg2, lanes, monkeypatch):
+    # the IC tier-0 kernel's lanes per set is a launch-shape choice only
+    import paper_1404_0900_amd as tim
+    monkeypatch.setenv("TIM_IC_SEG_LANES", lanes)
+    with tim.Engine(0) as e:
+        _check_sets(e, cfg1, IC, 1, 64, 0, 20000)
+        _check_sets(e, cfg2, IC, 2, 64, 5, 5000)
+        _run_equal(e, cfg1, e.upload(cfg1), IC, 50, 0.5, 1.0, 1)
