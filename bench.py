@@ -22,10 +22,28 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
+import hashlib
+
 KS = (1, 10, 50)
 EPS, ELL, SEED = 0.2, 1.0, 2
 HBM_PEAK_GBS = 8000.0
 MODES = ("widths", "store", "cover")
+# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# WRITE_SIZE runs of this benchmark (scaled by a plain-copy calibration; see
+# profiles/ic_seg_kernel_chunglu_n1e6_m1e7.md).  Valid only for the kernel
+# sources they were taken on.
+TRAFFIC = {"kernel": "ic_seg_kernel<0, true, 8, 128, 0, 256> (widths)", "sources_sha256_16": "becfcd9cfdcd9bc9",
+           "fetch_bytes": 554121180, "write_bytes": 16698417}
+KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
+                  "paper_1404_0900_amd/csrc/engine.hpp")
+
+
+def sources_sha():
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def kernel_name(model, mode):
@@ -33,10 +51,11 @@ def kernel_name(model, mode):
     if model == 1:
         return f"lt_lane_kernel<{mode}> ({MODES[mode]})"
     lanes = int(os.environ.get("TIM_IC_SEG_LANES", "8"))
-    lanes = lanes if lanes in (8, 16, 32, 64) else 8
-    q = {8: 64, 16: 128, 32: 256, 64: 512}[lanes]
-    hlog = {8: 7, 16: 8, 32: 9, 64: 10}[lanes]
-    return f"ic_seg_kernel<{mode}, true, {lanes}, {q}, {hlog}> ({MODES[mode]})"
+    lanes = lanes if lanes in (4, 8, 16, 32, 64) else 8
+    q = {4: 64, 8: 128, 16: 128, 32: 256, 64: 512}[lanes]
+    hlog = {4: 0, 8: 0, 16: 8, 32: 9, 64: 10}[lanes]
+    gmax = {4: 256, 8: 256, 16: 512, 32: 1024, 64: 2048}[lanes]
+    return f"ic_seg_kernel<{mode}, true, {lanes}, {q}, {hlog}, {gmax}> ({MODES[mode]})"
 
 
 def log(msg):
@@ -103,10 +122,13 @@ def main():
                 best = (model, mode, kp)
     model, mode, kp = best
     achieved = kp.bytes / (kp.kernel_ms * 1e-3) / 1e9
+    traffic = None
+    if kernel_name(model, mode) == TRAFFIC["kernel"] and sources_sha() == TRAFFIC["sources_sha256_16"]:
+        traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
     sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
     roofline = {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": None,
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
         "kernel": kernel_name(model, mode), "launches": int(kp.launches),
         "avg_launch_us": round(kp.kernel_ms * 1e3 / kp.launches, 3),
         "bytes_per_launch": int(kp.bytes // kp.launches),

@@ -35,7 +35,7 @@
  *   - All GPU work is ordered on the context's stream; every call returns
  *     after that work has finished (results are final on return).
  *   - One context per host thread; calls on one context must not overlap.
- *   - Node ids are int32 (n < 2^31), CSR offsets int64.
+ *   - Node ids are int32 (n < 2^31), CSR offsets int64 (m < 2^32).
  */
 #ifndef TIM_H_
 #define TIM_H_
@@ -189,7 +189,8 @@ tim_status tim_profile_read(const tim_ctx *ctx, tim_profile *out);
  *   ic_thr  host uint32[m] or NULL: IC threshold t(e) = floor(p(e)*2^32) - 1 of
  *           each edge (p(e) = (t+1)/2^32).  NULL selects the weighted cascade
  *           p(e) = 1/indeg(dst) of Section 7.1.  LT ignores it.
- * Requires 2 <= n < 2^31, 1 <= m.  TIM_EINVAL names the first violation. */
+ * Requires 2 <= n < 2^31 and 1 <= m <= 2^32 - 16 (edge positions are 32-bit
+ * inside the kernels).  TIM_EINVAL names the first violation. */
 tim_status tim_graph_upload(tim_ctx *ctx, int64_t n, int64_t m, const int64_t *in_off, const int32_t *in_src,
                             const uint32_t *ic_thr, tim_graph **out);
 void tim_graph_free(tim_graph *g);

@@ -75,7 +75,7 @@ struct tim_ctx {
   int grid_lt[3] = {};
   unsigned long long* ctr = nullptr;       // device counters of the current launch
   unsigned long long* ctr_host = nullptr;  // pinned mirror
-  DevBuf list1, list2, pool, set_start, set_len;
+  DevBuf list1, list2, wbuf, pool, set_start, set_len;
   DevBuf big_stamp, big_queue, big_epoch;
   int big_slots = 0;
   int64_t big_n = -1;
@@ -214,6 +214,10 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   a.ctr = c->ctr;
   a.widths = widths;
   a.sizes = sizes;
+  if (mode == tim::kModeWidth) {
+    TIM_TRY(ensure(c, c->wbuf, count * 4, "width buffer"));
+    a.wbuf = c->wbuf.as<uint32_t>();
+  }
   if (mode == tim::kModeEmit) {
     const uint64_t cap = c->pool.bytes / 4;
     a.pool = c->pool.as<int32_t>() + std::min(pool_base, cap);
@@ -593,7 +597,7 @@ void tim_ctx_destroy(tim_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
-  DevBuf* bufs[] = {&c->list1, &c->list2, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
+  DevBuf* bufs[] = {&c->list1, &c->list2, &c->wbuf, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
                     &c->rr_off, &c->rr_nodes, &c->sizes, &c->cnt, &c->fill, &c->inv_off, &c->inv_sets, &c->covered,
                     &c->selected, &c->best, &c->scan_tmp, &c->seed_bits};
   for (DevBuf* b : bufs) release(c, *b);
@@ -627,7 +631,7 @@ tim_status tim_graph_upload(tim_ctx* c, int64_t n, int64_t m, const int64_t* in_
   if (!c || !out || !in_off || !in_src) return fail(TIM_EINVAL, "null argument");
   *out = nullptr;
   if (n < 2 || n > 0x7FFFFFFFLL) return fail(TIM_EINVAL, "n=%lld outside [2, 2^31)", (long long)n);
-  if (m < 1 || m >= (1LL << 33)) return fail(TIM_EINVAL, "m=%lld outside [1, 2^33)", (long long)m);
+  if (m < 1 || m > 0xFFFFFFF0LL) return fail(TIM_EINVAL, "m=%lld outside [1, 2^32 - 16]", (long long)m);
   if (in_off[0] != 0 || in_off[n] != m) return fail(TIM_EINVAL, "in_off[0] must be 0 and in_off[n] must be m");
   for (int64_t v = 0; v < n; ++v) {
     if (in_off[v + 1] < in_off[v]) return fail(TIM_EINVAL, "in_off decreases at node %lld", (long long)v);

@@ -64,8 +64,9 @@ struct SampleArgs {
   uint64_t first, count;
   int k;                          // kappa exponent (width mode)
   unsigned long long* ctr;        // kCtrCount counters
-  uint64_t* widths;               // per set, nullable
+  uint64_t* widths;               // per set, nullable (store mode; width mode: copied from wbuf)
   uint32_t* sizes;                // per set, nullable
+  uint32_t* wbuf;                 // width mode: w(R) of every set of the launch
   int32_t* pool;                  // emit: this launch's part of the node pool
   uint64_t pool_cap;              // entries in it
   uint64_t pool_base;             // its offset in the whole pool (added to set_start)
@@ -83,7 +84,7 @@ struct SampleArgs {
 
 // ---- sample.hip ----
 void launch_clear_counters(unsigned long long* ctr, hipStream_t s);
-// Lanes per set of the IC tier-0 kernel: 8, 16, 32 or 64 (environment
+// Lanes per set of the IC tier-0 kernel: 4, 8, 16, 32 or 64 (environment
 // variable TIM_IC_SEG_LANES, read when a context is created; default 8).
 int ic_seg_lanes();
 int ic_blocks_per_cu(int mode, bool wc, int seg_lanes);

@@ -28,27 +28,36 @@ __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
   return c;
 }
 
+// The key: the same for every set of a launch (kept in scalar registers).
+struct Key {
+  uint32_t k0, k1;
+};
+
+__device__ __forceinline__ Key make_key(uint64_t seed) {
+  Key k;
+  k.k0 = (uint32_t)seed;
+  k.k1 = (uint32_t)(seed >> 32);
+  return k;
+}
+
 // The part of a counter that is fixed for one RR set.
 struct SetStream {
-  uint32_t k0, k1;      // key
   uint32_t phase_bits;  // phase << 24
   uint32_t s_lo, s_hi;  // set id
 };
 
-__device__ __forceinline__ SetStream make_set_stream(uint64_t seed, uint32_t phase, uint64_t set) {
+__device__ __forceinline__ SetStream make_set_stream(uint32_t phase, uint64_t set) {
   SetStream st;
-  st.k0 = (uint32_t)seed;
-  st.k1 = (uint32_t)(seed >> 32);
   st.phase_bits = phase << 24;
   st.s_lo = (uint32_t)set;
   st.s_hi = (uint32_t)(set >> 32);
   return st;
 }
 
-__device__ __forceinline__ uint4 draw(const SetStream& st, uint32_t kind, uint64_t idx) {
+__device__ __forceinline__ uint4 draw(const Key& key, const SetStream& st, uint32_t kind, uint64_t idx) {
   const uint4 c = make_uint4((uint32_t)idx, st.phase_bits | (kind << 16) | ((uint32_t)(idx >> 32) & 0xFFFFu),
                              st.s_lo, st.s_hi);
-  return philox10(c, st.k0, st.k1);
+  return philox10(c, key.k0, key.k1);
 }
 
 // floor(X64 * r / 2^64) with X64 = word1:word0 — a uniform index in [0, r).
@@ -58,8 +67,8 @@ __device__ __forceinline__ uint64_t scale64(uint4 x, uint64_t r) {
 }
 
 // Uniform root of the set (Definition 2).
-__device__ __forceinline__ int32_t draw_root(const SetStream& st, int64_t n) {
-  return (int32_t)scale64(draw(st, kKindRoot, 0), (uint64_t)n);
+__device__ __forceinline__ int32_t draw_root(const Key& key, const SetStream& st, int64_t n) {
+  return (int32_t)scale64(draw(key, st, kKindRoot, 0), (uint64_t)n);
 }
 
 }  // namespace tim

@@ -20,9 +20,11 @@
 // with a 64-bit membership signature in a register; longer chains go to the
 // last tier (one lane per set, stamps in device memory).
 //
-// Every launch also reduces what the phase needs: the exact 128-bit sum of
-// kappa(R) * 2^53 (Equation (8)), the widths (Equation (1)), the set sizes,
-// and the number of sets meeting a seed set (Algorithm 3, line 10).
+// Every launch also reduces what the phase needs: the widths (Equation (1)),
+// the set sizes, the number of sets meeting a seed set (Algorithm 3, line 10)
+// and, in width mode, the exact 128-bit sum of kappa(R) * 2^53 (Equation (8)),
+// computed by a separate pass over the widths so that the binary64 kappa
+// arithmetic runs one set per lane instead of inside the traversal loop.
 #include <stdlib.h>
 
 #include "engine.hpp"
@@ -215,16 +217,84 @@ __device__ __forceinline__ bool take(const SampleArgs& a, int next_ctr, unsigned
   return got;
 }
 
+// Roots of the sets a wavefront hands out, drawn 64 at a time: lane j holds
+// the root (and set id) of reservoir item base + j, so one Philox call per lane
+// serves 64 sets instead of one call per set issued across the wavefront.
+struct RootBuffer {
+  unsigned long long base = ~0ull;
+  unsigned long long rel = 0;  // lane j: relative set id of item base + j
+  int32_t root = 0;            // lane j: its root
+};
+
+__device__ __forceinline__ void fill_roots(const SampleArgs& a, const TierIO& io, unsigned long long total,
+                                           unsigned long long base, RootBuffer& rb, int lane) {
+  rb.base = base;
+  const unsigned long long item = base + (unsigned long long)lane;
+  if (item < total) {
+    rb.rel = io.in_list ? io.in_list[item] : item;
+    rb.root = draw_root(make_key(a.seed), make_set_stream(a.phase, a.first + rb.rel), a.g.n);
+  }
+}
+
+// take() for the IC kernels: hands one item to every requesting segment and
+// returns its set id and root from the wavefront's root buffer.
+__device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, unsigned long long total, Reservoir& r,
+                                         RootBuffer& rb, bool want, bool is_leader, uint64_t below_leader, int lane,
+                                         bool& exhausted, unsigned long long& rel, int32_t& root) {
+  bool got = false;
+  unsigned long long item = 0;
+  uint64_t wmask = __ballot(want && is_leader);
+  while (wmask) {
+    if (r.cur >= r.end) {
+      unsigned long long base = 0;
+      if (lane == 0) base = atomicAdd(&a.ctr[io.next_ctr], r.chunk);
+      base = __shfl(base, 0);
+      if (base >= total) {
+        if (want) exhausted = true;
+        break;
+      }
+      r.cur = base;
+      r.end = min(base + r.chunk, total);
+    }
+    const unsigned long long avail = r.end - r.cur;
+    const unsigned long long nw = (unsigned long long)__popcll(wmask);
+    const unsigned long long give = nw < avail ? nw : avail;
+    if (r.cur < rb.base || r.cur + give > rb.base + (unsigned long long)kWave) fill_roots(a, io, total, r.cur, rb, lane);
+    const unsigned long long rank = (unsigned long long)__popcll(wmask & below_leader);
+    const bool mine = want && rank < avail;
+    const int src = (int)(r.cur + rank - rb.base) & (kWave - 1);
+    const unsigned long long rel_x = __shfl(rb.rel, src);
+    const int32_t root_x = __shfl(rb.root, src);
+    if (mine) {
+      item = r.cur + rank;
+      rel = rel_x;
+      root = root_x;
+      got = true;
+      want = false;
+    }
+    r.cur += give;
+    wmask = __ballot(want && is_leader);
+  }
+  (void)item;
+  return got;
+}
+
 // ------------------------------------------------------------------------
-// IC, tiers 0 and 1: S lanes per set.
+// IC, tiers 0 and 1: S lanes per set.  Edge positions fit 32 bits (m < 2^32).
+// HLOG > 0: visited nodes are marked in an LDS hash of 2^HLOG slots and live
+// edges are inserted concurrently.  HLOG == 0: no hash; the segment takes its
+// live edges one at a time and looks each source up in its own queue (all S
+// lanes scan Q/S entries), which leaves the LDS to more sets in flight.
+// Width mode writes w(R) per set; kappa is summed by kappa_reduce_kernel.
 // ------------------------------------------------------------------------
 template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX>
 __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
-  constexpr int H = 1 << HLOG;
+  constexpr bool kHash = HLOG > 0;
+  constexpr int H = kHash ? (1 << HLOG) : 4;
   constexpr int NSEG = kSegThreads / S;
   __shared__ int32_t s_q[NSEG][Q];
-  __shared__ uint32_t s_h[NSEG][H];
-  __shared__ uint32_t s_tail[NSEG];
+  __shared__ uint32_t s_h[kHash ? NSEG : 1][H];
+  __shared__ uint32_t s_tail[kHash ? NSEG : 1];
   const int lane = threadIdx.x % kWave;
   const int sl = threadIdx.x % S;       // lane within the segment
   const int seg = threadIdx.x / S;      // segment within the block
@@ -234,42 +304,48 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
   const uint64_t below_leader = leader ? (~0ull >> (64 - leader)) : 0ull;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   int32_t* q = s_q[seg];
-  uint32_t* h = s_h[seg];
+  uint32_t* h = s_h[kHash ? seg : 0];
   const GraphView g = a.g;
+  const Key key = make_key(a.seed);
+  const uint32_t* off32 = nullptr;  // unused: offsets are read as int64 and narrowed
+  (void)off32;
   const unsigned long long total = io.in_list ? list_len(a, io.in_len_ctr) : a.count;
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
+  RootBuffer rb;
   unsigned long long pool_next = 0, pool_end = 0;  // wavefront's slice of the node pool
 
   // segment state (the same in every lane of a segment)
   bool has = false, exhausted = false, hit = false, bad = false;
   unsigned long long rel = 0;
-  SetStream st = make_set_stream(a.seed, a.phase, a.first);
-  int head = 0;
+  SetStream st = make_set_stream(a.phase, a.first);
+  int head = 0, tail_r = 0;                  // queue cursor; queue length (hash-free variant)
   uint32_t G = 0, done_items = 0, gsum = 0;  // groups of the current batch / done / of the set so far
   // lane state: this lane's node of the current batch
-  int64_t ea = 0, d = 0;
-  uint32_t ng = 0, incl = 0;
-  unsigned long long wlane = 0;
+  uint32_t ea = 0, d = 0, ng = 0, incl = 0;
+  uint32_t wlane = 0;
 
   for (;;) {
     // ---- A: idle segments take their next set
     {
-      unsigned long long item = 0;
+      int32_t root = 0;
       const bool want = !has && !exhausted;
-      if (take(a, io.next_ctr, total, res, want, is_leader, below_leader, lane, exhausted, item)) {
-        rel = io.in_list ? io.in_list[item] : item;
-        st = make_set_stream(a.seed, a.phase, a.first + rel);
-        uint4* h4 = reinterpret_cast<uint4*>(h);
-        for (int i = sl; i < H / 4; i += S) h4[i] = make_uint4(0u, 0u, 0u, 0u);
-        const int32_t root = draw_root(st, g.n);
-        wave_sync();
+      if (take_set(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
+        st = make_set_stream(a.phase, a.first + rel);
+        if (kHash) {
+          uint4* h4 = reinterpret_cast<uint4*>(h);
+          for (int i = sl; i < H / 4; i += S) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+          wave_sync();
+        }
         if (is_leader) {
           q[0] = root;
-          s_tail[seg] = 1u;
-          lds_insert<HLOG>(h, (uint32_t)root);
+          if (kHash) {
+            s_tail[seg] = 1u;
+            lds_insert<(kHash ? HLOG : 1)>(h, (uint32_t)root);
+          }
         }
+        tail_r = 1;
         has = true;
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
         bad = false;
@@ -285,12 +361,14 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
 
     // ---- B: segments whose batch is done finish the set or load the next batch
     bool fin = false, defer_now = false;
-    uint32_t fin_len = 0;
-    unsigned long long fin_width = 0;
+    uint32_t fin_len = 0, fin_width = 0;
     if (has && (done_items >= G || hit || bad)) {
-      const int tail = (int)s_tail[seg];
+      const int tail = kHash ? (int)s_tail[seg] : tail_r;
       if (bad || tail > Q || hit || head >= tail) {
-        fin_width = seg_sum<S>(wlane);
+        uint32_t w = wlane;
+#pragma unroll
+        for (int o = S / 2; o > 0; o >>= 1) w += __shfl_xor(w, o, S);
+        fin_width = w;
         has = false;
         if (bad || tail > Q) {
           defer_now = true;
@@ -299,10 +377,9 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
           fin_len = (uint32_t)tail;
           if (is_leader) {
             if (MODE == kModeWidth) {
-              acc.kappa += kappa_fixed(fin_width, g.m, a.k);
+              a.wbuf[rel] = fin_width;
               acc.width += fin_width;
               acc.nodes += fin_len;
-              if (a.widths) a.widths[rel] = fin_width;
               if (a.sizes) a.sizes[rel] = fin_len;
             } else if (MODE == kModeCover) {
               acc.width += fin_width;
@@ -318,12 +395,12 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
         ng = 0;
         if (sl < nb) {
           const int32_t v = q[head + sl];
-          ea = g.off[v];
-          const int64_t eb = g.off[v + 1];
+          ea = (uint32_t)g.off[v];
+          const uint32_t eb = (uint32_t)g.off[v + 1];
           d = eb - ea;
-          ng = d ? (uint32_t)(((eb - 1) >> 2) - (ea >> 2) + 1) : 0u;
+          ng = d ? ((eb - 1u) >> 2) - (ea >> 2) + 1u : 0u;
         }
-        wlane += (unsigned long long)d;
+        wlane += d;
         head += nb;
         incl = seg_incl_scan<S>(ng, sl);
         G = __shfl(incl, S - 1, S);
@@ -354,9 +431,10 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
     // stored sets: one reservation in the wavefront's pool slice per iteration
     if (MODE == kModeEmit) {
       const uint32_t mine = (fin && is_leader) ? fin_len : 0u;
-      const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
-      const uint32_t tot = __shfl(winc, kWave - 1);
-      if (tot) {
+      const uint64_t fm = __ballot(mine != 0u);
+      if (fm) {
+        const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
+        const uint32_t tot = __shfl(winc, kWave - 1);
         if (pool_next + tot > pool_end) {
           const unsigned long long want_n = max(kPoolChunk, (unsigned long long)tot);
           unsigned long long got = 0;
@@ -393,26 +471,36 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
         if (c <= item) owner += step;
       }
       owner = min(owner, S - 1);
-      const int64_t oa = __shfl(ea, owner, S);
-      const int64_t od = __shfl(d, owner, S);
+      const uint32_t oa = __shfl(ea, owner, S);
+      const uint32_t od = __shfl(d, owner, S);
       const uint32_t oex = __shfl(incl - ng, owner, S);
+      int32_t sv[4] = {0, 0, 0, 0};
+      bool live[4] = {false, false, false, false};
       if (item < G) {
-        const int64_t grp = (oa >> 2) + (int64_t)(item - oex);
+        const uint32_t grp = (oa >> 2) + (item - oex);
         const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
         uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
         if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
-        const uint4 x = draw(st, kKindCoin, (uint64_t)grp);
-        const int32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
+        const uint4 x = draw(key, st, kKindCoin, (uint64_t)grp);
+        sv[0] = s4.x;
+        sv[1] = s4.y;
+        sv[2] = s4.z;
+        sv[3] = s4.w;
         const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
         const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
-        const int64_t e0 = grp << 2;
+        const uint32_t e0 = grp << 2;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          const int64_t e = e0 + w;
-          if (e < oa || e >= oa + od) continue;
-          if (!edge_live<WC>(xv[w], tv[w], od)) continue;
+          const uint32_t e = e0 + (uint32_t)w;
+          live[w] = e - oa < od && edge_live<WC>(xv[w], tv[w], od);
+        }
+      }
+      if (kHash) {
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          if (!live[w]) continue;
           const int32_t u = sv[w];
-          const int r = lds_insert<HLOG>(h, (uint32_t)u);
+          const int r = lds_insert<(kHash ? HLOG : 1)>(h, (uint32_t)u);
           if (r < 0) {
             lbad = true;
           } else if (r == 1) {
@@ -420,6 +508,30 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
             if (pos < (uint32_t)Q) q[pos] = u;
             else lbad = true;
             if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+          }
+        }
+      } else if (seg_bits<S>(__ballot(live[0] || live[1] || live[2] || live[3]), sw) != 0ull) {
+        // the segment's live edges, one at a time: append the source unless
+        // the queue already holds it
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          uint64_t m = seg_bits<S>(__ballot(live[w]), sw);
+          while (m) {
+            const int src_lane = __ffsll((unsigned long long)m) - 1;
+            m &= m - 1ull;
+            const int32_t u = __shfl(sv[w], src_lane, S);
+            bool found = false;
+            for (int i = sl; i < tail_r; i += S) found |= q[i] == u;
+            if (seg_bits<S>(__ballot(found), sw) == 0ull) {
+              if (tail_r < Q) {
+                if (is_leader) q[tail_r] = u;
+                ++tail_r;
+                wave_sync();
+                if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+              } else {
+                lbad = true;
+              }
+            }
           }
         }
       }
@@ -431,6 +543,19 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
     bad = bad || seg_bits<S>(bm, sw) != 0ull;
   }
   wave_flush(a, acc, io.acc, lane);
+}
+
+// Exact sum of kappa(R) * 2^53 over the widths a width-mode launch wrote
+// (Equation (8)); optionally copies the widths out as uint64.
+__global__ __launch_bounds__(kSegThreads) void kappa_reduce_kernel(SampleArgs a) {
+  Acc acc;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count; i += stride) {
+    const uint32_t w = a.wbuf[i];
+    acc.kappa += kappa_fixed(w, a.g.m, a.k);
+    if (a.widths) a.widths[i] = w;
+  }
+  wave_flush(a, acc, 0, threadIdx.x % kWave);
 }
 
 // ------------------------------------------------------------------------
@@ -445,6 +570,7 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
   const int lane = threadIdx.x % kWave;
   int32_t(*chain)[kWave] = s_chain[wv];
   const GraphView g = a.g;
+  const Key key = make_key(a.seed);
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   Acc acc;
   Reservoir res;
@@ -456,14 +582,14 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
   int32_t v = 0;
   int len = 0;
   uint64_t sig = 0;
-  SetStream st = make_set_stream(a.seed, a.phase, a.first);
+  SetStream st = make_set_stream(a.phase, a.first);
   for (;;) {
     {
       unsigned long long item = 0;
       if (take(a, io.next_ctr, a.count, res, !active && !exhausted, true, below, lane, exhausted, item)) {
         rel = item;
-        st = make_set_stream(a.seed, a.phase, a.first + rel);
-        v = draw_root(st, g.n);
+        st = make_set_stream(a.phase, a.first + rel);
+        v = draw_root(key, st, g.n);
         chain[0][lane] = v;
         len = 1;
         width = 0;
@@ -483,7 +609,7 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
         if (d == 0) {
           done = true;
         } else {
-          const uint64_t j = scale64(draw(st, kKindPick, (uint64_t)v), (uint64_t)d);
+          const uint64_t j = scale64(draw(key, st, kKindPick, (uint64_t)v), (uint64_t)d);
           const int32_t u = g.src[ea + (int64_t)j];
           const uint64_t bit = sig_bit(u);
           bool seen = false;
@@ -555,10 +681,9 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
     if (done) {
       active = false;
       if (fin && MODE == kModeWidth) {
-        acc.kappa += kappa_fixed(width, g.m, a.k);
+        a.wbuf[rel] = (uint32_t)width;
         acc.width += width;
         acc.nodes += (unsigned long long)len;
-        if (a.widths) a.widths[rel] = width;
         if (a.sizes) a.sizes[rel] = (uint32_t)len;
       } else if (fin && MODE == kModeCover) {
         acc.width += width;
@@ -589,6 +714,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
   const int tid = threadIdx.x;
   const int lane = tid % kWave, wv = tid / kWave;
   const GraphView g = a.g;
+  const Key key = make_key(a.seed);
   const int slot = blockIdx.x;
   uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)g.n;
   int32_t* queue = a.big_queue + (size_t)slot * (size_t)g.n;
@@ -609,8 +735,8 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
       epoch = 1u;
     }
     const unsigned long long rel = io.in_list[idx];
-    const SetStream st = make_set_stream(a.seed, a.phase, a.first + rel);
-    const int32_t root = draw_root(st, g.n);
+    const SetStream st = make_set_stream(a.phase, a.first + rel);
+    const int32_t root = draw_root(key, st, g.n);
     __syncthreads();
     if (tid == 0) {
       a.big_epoch[slot] = epoch;
@@ -663,7 +789,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
           const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
           uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
           if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
-          const uint4 x = draw(st, kKindCoin, (uint64_t)grp);
+          const uint4 x = draw(key, st, kKindCoin, (uint64_t)grp);
           const int32_t sv[4] = {s4.x, s4.y, s4.z, s4.w};
           const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
           const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
@@ -708,10 +834,9 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
       unsigned long long width = 0;
       for (int w = 0; w < T / kWave; ++w) width += s_red[w];
       if (MODE == kModeWidth) {
-        acc.kappa += kappa_fixed(width, g.m, a.k);
+        a.wbuf[rel] = (uint32_t)width;
         acc.width += width;
         acc.nodes += len;
-        if (a.widths) a.widths[rel] = width;
         if (a.sizes) a.sizes[rel] = len;
       } else {
         acc.width += width;
@@ -730,6 +855,7 @@ __global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) 
   const int slot = blockIdx.x * kWave + threadIdx.x;
   if (slot >= a.big_slots) return;
   const GraphView g = a.g;
+  const Key key = make_key(a.seed);
   uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)g.n;
   int32_t* chain = a.big_queue + (size_t)slot * (size_t)g.n;
   const unsigned long long ndef = list_len(a, io.in_len_ctr);
@@ -743,8 +869,8 @@ __global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) 
       epoch = 1u;
     }
     const unsigned long long rel = io.in_list[idx];
-    const SetStream st = make_set_stream(a.seed, a.phase, a.first + rel);
-    int32_t v = draw_root(st, g.n);
+    const SetStream st = make_set_stream(a.phase, a.first + rel);
+    int32_t v = draw_root(key, st, g.n);
     stamp[v] = epoch;
     chain[0] = v;
     int64_t len = 1;
@@ -755,7 +881,7 @@ __global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) 
       const int64_t d = g.off[v + 1] - ea;
       width += (unsigned long long)d;
       if (d == 0) break;
-      const uint64_t j = scale64(draw(st, kKindPick, (uint64_t)v), (uint64_t)d);
+      const uint64_t j = scale64(draw(key, st, kKindPick, (uint64_t)v), (uint64_t)d);
       const int32_t u = g.src[ea + (int64_t)j];
       if (stamp[u] == epoch) break;
       stamp[u] = epoch;
@@ -764,10 +890,9 @@ __global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) 
       if (MODE == kModeCover && in_seed(a.seed_bits, u)) hit = true;
     }
     if (MODE == kModeWidth) {
-      acc.kappa += kappa_fixed(width, g.m, a.k);
+      a.wbuf[rel] = (uint32_t)width;
       acc.width += width;
       acc.nodes += (unsigned long long)len;
-      if (a.widths) a.widths[rel] = width;
       if (a.sizes) a.sizes[rel] = (uint32_t)len;
     } else if (MODE == kModeEmit) {
       const unsigned long long b = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)len);
@@ -799,33 +924,44 @@ int blocks_per_cu(K kernel, int threads) {
   return nb;
 }
 
-// Segment shapes: S lanes per set, Q nodes and 2Q hash slots in LDS per set,
-// and at most GMAX 4-edge groups per set (32 iterations' worth in tier 0,
-// 64 in tier 1) so that wide sets, which contain a hub's long in-list, move
-// on to a tier with more lanes per set instead of forming a long tail.
+// Tier-0 shapes: S lanes per set, a queue of Q nodes per set in LDS (with a
+// hash of 2^HLOG slots for S >= 16), and at most GMAX 4-edge groups per set
+// so that wide sets, which hold a hub's long in-list, move on to a tier with
+// more lanes per set instead of forming a long tail.  The hash-free shapes
+// keep 16 KB of LDS per block, so a CU holds 32 wavefronts.
 template <int MODE, bool WC, int S>
 struct SegKernel;
 template <int MODE, bool WC>
+struct SegKernel<MODE, WC, 4> {
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 4, 64, 0, 256>;
+};
+template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 8> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 8, 64, 7, 32 * 8>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 8, 128, 0, 256>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 16> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 16, 128, 8, 32 * 16>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 16, 128, 8, 512>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 32> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 32, 256, 9, 32 * 32>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 32, 256, 9, 1024>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 64> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 32 * 64>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 2048>;
 };
 // tier 1: one set per wavefront
 template <int MODE, bool WC>
 struct Tier1Kernel {
   static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 64 * 64>;
 };
+
+void launch_kappa_reduce(const SampleArgs& a, hipStream_t s) {
+  uint64_t blocks = (a.count + kSegThreads - 1) / kSegThreads;
+  blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+  hipLaunchKernelGGL(kappa_reduce_kernel, dim3((unsigned)blocks), dim3(kSegThreads), 0, s, a);
+}
 
 template <int MODE, bool WC>
 void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, hipEvent_t after0) {
@@ -834,6 +970,7 @@ void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, 
   const TierIO t1 = {a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1};
   const TierIO t2 = {a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2};
   switch (S) {
+    case 4: hipLaunchKernelGGL((SegKernel<MODE, WC, 4>::fn), dim3(grid0), blk, 0, s, a, t0); break;
     case 8: hipLaunchKernelGGL((SegKernel<MODE, WC, 8>::fn), dim3(grid0), blk, 0, s, a, t0); break;
     case 16: hipLaunchKernelGGL((SegKernel<MODE, WC, 16>::fn), dim3(grid0), blk, 0, s, a, t0); break;
     case 32: hipLaunchKernelGGL((SegKernel<MODE, WC, 32>::fn), dim3(grid0), blk, 0, s, a, t0); break;
@@ -842,6 +979,7 @@ void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, 
   if (after0) (void)hipEventRecord(after0, s);
   hipLaunchKernelGGL((Tier1Kernel<MODE, WC>::fn), dim3(grid1), blk, 0, s, a, t1);
   hipLaunchKernelGGL((ic_big_kernel<MODE, WC>), dim3(a.big_slots), dim3(kBigThreads), 0, s, a, t2);
+  if (MODE == kModeWidth) launch_kappa_reduce(a, s);
 }
 
 template <int MODE>
@@ -851,11 +989,13 @@ void launch_lt(const SampleArgs& a, int grid0, hipStream_t s, hipEvent_t after0)
   hipLaunchKernelGGL((lt_lane_kernel<MODE>), dim3(grid0), dim3(kLtWaves * kWave), 0, s, a, t0);
   if (after0) (void)hipEventRecord(after0, s);
   hipLaunchKernelGGL((lt_big_kernel<MODE>), dim3((a.big_slots + kWave - 1) / kWave), dim3(kWave), 0, s, a, t2);
+  if (MODE == kModeWidth) launch_kappa_reduce(a, s);
 }
 
 template <int MODE, bool WC>
 int ic_occupancy(int S) {
   switch (S) {
+    case 4: return blocks_per_cu((SegKernel<MODE, WC, 4>::fn), kSegThreads);
     case 8: return blocks_per_cu((SegKernel<MODE, WC, 8>::fn), kSegThreads);
     case 16: return blocks_per_cu((SegKernel<MODE, WC, 16>::fn), kSegThreads);
     case 32: return blocks_per_cu((SegKernel<MODE, WC, 32>::fn), kSegThreads);
@@ -872,7 +1012,7 @@ void launch_clear_counters(unsigned long long* ctr, hipStream_t s) {
 int ic_seg_lanes() {
   const char* e = getenv("TIM_IC_SEG_LANES");
   const int v = e ? atoi(e) : 8;
-  return (v == 8 || v == 16 || v == 32 || v == 64) ? v : 8;
+  return (v == 4 || v == 8 || v == 16 || v == 32 || v == 64) ? v : 8;
 }
 
 int ic_tier1_blocks_per_cu(int mode, bool wc) {

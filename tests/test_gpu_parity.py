@@ -360,7 +360,7 @@ def test_max_coverage_large_tiles_overflow_lds_tables(eng):
         assert np.array_equal(seeds, ws) and np.array_equal(gains, wg), k
 
 
-@pytest.mark.parametrize("lanes", ["16", "32", "64"])
+@pytest.mark.parametrize("lanes", ["4", "16", "32", "64"])
 def test_segment_width_does_not_change_results(cfg1, cfg2, lanes, monkeypatch):
     # the IC tier-0 kernel's lanes per set is a launch-shape choice only
     import paper_1404_0900_amd as tim
