@@ -113,13 +113,23 @@ typedef struct {
   double kpt_plus;        /* max(KPT', KPT*) */
 } tim_refine_result;
 
-/* NodeSelection (Algorithm 1). */
+/* NodeSelection (Algorithm 1).  The collection is kept in device memory
+ * with its inverted index when it fits the context's budget (without one:
+ * the free device memory).  Otherwise sets [0, resident_sets) are kept and
+ * the rest is regenerated from its keys in chunks of chunk_sets sets, once
+ * for the initial counts and once after every greedy step but the last
+ * (regenerated_sets counts the generations beyond the first).  Sets are a
+ * function of (seed, phase, id), so the seeds and gains do not depend on
+ * this. */
 typedef struct {
   uint64_t theta;     /* sets generated */
   uint64_t nodes;     /* total size of the RR collection */
   uint64_t width;     /* total width (edges examined) */
   uint64_t covered;   /* sets covered by the k seeds = sum of gains */
-  uint64_t store_bytes; /* device bytes of the RR collection and its index */
+  uint64_t store_bytes; /* device bytes held for the collection and its index */
+  uint64_t resident_sets;    /* sets kept with their inverted index (theta if all) */
+  uint64_t chunk_sets;       /* sets per regenerated chunk (0 if none) */
+  uint64_t regenerated_sets; /* set generations beyond the first */
 } tim_select_result;
 
 /* Everything tim_run computes, with per-phase GPU times in milliseconds. */
@@ -139,8 +149,12 @@ typedef struct {
 
 /* Creates a context on HIP device `device`.  `stream` is a hipStream_t to
  * order work on (NULL: the library creates its own).  `hbm_budget_bytes`
- * caps the device memory the library allocates for RR sets and their index
- * (0: no cap).  Returns TIM_EDEVICE if the device cannot be used. */
+ * caps the device memory the library allocates for RR sets, their index and
+ * the sampler's work space (0: no cap; the free device memory then bounds
+ * the RR collection).  The graph is not counted.  A collection that does
+ * not fit is processed in regenerated chunks (see tim_select_result);
+ * TIM_EBUDGET means the budget is too small even for that.  Returns
+ * TIM_EDEVICE if the device cannot be used. */
 tim_status tim_ctx_create(int device, void *stream, uint64_t hbm_budget_bytes, tim_ctx **out);
 void tim_ctx_destroy(tim_ctx *ctx);
 
@@ -149,6 +163,13 @@ const char *tim_last_error(void);
 
 /* Bytes of device memory currently held by the context (graphs excluded). */
 uint64_t tim_ctx_device_bytes(const tim_ctx *ctx);
+
+/* Most RR sets a greedy (RefineKPT's and NodeSelection's) keeps resident
+ * with their inverted index; the rest is regenerated in chunks between
+ * greedy steps, as when the collection exceeds the budget.  UINT64_MAX (the
+ * default) sets no limit; 0 regenerates every set.  Results do not depend on
+ * it. */
+tim_status tim_set_resident_limit(tim_ctx *ctx, uint64_t max_sets);
 
 /* ---- profile ------------------------------------------------------------ */
 

@@ -25,7 +25,8 @@ MAX_ROUNDS = 64
 OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, ECAPACITY = range(6)
 _STATUS = {1: "TIM_EINVAL", 2: "TIM_ENOMEM", 3: "TIM_EBUDGET", 4: "TIM_EDEVICE", 5: "TIM_ECAPACITY"}
 
-EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_device_bytes", "tim_graph_upload",
+EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_device_bytes", "tim_set_resident_limit",
+            "tim_graph_upload",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
             "tim_profile_read")
@@ -64,7 +65,8 @@ class RefineResult(ctypes.Structure):
 
 
 class SelectResult(ctypes.Structure):
-    _fields_ = [("theta", U64), ("nodes", U64), ("width", U64), ("covered", U64), ("store_bytes", U64)]
+    _fields_ = [("theta", U64), ("nodes", U64), ("width", U64), ("covered", U64), ("store_bytes", U64),
+                ("resident_sets", U64), ("chunk_sets", U64), ("regenerated_sets", U64)]
 
 
 class Report(ctypes.Structure):
@@ -103,6 +105,7 @@ def load_library():
         "tim_ctx_destroy": (None, [P]),
         "tim_last_error": (ctypes.c_char_p, []),
         "tim_ctx_device_bytes": (U64, [P]),
+        "tim_set_resident_limit": (ctypes.c_int, [P, U64]),
         "tim_graph_upload": (ctypes.c_int, [P, I64, I64, P, P, P, ctypes.POINTER(P)]),
         "tim_graph_free": (None, [P]),
         "tim_sample_rr": (ctypes.c_int, [P, P, ctypes.c_int, U64, U32, U64, U64, P, P, U64, P,
@@ -185,6 +188,10 @@ class Engine:
 
     def device_bytes(self) -> int:
         return int(self.lib.tim_ctx_device_bytes(self.ctx))
+
+    def set_resident_limit(self, max_sets: int | None):
+        """Most RR sets a greedy keeps resident (None: no limit); the rest is regenerated in chunks."""
+        _check(self.lib.tim_set_resident_limit(self.ctx, (1 << 64) - 1 if max_sets is None else int(max_sets)))
 
     def profile(self, on: bool = True):
         """Turns per-kernel timing on/off and clears the counters."""

@@ -70,6 +70,9 @@ struct tim_ctx {
   uint64_t held = 0;
   int num_cu = 0;
   int seg_lanes = 8;
+  uint32_t slice_cap = tim::kPoolChunk;  // largest node-pool slice of a wavefront
+  uint32_t slice = tim::kPoolChunk;      // slice of the current emit launches
+  uint64_t resident_limit = ~0ull;       // most sets a greedy keeps resident
   int grid_ic[3][2] = {};
   int grid_ic64[3][2] = {};
   int grid_lt[3] = {};
@@ -108,7 +111,10 @@ tim_status ensure(tim_ctx* c, DevBuf& b, size_t bytes, const char* what) {
       return fail(TIM_EBUDGET, "%s needs %zu bytes; %llu of the %llu-byte budget are in use", what, bytes,
                   (unsigned long long)others, (unsigned long long)c->budget);
   }
-  if (b.p) (void)hipFree(b.p);
+  if (b.p) {
+    (void)hipStreamSynchronize(c->stream);  // kernels in flight may still read it
+    (void)hipFree(b.p);
+  }
   c->held = others;
   b.p = nullptr;
   b.bytes = 0;
@@ -122,7 +128,10 @@ tim_status ensure(tim_ctx* c, DevBuf& b, size_t bytes, const char* what) {
 }
 
 void release(tim_ctx* c, DevBuf& b) {
-  if (b.p) (void)hipFree(b.p);
+  if (b.p) {
+    (void)hipStreamSynchronize(c->stream);
+    (void)hipFree(b.p);
+  }
   c->held -= b.bytes;
   b = DevBuf();
 }
@@ -180,13 +189,28 @@ uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t co
   return grid;
 }
 
-// Node-pool entries that per-wavefront slices can leave unused in one launch.
-uint64_t pool_slack(const tim_ctx* c, int model) {
-  uint64_t waves = 0;
-  sample_grid(c, model, tim::kModeEmit, true, ~0ull >> 1, &waves);
-  uint64_t w2 = 0;
-  sample_grid(c, model, tim::kModeEmit, false, ~0ull >> 1, &w2);
-  return std::max(waves, w2) * tim::kPoolChunk;
+// Wavefronts of the tier-0 launch over `count` sets (the only tier that
+// reserves node-pool slices; the others reserve exactly what they store).
+uint64_t emit_waves(const tim_ctx* c, int model, uint64_t count) {
+  uint64_t waves = 0, w2 = 0;
+  sample_grid(c, model, tim::kModeEmit, true, count, &waves);
+  sample_grid(c, model, tim::kModeEmit, false, count, &w2);
+  return std::max(waves, w2);
+}
+
+// Node-pool slice for launches of `count` sets holding about `nodes`
+// entries: about a quarter of a wavefront's share, a power of two in
+// [64, slice_cap].
+uint32_t pick_slice(const tim_ctx* c, int model, uint64_t count, uint64_t nodes) {
+  const uint64_t per_wave = nodes / std::max<uint64_t>(1, emit_waves(c, model, std::min(count, kMaxLaunchSets)));
+  uint32_t s = 64;
+  while (s < c->slice_cap && (uint64_t)s * 8 <= per_wave) s <<= 1;
+  return std::min(s, c->slice_cap);
+}
+
+// Node-pool entries that part-used slices can leave empty in one launch.
+uint64_t pool_slack(const tim_ctx* c, int model, uint64_t count, uint32_t slice) {
+  return emit_waves(c, model, std::min(count, kMaxLaunchSets)) * (uint64_t)slice;
 }
 
 // One sampling launch pair (wave/lane-level pass, then the large-set pass)
@@ -223,6 +247,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
     a.pool = c->pool.as<int32_t>() + std::min(pool_base, cap);
     a.pool_cap = pool_base < cap ? cap - pool_base : 0;
     a.pool_base = pool_base;
+    a.pool_chunk = c->slice;
     a.set_start = c->set_start.as<uint64_t>() + set_offset;
     a.set_len = c->set_len.as<uint32_t>() + set_offset;
   }
@@ -282,11 +307,20 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   return TIM_OK;
 }
 
+// Sets per width- or coverage-mode launch: kMaxLaunchSets, or fewer where
+// the budget leaves less than four times their deferral lists and widths.
+uint64_t launch_cap(const tim_ctx* c) {
+  if (!c->budget) return kMaxLaunchSets;
+  const uint64_t room = c->budget > c->held ? c->budget - c->held : 0;
+  return std::max<uint64_t>(4096, std::min<uint64_t>(kMaxLaunchSets, room / 4 / 20));
+}
+
 // Width or coverage mode over any number of sets, in launches of bounded size.
 tim_status sample_counts(tim_ctx* c, const tim_graph* g, int model, int mode, uint64_t seed, uint32_t phase,
                          uint64_t first, uint64_t count, int k, uint64_t* widths, uint32_t* sizes, Totals* t) {
+  const uint64_t cap = launch_cap(c);
   for (uint64_t done = 0; done < count;) {
-    const uint64_t part = std::min(count - done, kMaxLaunchSets);
+    const uint64_t part = std::min(count - done, cap);
     TIM_TRY(sample_launch(c, g, model, mode, seed, phase, first + done, part, k, widths ? widths + done : nullptr,
                           sizes ? sizes + done : nullptr, 0, 0, t));
     done += part;
@@ -301,7 +335,8 @@ tim_status emit_sets(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, u
                      uint64_t count, uint64_t expect_nodes, uint64_t* widths, Totals* t_out) {
   TIM_TRY(ensure(c, c->set_start, count * 8, "set offsets"));
   TIM_TRY(ensure(c, c->set_len, count * 4, "set sizes"));
-  const uint64_t slack = pool_slack(c, model) * ((count + kMaxLaunchSets - 1) / kMaxLaunchSets);
+  c->slice = pick_slice(c, model, count, expect_nodes);
+  const uint64_t slack = pool_slack(c, model, count, c->slice) * ((count + kMaxLaunchSets - 1) / kMaxLaunchSets);
   TIM_TRY(ensure(c, c->pool, (std::max<uint64_t>(expect_nodes, 1024) + slack) * 4, "RR node pool"));
   for (int attempt = 0; attempt < 2; ++attempt) {
     Totals t;
@@ -383,6 +418,265 @@ tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off,
     seeds[j] = (int32_t)(0xFFFFFFFFull - (keys[j] & 0xFFFFFFFFull));
     if (gains) gains[j] = keys[j] >> 32;
   }
+  return TIM_OK;
+}
+
+// ---- greedy over a phase's sets under the device-memory budget ----
+//
+// The paper keeps the whole collection R in memory (R, of lambda / KPT+ sets,
+// dominates its memory use: Section 7.4).  When the sets and their index do not
+// fit, a prefix of the sets is kept with its index and the rest is
+// regenerated from its keys in chunks: once to add its memberships to the
+// counts, then after every greedy step to take the newly covered sets out of
+// them.  Sets are a pure function of (seed, phase, id), so this is the same
+// collection and the same greedy, step for step.
+
+float elapsed_ms(tim_ctx* c);
+
+struct CollectionStats {
+  uint64_t nodes = 0, width = 0;  // of the collection (each set counted once)
+  uint64_t resident = 0;          // sets kept with their index
+  uint64_t chunk = 0;             // sets per regenerated chunk (0: none)
+  uint64_t regenerated = 0;       // set generations beyond the first
+  uint64_t store_bytes = 0;
+  float ms_sample = 0.f, ms_greedy = 0.f;
+};
+
+DevBuf* const* transient_bufs(tim_ctx* c, size_t* n) {
+  static thread_local DevBuf* bufs[17];
+  DevBuf* list[] = {&c->list1,  &c->list2,   &c->wbuf,    &c->pool,     &c->set_start, &c->set_len,
+                    &c->rr_off, &c->rr_nodes, &c->sizes,  &c->cnt,      &c->fill,      &c->inv_off,
+                    &c->inv_sets, &c->covered, &c->selected, &c->best, &c->scan_tmp};
+  for (size_t i = 0; i < 17; ++i) bufs[i] = list[i];
+  *n = 17;
+  return bufs;
+}
+
+uint64_t transient_bytes(tim_ctx* c) {
+  size_t nb = 0;
+  DevBuf* const* b = transient_bufs(c, &nb);
+  uint64_t t = 0;
+  for (size_t i = 0; i < nb; ++i) t += b[i]->bytes;
+  return t;
+}
+
+void release_transients(tim_ctx* c) {
+  size_t nb = 0;
+  DevBuf* const* b = transient_bufs(c, &nb);
+  (void)hipStreamSynchronize(c->stream);
+  for (size_t i = 0; i < nb; ++i) release(c, *b[i]);
+}
+
+// Bytes a collection may take: the budget (without one, 90% of the free
+// device memory) less what the context holds for other purposes.
+tim_status collection_room(tim_ctx* c, uint64_t* room) {
+  const uint64_t trans = transient_bytes(c);
+  const uint64_t other = c->held - trans;
+  if (c->budget) {
+    *room = c->budget > other ? c->budget - other : 0;
+    return TIM_OK;
+  }
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  *room = (uint64_t)(0.9 * (double)(free_b + trans));
+  return TIM_OK;
+}
+
+uint64_t lists_per_set(int model) { return model == TIM_MODEL_IC ? 16 : 8; }
+
+// Peak bytes of the all-resident path for `count` sets of `nodes` entries.
+uint64_t resident_bytes(const tim_ctx* c, int64_t n, int model, uint64_t count, uint64_t nodes, int k) {
+  const uint64_t launches = (count + kMaxLaunchSets - 1) / kMaxLaunchSets;
+  const uint64_t lists = std::min(count, kMaxLaunchSets) * lists_per_set(model);
+  const uint64_t emit = count * 12 + (nodes + pool_slack(c, model, count, pick_slice(c, model, count, nodes)) *
+                                                 launches) * 4;
+  const uint64_t store = (count + 1) * 8 + nodes * 4;
+  const uint64_t index = (uint64_t)n * 17 + 8 + nodes * 4 + count + 8 * (uint64_t)k +
+                         tim::scan_temp_bytes(std::max<uint64_t>(count, (uint64_t)n + 1)) + 17 * 256;
+  return lists + emit + store + index;
+}
+
+// Regenerates sets [from, to) of a phase into the node pool, `*chunk` sets at
+// a time (halved while a chunk does not fit), and hands every chunk to fn.
+template <class F>
+tim_status for_chunks(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t from,
+                      uint64_t to, uint64_t* chunk, double nodes_per_set, Totals* tot, F fn) {
+  for (uint64_t a = from; a < to;) {
+    const uint64_t len = std::min(*chunk, to - a);
+    Totals t;
+    const tim_status st = emit_sets(c, g, model, seed, phase, a, len, (uint64_t)(nodes_per_set * (double)len) + 1024,
+                                    nullptr, &t);
+    if (st == TIM_EBUDGET && len > 64) {
+      *chunk = len / 2;
+      continue;
+    }
+    TIM_TRY(st);
+    fn(a, len);
+    HIP_TRY(hipGetLastError());
+    if (tot) {
+      tot->nodes += t.nodes;
+      tot->width += t.width;
+    }
+    a += len;
+  }
+  return TIM_OK;
+}
+
+// Sets of phase `phase` with ids [0, count): the greedy of Algorithm 1
+// (lines 3-7) on them, keeping as many as the budget allows resident.
+// expect_nodes estimates their total size.
+tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase,
+                             uint64_t count, int k, uint64_t expect_nodes, int32_t* seeds, uint64_t* gains,
+                             CollectionStats* st) {
+  if (count >= 0xFFFFFFFFull) return fail(TIM_EINVAL, "more than 2^32-1 sets in one collection");
+  const int64_t n = g->n;
+  uint64_t room = 0;
+  TIM_TRY(collection_room(c, &room));
+  HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+  if (count <= c->resident_limit && resident_bytes(c, n, model, count, expect_nodes, k) <= room) {
+    Totals t;
+    TIM_TRY(sample_store(c, g, model, seed, phase, 0, count, expect_nodes, nullptr, &t));
+    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+    st->ms_sample = elapsed_ms(c);
+    HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+    TIM_TRY(greedy(c, n, count, c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), t.nodes, k, seeds, gains));
+    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+    st->ms_greedy = elapsed_ms(c);
+    st->nodes = t.nodes;
+    st->width = t.width;
+    st->resident = count;
+    st->store_bytes = (count + 1) * 8 + t.nodes * 8 + ((uint64_t)n + 1) * 8;
+    return TIM_OK;
+  }
+
+  // ---- plan: a chunk size for the regenerated part, then the resident prefix
+  release_transients(c);
+  TIM_TRY(collection_room(c, &room));
+  struct SliceScope {
+    tim_ctx* c;
+    ~SliceScope() { c->slice_cap = tim::kPoolChunk; }
+  } scope{c};
+  c->slice_cap = 64;  // small pool slices: the pool is sized for one chunk
+  const double nps = count ? std::max(1.0, (double)expect_nodes / (double)count) : 1.0;
+  const uint64_t fixed = (uint64_t)n * 5 + count + 8 * (uint64_t)k + 8 * 256;  // cnt, selected, covered, best
+  if (fixed >= room)
+    return fail(TIM_EBUDGET, "budget too small for the coverage counts of %llu sets (%llu bytes needed, %llu left)",
+                (unsigned long long)count, (unsigned long long)fixed, (unsigned long long)room);
+  const uint64_t avail = room - fixed;
+  // per chunk set: offsets and size, deferral lists, its nodes, and the
+  // slack of its tier-0 wavefronts' slices
+  const uint64_t slack_fixed = pool_slack(c, model, 0, 64) * 4 + 8 * 256;
+  const double waves_per_set =
+      model == TIM_MODEL_IC ? (double)c->seg_lanes / 64.0 : 2.0 / 128.0;  // tier-0 wavefronts per set
+  const double slice_per_set = 64.0 * 4.0 * waves_per_set;
+  const double per_chunk_set = 12.0 + (double)lists_per_set(model) + 4.0 * nps + slice_per_set;
+  uint64_t chunk = avail / 4 > slack_fixed ? (uint64_t)((double)(avail / 4 - slack_fixed) / per_chunk_set) : 0;
+  chunk = std::min({chunk, count, kMaxLaunchSets});
+  if (chunk < 64 && chunk < count)
+    return fail(TIM_EBUDGET, "budget too small to regenerate %llu sets in chunks (%llu bytes left)",
+                (unsigned long long)count, (unsigned long long)avail);
+  const uint64_t chunk_cost = (uint64_t)((double)chunk * per_chunk_set) + slack_fixed;
+  const uint64_t idx_fixed = (uint64_t)n * 12 + 8 + 6 * 256 + tim::scan_temp_bytes(count);  // fill, inv_off, scan
+  const double per_res_steady = 8.0 + 8.0 * nps;
+  const double per_res_peak = 20.0 + (double)lists_per_set(model) + 8.0 * nps + slice_per_set;
+  uint64_t resident = 0;
+  if (avail > chunk_cost + idx_fixed) {
+    const uint64_t r1 = (uint64_t)((double)(avail - chunk_cost - idx_fixed) / per_res_steady);
+    const uint64_t r2 = avail > slack_fixed ? (uint64_t)((double)(avail - slack_fixed) / per_res_peak) : 0;
+    resident = std::min({r1, r2, count - 1, c->resident_limit});
+  }
+
+  tim::GreedyArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.scan_temp = nullptr;
+  Totals first_pass;
+  if (resident > 0) {
+    Totals t;
+    tim_status s1 = sample_store(c, g, model, seed, phase, 0, resident, (uint64_t)(nps * (double)resident) + 1024,
+                                 nullptr, &t);
+    if (s1 == TIM_OK) {
+      release(c, c->pool);
+      release(c, c->set_start);
+      release(c, c->set_len);
+      release(c, c->list1);
+      release(c, c->list2);
+      s1 = ensure(c, c->inv_sets, t.nodes * 4, "index entries");
+    }
+    if (s1 == TIM_OK) s1 = ensure(c, c->fill, (size_t)n * 4, "index cursors");
+    if (s1 == TIM_OK) s1 = ensure(c, c->inv_off, (size_t)(n + 1) * 8, "index offsets");
+    if (s1 == TIM_OK) s1 = ensure(c, c->cnt, (size_t)n * 4, "coverage counts");
+    if (s1 == TIM_OK) s1 = ensure(c, c->scan_tmp, tim::scan_temp_bytes((uint64_t)n + 1), "scan");
+    if (s1 == TIM_EBUDGET) {
+      // the prefix came out larger than estimated: regenerate everything instead
+      release_transients(c);
+      resident = 0;
+    } else {
+      TIM_TRY(s1);
+      a.nsets = resident;
+      a.total = t.nodes;
+      a.set_off = c->rr_off.as<int64_t>();
+      a.nodes = c->rr_nodes.as<int32_t>();
+      a.cnt = c->cnt.as<uint32_t>();
+      a.fill = c->fill.as<uint32_t>();
+      a.inv_off = c->inv_off.as<int64_t>();
+      a.inv_sets = c->inv_sets.as<uint32_t>();
+      a.scan_temp = c->scan_tmp.p;
+      tim::launch_index(a, c->stream);
+      HIP_TRY(hipGetLastError());
+      first_pass = t;
+    }
+  }
+  TIM_TRY(ensure(c, c->cnt, (size_t)n * 4, "coverage counts"));
+  TIM_TRY(ensure(c, c->covered, count, "covered marks"));
+  TIM_TRY(ensure(c, c->selected, (size_t)n, "selected marks"));
+  TIM_TRY(ensure(c, c->best, (size_t)k * 8, "argmax keys"));
+  a.cnt = c->cnt.as<uint32_t>();
+  a.covered = c->covered.as<uint8_t>();
+  a.selected = c->selected.as<uint8_t>();
+  a.best = c->best.as<unsigned long long>();
+  if (resident == 0) {
+    a.nsets = 0;
+    tim::launch_zero_counts(a.cnt, n, c->stream);
+  }
+  tim::launch_greedy_init(a, count, k, c->stream);
+
+  // memberships of the regenerated part
+  TIM_TRY(for_chunks(c, g, model, seed, phase, resident, count, &chunk, nps, &first_pass,
+                     [&](uint64_t, uint64_t len) {
+                       tim::launch_pool_hist(c->pool.as<int32_t>(), c->set_start.as<uint64_t>(),
+                                             c->set_len.as<uint32_t>(), len, a.cnt, c->stream);
+                     }));
+  HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+  st->ms_sample = elapsed_ms(c);
+  HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+  for (int j = 0; j < k; ++j) {
+    tim::launch_argmax_step(a, j, c->stream);
+    if (j + 1 == k) break;  // the last choice changes no later step
+    tim::launch_cover_step(a, j, c->stream);
+    TIM_TRY(for_chunks(c, g, model, seed, phase, resident, count, &chunk, nps, nullptr,
+                       [&](uint64_t first, uint64_t len) {
+                         tim::launch_pool_cover(a.best + j, c->pool.as<int32_t>(), c->set_start.as<uint64_t>(),
+                                                c->set_len.as<uint32_t>(), len, a.covered + first, a.cnt,
+                                                c->stream);
+                       }));
+    st->regenerated += count - resident;
+  }
+  HIP_TRY(hipGetLastError());
+  std::vector<unsigned long long> keys((size_t)k);
+  HIP_TRY(hipMemcpyAsync(keys.data(), a.best, (size_t)k * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+  st->ms_greedy = elapsed_ms(c);
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int j = 0; j < k; ++j) {
+    seeds[j] = (int32_t)(0xFFFFFFFFull - (keys[j] & 0xFFFFFFFFull));
+    if (gains) gains[j] = keys[j] >> 32;
+  }
+  st->nodes = first_pass.nodes;
+  st->width = first_pass.width;
+  st->resident = resident;
+  st->chunk = chunk;
+  st->store_bytes = transient_bytes(c);
   return TIM_OK;
 }
 
@@ -474,16 +768,14 @@ tim_status refine_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed,
                        tim_refine_result* out, uint64_t* sets, uint64_t* width) {
   memset(out, 0, sizeof(*out));
   // lines 1-6: greedy on the sets of the last round of Algorithm 2
-  Totals t;
+  CollectionStats cs;
   if (c_last > 0) {
-    TIM_TRY(sample_store(c, g, model, seed, (uint32_t)i_last, 0, c_last, expect_nodes, nullptr, &t));
-    TIM_TRY(greedy(c, g->n, c_last, c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), t.nodes, k, s_prime,
-                   nullptr));
+    TIM_TRY(collection_greedy(c, g, model, seed, (uint32_t)i_last, c_last, k, expect_nodes, s_prime, nullptr, &cs));
   } else {
     for (int j = 0; j < k; ++j) s_prime[j] = j;
   }
   if (sets) *sets += c_last;
-  if (width) *width += t.width;
+  if (width) *width += cs.width;
   // lines 7-10
   const double nd = (double)g->n;
   const double eps_p = 5.0 * std::cbrt(ell * eps * eps / ((double)k + ell));
@@ -512,29 +804,26 @@ struct SelectTimes {
 tim_status node_select_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, uint64_t theta,
                             uint64_t expect_nodes, int32_t* seeds, uint64_t* gains, tim_select_result* out,
                             SelectTimes* times) {
-  Totals t;
-  if (times) HIP_TRY(hipEventRecord(c->ev[0], c->stream));
-  TIM_TRY(sample_store(c, g, model, seed, TIM_PHASE_SELECT, 0, theta, expect_nodes, nullptr, &t));
-  if (times) {
-    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
-    times->sample = elapsed_ms(c);
-    HIP_TRY(hipEventRecord(c->ev[0], c->stream));
-  }
   std::vector<uint64_t> g_local((size_t)k);
   uint64_t* gp = gains ? gains : g_local.data();
-  TIM_TRY(greedy(c, g->n, theta, c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), t.nodes, k, seeds, gp));
+  CollectionStats cs;
+  TIM_TRY(collection_greedy(c, g, model, seed, TIM_PHASE_SELECT, theta, k, expect_nodes, seeds, gp, &cs));
   if (times) {
-    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
-    times->index_greedy = elapsed_ms(c);
+    times->sample = cs.ms_sample;
+    times->index_greedy = cs.ms_greedy;
   }
   if (out) {
+    memset(out, 0, sizeof(*out));
     out->theta = theta;
-    out->nodes = t.nodes;
-    out->width = t.width;
+    out->nodes = cs.nodes;
+    out->width = cs.width;
     uint64_t cov = 0;
     for (int j = 0; j < k; ++j) cov += gp[j];
     out->covered = cov;
-    out->store_bytes = (theta + 1) * 8 + t.nodes * 4 + t.nodes * 4 + ((uint64_t)g->n + 1) * 8;
+    out->store_bytes = cs.store_bytes;
+    out->resident_sets = cs.resident;
+    out->chunk_sets = cs.chunk;
+    out->regenerated_sets = cs.regenerated;
   }
   return TIM_OK;
 }
@@ -612,6 +901,12 @@ void tim_ctx_destroy(tim_ctx* c) {
 }
 
 uint64_t tim_ctx_device_bytes(const tim_ctx* c) { return c ? c->held : 0; }
+
+tim_status tim_set_resident_limit(tim_ctx* c, uint64_t max_sets) {
+  if (!c) return fail(TIM_EINVAL, "null context");
+  c->resident_limit = max_sets;
+  return TIM_OK;
+}
 
 tim_status tim_profile_enable(tim_ctx* c, int on) {
   if (!c) return fail(TIM_EINVAL, "null context");

@@ -269,6 +269,54 @@ __global__ __launch_bounds__(kThreads) void argmax_kernel(const uint32_t* cnt, c
   }
 }
 
+// Block-wide prefix of the sizes of a tile's sets: thread t < kTileSets
+// carries set t (len 0 if it takes no part); afterwards s_pre[t] is the first
+// tile position of set t, s_pre[kTileSets] the tile total, and s_start[t] its
+// first entry in the collection.
+__device__ __forceinline__ void tile_prefix(uint32_t len, int64_t start, int64_t* s_start, int64_t* s_pre,
+                                            uint32_t* s_wtot) {
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  uint32_t incl = len;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) s_wtot[wv] = incl;
+  __syncthreads();
+  uint32_t carry = 0;
+  for (int w = 0; w < wv; ++w) carry += s_wtot[w];
+  if (threadIdx.x < kTileSets) {
+    s_start[threadIdx.x] = start;
+    s_pre[threadIdx.x + 1] = carry + incl;
+  }
+  if (threadIdx.x == 0) s_pre[0] = 0;
+  __syncthreads();
+}
+
+// Decrements of a tile's sets (prefix from tile_prefix): one per member
+// other than v, summed per node in LDS.
+__device__ __forceinline__ void tile_decrement(const int32_t* nodes, const int64_t* s_start, const int64_t* s_pre,
+                                               int64_t v, uint32_t* s_key, uint32_t* s_cnt, uint32_t* cnt) {
+  const int64_t tot = s_pre[kTileSets];
+  for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+    const int j = tile_set_of(s_pre, kTileSets, e);
+    const int32_t u = nodes[s_start[j] + (e - s_pre[j])];
+    if (u == v) continue;
+    const int slot = agg_slot(s_key, (uint32_t)u, true);
+    if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
+    else atomicSub(&cnt[u], 1u);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kAgg; i += kThreads)
+    if (s_key[i]) atomicSub(&cnt[s_key[i] - 1u], s_cnt[i]);
+  __syncthreads();
+}
+
+__device__ __forceinline__ int64_t node_of_key(unsigned long long key) {
+  return (int64_t)(0xFFFFFFFFull - (key & 0xFFFFFFFFull));
+}
+
 // The chosen node v covers the sets listed in inv_sets[inv_off[v] ..]: mark
 // those not covered yet and take them out of the counts of their members
 // (v's own count is left alone: v is never chosen again).
@@ -277,14 +325,13 @@ __global__ __launch_bounds__(kThreads) void cover_kernel(const unsigned long lon
                                                          const int32_t* nodes, uint8_t* covered, uint8_t* selected,
                                                          uint32_t* cnt) {
   __shared__ int64_t s_start[kTileSets];
-  __shared__ int64_t s_pre[kTileSets + 1];  // prefix sums of the new sets' sizes
+  __shared__ int64_t s_pre[kTileSets + 1];
   __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
   __shared__ uint32_t s_wtot[kThreads / 64];
   if (*best == 0ull) return;  // no unselected node (cannot happen for k <= n)
-  const int64_t v = (int64_t)(0xFFFFFFFFull - (*best & 0xFFFFFFFFull));
+  const int64_t v = node_of_key(*best);
   if (blockIdx.x == 0 && threadIdx.x == 0) selected[v] = 1u;
   const int64_t lo = inv_off[v], hi = inv_off[v + 1];
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
   for (int64_t i0 = lo + (int64_t)blockIdx.x * kTileSets; i0 < hi; i0 += (int64_t)gridDim.x * kTileSets) {
     const int ni = (int)min((int64_t)kTileSets, hi - i0);
     agg_clear(s_key, s_cnt);
@@ -299,35 +346,84 @@ __global__ __launch_bounds__(kThreads) void cover_kernel(const unsigned long lon
         len = (uint32_t)(set_off[sid + 1] - start);
       }
     }
-    uint32_t incl = len;
-#pragma unroll
-    for (int o = 1; o < 64; o <<= 1) {
-      const uint32_t y = __shfl_up(incl, o, 64);
-      if (lane >= o) incl += y;
+    tile_prefix(len, start, s_start, s_pre, s_wtot);
+    tile_decrement(nodes, s_start, s_pre, v, s_key, s_cnt, cnt);
+  }
+}
+
+__global__ void select_kernel(const unsigned long long* best, uint8_t* selected) {
+  if (threadIdx.x == 0 && *best != 0ull) selected[node_of_key(*best)] = 1u;
+}
+
+// cnt[u] += number of pool sets containing u.
+__global__ __launch_bounds__(kThreads) void pool_hist_kernel(const int32_t* pool, const uint64_t* set_start,
+                                                             const uint32_t* set_len, uint64_t nsets, uint32_t* cnt) {
+  __shared__ int64_t s_start[kTileSets];
+  __shared__ int64_t s_pre[kTileSets + 1];
+  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
+  __shared__ uint32_t s_wtot[kThreads / 64];
+  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
+    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
+    agg_clear(s_key, s_cnt);
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < ns) {
+      start = (int64_t)set_start[s0 + threadIdx.x];
+      len = set_len[s0 + threadIdx.x];
     }
-    if (lane == 63) s_wtot[wv] = incl;
-    __syncthreads();
-    uint32_t carry = 0;
-    for (int w = 0; w < wv; ++w) carry += s_wtot[w];
-    if (threadIdx.x < kTileSets) {
-      s_start[threadIdx.x] = start;
-      s_pre[threadIdx.x + 1] = carry + incl;
-    }
-    if (threadIdx.x == 0) s_pre[0] = 0;
-    __syncthreads();
+    tile_prefix(len, start, s_start, s_pre, s_wtot);
     const int64_t tot = s_pre[kTileSets];
     for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
       const int j = tile_set_of(s_pre, kTileSets, e);
-      const int32_t u = nodes[s_start[j] + (e - s_pre[j])];
-      if (u == v) continue;
-      const int slot = agg_slot(s_key, (uint32_t)u, true);
+      const uint32_t u = (uint32_t)pool[s_start[j] + (e - s_pre[j])];
+      const int slot = agg_slot(s_key, u, true);
       if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
-      else atomicSub(&cnt[u], 1u);
+      else atomicAdd(&cnt[u], 1u);
     }
     __syncthreads();
     for (int i = threadIdx.x; i < kAgg; i += kThreads)
-      if (s_key[i]) atomicSub(&cnt[s_key[i] - 1u], s_cnt[i]);
+      if (s_key[i]) atomicAdd(&cnt[s_key[i] - 1u], s_cnt[i]);
     __syncthreads();
+  }
+}
+
+// Pool sets not covered yet that contain the chosen node v: mark them and
+// take them out of the counts of their members.
+__global__ __launch_bounds__(kThreads) void pool_cover_kernel(const unsigned long long* best, const int32_t* pool,
+                                                              const uint64_t* set_start, const uint32_t* set_len,
+                                                              uint64_t nsets, uint8_t* covered, uint32_t* cnt) {
+  __shared__ int64_t s_start[kTileSets];
+  __shared__ int64_t s_pre[kTileSets + 1];
+  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
+  __shared__ uint32_t s_wtot[kThreads / 64];
+  __shared__ uint32_t s_hit[kTileSets];
+  if (*best == 0ull) return;
+  const int64_t v = node_of_key(*best);
+  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
+    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
+    agg_clear(s_key, s_cnt);
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < ns && !covered[s0 + threadIdx.x]) {
+      start = (int64_t)set_start[s0 + threadIdx.x];
+      len = set_len[s0 + threadIdx.x];
+    }
+    if (threadIdx.x < kTileSets) s_hit[threadIdx.x] = 0u;
+    tile_prefix(len, start, s_start, s_pre, s_wtot);
+    // membership of v
+    const int64_t tot = s_pre[kTileSets];
+    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+      const int j = tile_set_of(s_pre, kTileSets, e);
+      if (pool[s_start[j] + (e - s_pre[j])] == v) s_hit[j] = 1u;
+    }
+    __syncthreads();
+    bool hit = false;
+    if (threadIdx.x < ns) {
+      hit = s_hit[threadIdx.x] != 0u;
+      if (hit) covered[s0 + threadIdx.x] = 1u;
+    }
+    tile_prefix(hit ? len : 0u, start, s_start, s_pre, s_wtot);
+    tile_decrement(pool, s_start, s_pre, v, s_key, s_cnt, cnt);
   }
 }
 
@@ -382,6 +478,46 @@ void launch_index(const GreedyArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s,
                        a.set_off, a.nodes, a.nsets, a.inv_off, a.fill, a.inv_sets);
   }
+}
+
+void launch_zero_counts(uint32_t* cnt, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(zero_u32, dim3(grid_for((uint64_t)n, 4096)), dim3(kThreads), 0, s, cnt, (uint64_t)n);
+}
+
+void launch_greedy_init(const GreedyArgs& a, uint64_t covered_len, int k, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n;
+  if (covered_len)
+    hipLaunchKernelGGL(zero_u8, dim3(grid_for(covered_len, 4096)), dim3(kThreads), 0, s, a.covered, covered_len);
+  hipLaunchKernelGGL(zero_u8, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.selected, n);
+  hipLaunchKernelGGL(zero_u64, dim3(1), dim3(kThreads), 0, s, a.best, (uint64_t)k);
+}
+
+void launch_argmax_step(const GreedyArgs& a, int j, hipStream_t s) {
+  hipLaunchKernelGGL(argmax_kernel, dim3(grid_for((uint64_t)a.n, 2048)), dim3(kThreads), 0, s, a.cnt, a.selected,
+                     a.n, a.best + j);
+  hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a.best + j, a.selected);
+}
+
+void launch_cover_step(const GreedyArgs& a, int j, hipStream_t s) {
+  if (!a.nsets) return;
+  hipLaunchKernelGGL(cover_kernel, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets, a.set_off,
+                     a.nodes, a.covered, a.selected, a.cnt);
+}
+
+void launch_pool_hist(const int32_t* pool, const uint64_t* set_start, const uint32_t* set_len, uint64_t nsets,
+                      uint32_t* cnt, hipStream_t s) {
+  if (!nsets) return;
+  const uint64_t tiles = (nsets + kTileSets - 1) / kTileSets;
+  hipLaunchKernelGGL(pool_hist_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s, pool,
+                     set_start, set_len, nsets, cnt);
+}
+
+void launch_pool_cover(const unsigned long long* best, const int32_t* pool, const uint64_t* set_start,
+                       const uint32_t* set_len, uint64_t nsets, uint8_t* covered, uint32_t* cnt, hipStream_t s) {
+  if (!nsets) return;
+  const uint64_t tiles = (nsets + kTileSets - 1) / kTileSets;
+  hipLaunchKernelGGL(pool_cover_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s, best,
+                     pool, set_start, set_len, nsets, covered, cnt);
 }
 
 void launch_greedy(const GreedyArgs& a, int k, hipStream_t s) {

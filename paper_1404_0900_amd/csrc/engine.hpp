@@ -47,8 +47,9 @@ struct TierIO {
   int acc;                  // accumulator block (tier number)
 };
 
-// Node-pool entries a wavefront reserves at a time when it stores sets.
-constexpr uint64_t kPoolChunk = 2048;
+// Node-pool entries a wavefront reserves at a time when it stores sets (the
+// default; SampleArgs::pool_chunk sets it per launch).
+constexpr uint32_t kPoolChunk = 2048;
 
 struct GraphView {
   const int64_t* off;   // n+1
@@ -70,6 +71,7 @@ struct SampleArgs {
   int32_t* pool;                  // emit: this launch's part of the node pool
   uint64_t pool_cap;              // entries in it
   uint64_t pool_base;             // its offset in the whole pool (added to set_start)
+  uint32_t pool_chunk;            // entries a wavefront reserves at a time (>= 1)
   uint64_t* set_start;            // emit: pool offset of each set
   uint32_t* set_len;              // emit: size of each set
   const uint32_t* seed_bits;      // cover: n-bit membership of the seed set
@@ -122,5 +124,22 @@ struct GreedyArgs {
 };
 void launch_index(const GreedyArgs& a, hipStream_t s);
 void launch_greedy(const GreedyArgs& a, int k, hipStream_t s);
+// The same greedy one step at a time, for collections of which only sets
+// [0, a.nsets) are stored (the rest is regenerated in parts between steps):
+// init clears covered[0, covered_len), the selections and the k keys;
+// argmax writes key j and marks the chosen node selected; cover takes the
+// stored sets containing it out of the counts.
+void launch_zero_counts(uint32_t* cnt, int64_t n, hipStream_t s);
+void launch_greedy_init(const GreedyArgs& a, uint64_t covered_len, int k, hipStream_t s);
+void launch_argmax_step(const GreedyArgs& a, int j, hipStream_t s);
+void launch_cover_step(const GreedyArgs& a, int j, hipStream_t s);
+// Sets left in the node pool by an emit launch (set j: set_len[j] nodes from
+// pool[set_start[j]]).  pool_hist adds their memberships to cnt; pool_cover
+// marks those not yet covered that contain the node of key *best (covered
+// indexed like the sets) and takes them out of the counts of their members.
+void launch_pool_hist(const int32_t* pool, const uint64_t* set_start, const uint32_t* set_len, uint64_t nsets,
+                      uint32_t* cnt, hipStream_t s);
+void launch_pool_cover(const unsigned long long* best, const int32_t* pool, const uint64_t* set_start,
+                       const uint32_t* set_len, uint64_t nsets, uint8_t* covered, uint32_t* cnt, hipStream_t s);
 
 }  // namespace tim

@@ -436,7 +436,9 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
         const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
         const uint32_t tot = __shfl(winc, kWave - 1);
         if (pool_next + tot > pool_end) {
-          const unsigned long long want_n = max(kPoolChunk, (unsigned long long)tot);
+          // tier 0 reserves slices; the deferral tier (large sets, few) exactly what it stores
+          const unsigned long long slice = io.acc == 0 ? (unsigned long long)a.pool_chunk : 0ull;
+          const unsigned long long want_n = max(slice, (unsigned long long)tot);
           unsigned long long got = 0;
           if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want_n);
           got = __shfl(got, 0);
@@ -658,7 +660,7 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
       const uint32_t tot = __shfl(winc, kWave - 1);
       if (tot) {
         if (pool_next + tot > pool_end) {
-          const unsigned long long want_n = max(kPoolChunk, (unsigned long long)tot);
+          const unsigned long long want_n = max((unsigned long long)a.pool_chunk, (unsigned long long)tot);
           unsigned long long got = 0;
           if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want_n);
           got = __shfl(got, 0);

@@ -338,6 +338,76 @@ def test_budget_too_small_is_reported(cfg1):
         assert ei.value.status == tim.EBUDGET
 
 
+# ------------------------------------- NodeSelection under a memory budget --
+def _select_equal(sel, seeds, gains, want):
+    assert np.array_equal(seeds, want["seeds"]) and np.array_equal(gains, want["gains"])
+    assert sel.nodes == want["ns_nodes"] and sel.width == want["ns_width"] and sel.covered == want["ns_covered"]
+
+
+@pytest.mark.parametrize("model", [IC, LT])
+def test_node_select_fully_regenerated(cfg1, model):
+    # resident limit 0: every set is regenerated after every greedy step
+    import paper_1404_0900_amd as tim
+    k, theta = 20, 30000
+    want = oracle.node_select(cfg1, model, 7, k, theta)
+    with tim.Engine(0) as e:
+        e.set_resident_limit(0)
+        dg = e.upload(cfg1)
+        _say(f"node_select regenerated: model={model} k={k} theta={theta}")
+        seeds, gains, sel = e.node_select(dg, model, 7, k, theta)
+    assert sel.resident_sets == 0 and sel.chunk_sets > 0
+    assert sel.regenerated_sets == (k - 1) * theta
+    _select_equal(sel, seeds, gains, want)
+
+
+@pytest.mark.parametrize("model", [IC, LT])
+def test_node_select_resident_prefix_and_chunks(cfg1, model):
+    # a resident prefix with its index plus the rest in regenerated chunks
+    import paper_1404_0900_amd as tim
+    k, theta = 50, 100000
+    want = oracle.node_select(cfg1, model, 8, k, theta)
+    with tim.Engine(0) as e:
+        e.set_resident_limit(theta // 3)
+        dg = e.upload(cfg1)
+        _say(f"node_select prefix: model={model} k={k} theta={theta}")
+        seeds, gains, sel = e.node_select(dg, model, 8, k, theta)
+        assert sel.resident_sets == theta // 3
+        assert sel.regenerated_sets == (k - 1) * (theta - theta // 3)
+        _select_equal(sel, seeds, gains, want)
+        e.set_resident_limit(None)
+        seeds2, gains2, sel2 = e.node_select(dg, model, 8, k, theta)
+        assert sel2.resident_sets == theta and sel2.chunk_sets == 0 and sel2.regenerated_sets == 0
+        _select_equal(sel2, seeds2, gains2, want)
+
+
+@pytest.mark.parametrize("model", [IC, LT])
+def test_node_select_under_budget_uses_many_chunks(cfg1, model):
+    # a budget far below the collection: the plan keeps a prefix and streams
+    # the rest in many chunks, under the budget throughout
+    import paper_1404_0900_amd as tim
+    k, theta, budget = 30, 400000, 12 << 20
+    want = oracle.node_select(cfg1, model, 9, k, theta)
+    with tim.Engine(0, budget_bytes=budget) as e:
+        dg = e.upload(cfg1)
+        _say(f"node_select budget: model={model} k={k} theta={theta} budget={budget}")
+        seeds, gains, sel = e.node_select(dg, model, 9, k, theta)
+        assert e.device_bytes() <= budget
+    _say(f"  resident={sel.resident_sets} chunk={sel.chunk_sets} regenerated={sel.regenerated_sets}")
+    assert 0 < sel.resident_sets < theta
+    assert 0 < sel.chunk_sets and (theta - sel.resident_sets) // sel.chunk_sets >= 4
+    _select_equal(sel, seeds, gains, want)
+
+
+def test_tim_plus_under_budget_cfg1(cfg1):
+    # whole TIM+ (RefineKPT's greedy and NodeSelection) under a small budget
+    import paper_1404_0900_amd as tim
+    with tim.Engine(0, budget_bytes=6 << 20) as e:
+        dg = e.upload(cfg1)
+        r = _run_equal(e, cfg1, dg, IC, 50, 0.5, 1.0, 1)
+        assert e.device_bytes() <= 6 << 20
+    assert r["theta"] > 0
+
+
 def test_max_coverage_large_tiles_overflow_lds_tables(eng):
     # tiles with more distinct nodes than the LDS aggregation tables hold, and
     # a few heavy nodes present in most sets (the hub pattern of RR sets)
