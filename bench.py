@@ -94,6 +94,8 @@ def main():
             out.append((k, time.perf_counter() - t0, rep))
         return out
 
+    phases = {}  # per k: GPU milliseconds of each phase and the collection sizes (last timed step)
+
     for i in range(args.warmup):
         step()
         log(f"warmup {i + 1}/{args.warmup} done")
@@ -107,6 +109,11 @@ def main():
             sets += rep.sets_total
             width += rep.width_total
             per_k[k] += dt
+            phases[str(k)] = {"kpt_ms": round(rep.ms_kpt, 3), "refine_ms": round(rep.ms_refine, 3),
+                              "select_sample_ms": round(rep.ms_select_sample, 3),
+                              "select_greedy_ms": round(rep.ms_select_greedy, 3),
+                              "c_last": int(rep.kpt.c_last), "theta_prime": int(rep.refine.theta_prime),
+                              "theta": int(rep.select.theta), "rr_entries": int(rep.select.nodes)}
         log(f"step {i + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
@@ -152,6 +159,7 @@ def main():
                    "graph_seed": 2, "model": "IC p=1/indeg", "k": list(KS), "eps": EPS, "ell": ELL, "seed": SEED},
         "edges_per_s": round(width / elapsed, 1),
         "tim_plus_s": {str(k): round(per_k[k] / args.steps, 6) for k in KS},
+        "phases": phases,
         "sets_per_step": sets // args.steps,
         "sampler_gpu_ms_per_step": round(sampler_ms / args.steps, 3),
         "index_greedy_gpu_ms_per_step": round((prof.index_ms + prof.greedy_ms) / args.steps, 3),

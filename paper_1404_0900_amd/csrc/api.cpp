@@ -372,33 +372,46 @@ tim_status sample_store(tim_ctx* c, const tim_graph* g, int model, uint64_t seed
 }
 
 // Greedy maximum coverage over a CSR collection in device memory.
-tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off, const int32_t* nodes,
-                  uint64_t total, int k, int32_t* seeds, uint64_t* gains) {
+// Greedy maximum coverage over a collection in device memory, in CSR layout
+// (set_off) or in the node-pool layout of an emit launch (set_start/set_len).
+// k = 1 needs only the coverage counts; larger k builds the inverted index.
+tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off, const uint64_t* set_start,
+                  const uint32_t* set_len, const int32_t* nodes, uint64_t total, int k, int32_t* seeds,
+                  uint64_t* gains) {
   if (nsets >= 0xFFFFFFFFull) return fail(TIM_EINVAL, "more than 2^32-1 sets in one collection");
+  const bool index = k > 1;
   TIM_TRY(ensure(c, c->cnt, (size_t)n * 4, "coverage counts"));
-  TIM_TRY(ensure(c, c->fill, (size_t)n * 4, "index cursors"));
-  TIM_TRY(ensure(c, c->inv_off, (size_t)(n + 1) * 8, "index offsets"));
-  TIM_TRY(ensure(c, c->inv_sets, total * 4, "index entries"));
+  if (index) {
+    TIM_TRY(ensure(c, c->fill, (size_t)n * 4, "index cursors"));
+    TIM_TRY(ensure(c, c->inv_off, (size_t)(n + 1) * 8, "index offsets"));
+    TIM_TRY(ensure(c, c->inv_sets, total * 4, "index entries"));
+    TIM_TRY(ensure(c, c->scan_tmp, tim::scan_temp_bytes((uint64_t)n + 1), "scan"));
+  }
   TIM_TRY(ensure(c, c->covered, nsets, "covered marks"));
   TIM_TRY(ensure(c, c->selected, (size_t)n, "selected marks"));
   TIM_TRY(ensure(c, c->best, (size_t)k * 8, "argmax keys"));
-  TIM_TRY(ensure(c, c->scan_tmp, tim::scan_temp_bytes((uint64_t)n + 1), "scan"));
   tim::GreedyArgs a;
+  memset(&a, 0, sizeof(a));
   a.n = n;
   a.nsets = nsets;
   a.total = total;
   a.set_off = set_off;
+  a.set_start = set_start;
+  a.set_len = set_len;
   a.nodes = nodes;
   a.cnt = c->cnt.as<uint32_t>();
-  a.fill = c->fill.as<uint32_t>();
-  a.inv_off = c->inv_off.as<int64_t>();
-  a.inv_sets = c->inv_sets.as<uint32_t>();
+  if (index) {
+    a.fill = c->fill.as<uint32_t>();
+    a.inv_off = c->inv_off.as<int64_t>();
+    a.inv_sets = c->inv_sets.as<uint32_t>();
+    a.scan_temp = c->scan_tmp.p;
+  }
   a.covered = c->covered.as<uint8_t>();
   a.selected = c->selected.as<uint8_t>();
   a.best = c->best.as<unsigned long long>();
-  a.scan_temp = c->scan_tmp.p;
   if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
-  tim::launch_index(a, c->stream);
+  if (index) tim::launch_index(a, c->stream);
+  else tim::launch_counts(a, c->stream);
   if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[1], c->stream));
   tim::launch_greedy(a, k, c->stream);
   if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[2], c->stream));
@@ -484,16 +497,16 @@ tim_status collection_room(tim_ctx* c, uint64_t* room) {
 
 uint64_t lists_per_set(int model) { return model == TIM_MODEL_IC ? 16 : 8; }
 
-// Peak bytes of the all-resident path for `count` sets of `nodes` entries.
+// Peak bytes of the all-resident path for `count` sets of `nodes` entries
+// (node pool, per-set starts and sizes, inverted index).
 uint64_t resident_bytes(const tim_ctx* c, int64_t n, int model, uint64_t count, uint64_t nodes, int k) {
   const uint64_t launches = (count + kMaxLaunchSets - 1) / kMaxLaunchSets;
   const uint64_t lists = std::min(count, kMaxLaunchSets) * lists_per_set(model);
   const uint64_t emit = count * 12 + (nodes + pool_slack(c, model, count, pick_slice(c, model, count, nodes)) *
                                                  launches) * 4;
-  const uint64_t store = (count + 1) * 8 + nodes * 4;
   const uint64_t index = (uint64_t)n * 17 + 8 + nodes * 4 + count + 8 * (uint64_t)k +
-                         tim::scan_temp_bytes(std::max<uint64_t>(count, (uint64_t)n + 1)) + 17 * 256;
-  return lists + emit + store + index;
+                         tim::scan_temp_bytes((uint64_t)n + 1) + 17 * 256;
+  return lists + emit + index;
 }
 
 // Regenerates sets [from, to) of a phase into the node pool, `*chunk` sets at
@@ -534,18 +547,21 @@ tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t
   TIM_TRY(collection_room(c, &room));
   HIP_TRY(hipEventRecord(c->ev[0], c->stream));
   if (count <= c->resident_limit && resident_bytes(c, n, model, count, expect_nodes, k) <= room) {
+    // the sets stay in the node pool as the samplers left them (no compaction)
     Totals t;
-    TIM_TRY(sample_store(c, g, model, seed, phase, 0, count, expect_nodes, nullptr, &t));
+    TIM_TRY(emit_sets(c, g, model, seed, phase, 0, count, expect_nodes, nullptr, &t));
     HIP_TRY(hipEventRecord(c->ev[1], c->stream));
     st->ms_sample = elapsed_ms(c);
     HIP_TRY(hipEventRecord(c->ev[0], c->stream));
-    TIM_TRY(greedy(c, n, count, c->rr_off.as<int64_t>(), c->rr_nodes.as<int32_t>(), t.nodes, k, seeds, gains));
+    TIM_TRY(greedy(c, n, count, nullptr, c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
+                   c->pool.as<int32_t>(), t.nodes, k, seeds, gains));
     HIP_TRY(hipEventRecord(c->ev[1], c->stream));
     st->ms_greedy = elapsed_ms(c);
     st->nodes = t.nodes;
     st->width = t.width;
     st->resident = count;
-    st->store_bytes = (count + 1) * 8 + t.nodes * 8 + ((uint64_t)n + 1) * 8;
+    st->store_bytes = c->pool.bytes + c->set_start.bytes + c->set_len.bytes +
+                      (k > 1 ? c->inv_sets.bytes + c->inv_off.bytes : 0);
     return TIM_OK;
   }
 
@@ -1064,7 +1080,7 @@ tim_status tim_max_coverage(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t
     HIP_TRY(hipMemcpyAsync(c->rr_off.p, &zero_off, 8, hipMemcpyHostToDevice, c->stream));
     off = c->rr_off.as<int64_t>();
   }
-  return greedy(c, n, nsets, off, d_nodes, (uint64_t)total, k, seeds, gains);
+  return greedy(c, n, nsets, off, nullptr, nullptr, d_nodes, (uint64_t)total, k, seeds, gains);
 }
 
 tim_status tim_kpt_estimate(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double ell,

@@ -144,15 +144,30 @@ __global__ void zero_u64(unsigned long long* p, uint64_t len) {
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0ull;
 }
 
+// ---- views of a collection: set s has len(s) nodes from nodes[start(s)] ----
+struct CsrSets {  // flat CSR (caller collections, resident prefixes)
+  const int64_t* off;
+  const int32_t* nodes;
+  __device__ __forceinline__ int64_t start(uint64_t s) const { return off[s]; }
+  __device__ __forceinline__ uint32_t len(uint64_t s) const { return (uint32_t)(off[s + 1] - off[s]); }
+};
+struct PoolSets {  // node pool as the samplers leave it (per-set start and size)
+  const uint64_t* st;
+  const uint32_t* ln;
+  const int32_t* nodes;
+  __device__ __forceinline__ int64_t start(uint64_t s) const { return (int64_t)st[s]; }
+  __device__ __forceinline__ uint32_t len(uint64_t s) const { return ln[s]; }
+};
+
 // ---- per-tile aggregation of node updates in LDS ----
 // A tile's updates to the same node (hub nodes recur in many RR sets) are
-// summed in an LDS open-addressing table and reach device memory as one
-// atomic per distinct node per tile.  Nodes that find the table full fall
-// back to direct atomics.
-constexpr int kAggLog = 11;
+// summed in an LDS open-addressing table (at most about half full for a tile
+// of typical sets) and reach device memory as one atomic per distinct node
+// per tile.  Nodes that find the table full fall back to direct atomics.
+constexpr int kAggLog = 12;
 constexpr int kAgg = 1 << kAggLog;
-constexpr int kTileSets = 128;   // sets per tile (scatter and cover)
-constexpr int kTileEntries = 2048;  // entries per tile (histogram)
+constexpr int kTileSets = 128;      // sets per tile (set-tiled kernels)
+constexpr int kTileEntries = 2048;  // entries per tile (flat histogram)
 
 __device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert) {
   const uint32_t key = u + 1u;
@@ -171,101 +186,11 @@ __device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert)
 }
 
 __device__ __forceinline__ void agg_clear(uint32_t* a, uint32_t* b) {
-  for (int i = threadIdx.x; i < kAgg; i += blockDim.x) {
-    a[i] = 0u;
-    if (b) b[i] = 0u;
-  }
-}
-
-// cnt[u] = number of sets containing u (sets never repeat a node).
-__global__ __launch_bounds__(kThreads) void hist_kernel(const int32_t* nodes, uint64_t total, uint32_t* cnt) {
-  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
-  for (uint64_t t0 = (uint64_t)blockIdx.x * kTileEntries; t0 < total; t0 += (uint64_t)gridDim.x * kTileEntries) {
-    agg_clear(s_key, s_cnt);
-    __syncthreads();
-    const uint64_t t1 = min(t0 + (uint64_t)kTileEntries, total);
-    for (uint64_t e = t0 + threadIdx.x; e < t1; e += kThreads) {
-      const uint32_t u = (uint32_t)nodes[e];
-      const int slot = agg_slot(s_key, u, true);
-      if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
-      else atomicAdd(&cnt[u], 1u);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kAgg; i += kThreads)
-      if (s_key[i]) atomicAdd(&cnt[s_key[i] - 1u], s_cnt[i]);
-    __syncthreads();
-  }
-}
-
-// Position of entry e among the tile's sets: the set j with off[j] <= e < off[j+1].
-__device__ __forceinline__ int tile_set_of(const int64_t* s_off, int ns, int64_t e) {
-  int lo = 0, hi = ns - 1;
-  while (lo < hi) {
-    const int mid = (lo + hi + 1) >> 1;
-    if (s_off[mid] <= e) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// inv_sets[inv_off[u] ..] = the sets containing u, in no particular order.
-__global__ __launch_bounds__(kThreads) void scatter_kernel(const int64_t* set_off, const int32_t* nodes, uint64_t nsets,
-                                                           const int64_t* inv_off, uint32_t* fill,
-                                                           uint32_t* inv_sets) {
-  __shared__ int64_t s_off[kTileSets + 1];
-  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg], s_base[kAgg];
-  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
-    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
-    agg_clear(s_key, s_cnt);
-    for (int i = threadIdx.x; i <= ns; i += kThreads) s_off[i] = set_off[s0 + i];
-    __syncthreads();
-    const int64_t e0 = s_off[0], e1 = s_off[ns];
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
-      const int slot = agg_slot(s_key, (uint32_t)nodes[e], true);
-      if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
-    }
-    __syncthreads();
-    for (int i = threadIdx.x; i < kAgg; i += kThreads) {
-      if (s_key[i]) s_base[i] = atomicAdd(&fill[s_key[i] - 1u], s_cnt[i]);
-      s_cnt[i] = 0u;
-    }
-    __syncthreads();
-    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
-      const uint32_t u = (uint32_t)nodes[e];
-      const uint32_t s = (uint32_t)(s0 + (uint64_t)tile_set_of(s_off, ns, e));
-      const int slot = agg_slot(s_key, u, false);
-      uint64_t pos;
-      if (slot >= 0) pos = (uint64_t)inv_off[u] + s_base[slot] + atomicAdd(&s_cnt[slot], 1u);
-      else pos = (uint64_t)inv_off[u] + atomicAdd(&fill[u], 1u);
-      inv_sets[pos] = s;
-    }
-    __syncthreads();
-  }
-}
-
-// Key of node u: 0 if selected, else count<<32 | (0xFFFFFFFF - u), so the
-// maximum key is the largest count with the lowest id; unselected keys > 0.
-__global__ __launch_bounds__(kThreads) void argmax_kernel(const uint32_t* cnt, const uint8_t* selected, int64_t n,
-                                                          unsigned long long* best) {
-  unsigned long long key = 0;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n; u += stride) {
-    if (selected[u]) continue;
-    const unsigned long long k = ((unsigned long long)cnt[u] << 32) | (0xFFFFFFFFull - (unsigned long long)u);
-    key = k > key ? k : key;
-  }
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const unsigned long long y = __shfl_xor(key, o, 64);
-    key = y > key ? y : key;
-  }
-  __shared__ unsigned long long red[kThreads / 64];
-  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
-  if (lane == 0) red[wv] = key;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    for (int w = 0; w < kThreads / 64; ++w) key = red[w] > key ? red[w] : key;
-    if (key) atomicMax(best, key);
+  uint4* a4 = reinterpret_cast<uint4*>(a);
+  uint4* b4 = reinterpret_cast<uint4*>(b);
+  for (int i = threadIdx.x; i < kAgg / 4; i += blockDim.x) {
+    a4[i] = make_uint4(0u, 0u, 0u, 0u);
+    if (b) b4[i] = make_uint4(0u, 0u, 0u, 0u);
   }
 }
 
@@ -294,88 +219,58 @@ __device__ __forceinline__ void tile_prefix(uint32_t len, int64_t start, int64_t
   __syncthreads();
 }
 
-// Decrements of a tile's sets (prefix from tile_prefix): one per member
-// other than v, summed per node in LDS.
-__device__ __forceinline__ void tile_decrement(const int32_t* nodes, const int64_t* s_start, const int64_t* s_pre,
-                                               int64_t v, uint32_t* s_key, uint32_t* s_cnt, uint32_t* cnt) {
-  const int64_t tot = s_pre[kTileSets];
+// Position of tile entry e among the tile's sets: the set j with
+// s_pre[j] <= e < s_pre[j+1].
+__device__ __forceinline__ int tile_set_of(const int64_t* s_pre, int ns, int64_t e) {
+  int lo = 0, hi = ns - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (s_pre[mid] <= e) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+struct TileShared {
+  int64_t start[kTileSets];
+  int64_t pre[kTileSets + 1];
+  uint32_t wtot[kThreads / 64];
+  uint32_t key[kAgg], cnt[kAgg];
+};
+
+// Adds (sign +1) or subtracts the memberships of the tile's listed sets (prefix
+// from tile_prefix) to cnt, skipping node `skip`.
+template <bool kAdd>
+__device__ __forceinline__ void tile_apply(const int32_t* nodes, TileShared& t, int64_t skip, uint32_t* cnt) {
+  const int64_t tot = t.pre[kTileSets];
   for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
-    const int j = tile_set_of(s_pre, kTileSets, e);
-    const int32_t u = nodes[s_start[j] + (e - s_pre[j])];
-    if (u == v) continue;
-    const int slot = agg_slot(s_key, (uint32_t)u, true);
-    if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
+    const int j = tile_set_of(t.pre, kTileSets, e);
+    const int32_t u = nodes[t.start[j] + (e - t.pre[j])];
+    if (u == skip) continue;
+    const int slot = agg_slot(t.key, (uint32_t)u, true);
+    if (slot >= 0) atomicAdd(&t.cnt[slot], 1u);
+    else if (kAdd) atomicAdd(&cnt[u], 1u);
     else atomicSub(&cnt[u], 1u);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kAgg; i += kThreads)
-    if (s_key[i]) atomicSub(&cnt[s_key[i] - 1u], s_cnt[i]);
+  for (int i = threadIdx.x; i < kAgg; i += kThreads) {
+    if (t.key[i]) {
+      if (kAdd) atomicAdd(&cnt[t.key[i] - 1u], t.cnt[i]);
+      else atomicSub(&cnt[t.key[i] - 1u], t.cnt[i]);
+    }
+  }
   __syncthreads();
 }
 
-__device__ __forceinline__ int64_t node_of_key(unsigned long long key) {
-  return (int64_t)(0xFFFFFFFFull - (key & 0xFFFFFFFFull));
-}
-
-// The chosen node v covers the sets listed in inv_sets[inv_off[v] ..]: mark
-// those not covered yet and take them out of the counts of their members
-// (v's own count is left alone: v is never chosen again).
-__global__ __launch_bounds__(kThreads) void cover_kernel(const unsigned long long* best, const int64_t* inv_off,
-                                                         const uint32_t* inv_sets, const int64_t* set_off,
-                                                         const int32_t* nodes, uint8_t* covered, uint8_t* selected,
-                                                         uint32_t* cnt) {
-  __shared__ int64_t s_start[kTileSets];
-  __shared__ int64_t s_pre[kTileSets + 1];
+// cnt[u] += number of sets containing u, over a flat entry array.
+__global__ __launch_bounds__(kThreads) void hist_flat_kernel(const int32_t* nodes, uint64_t total, uint32_t* cnt) {
   __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
-  __shared__ uint32_t s_wtot[kThreads / 64];
-  if (*best == 0ull) return;  // no unselected node (cannot happen for k <= n)
-  const int64_t v = node_of_key(*best);
-  if (blockIdx.x == 0 && threadIdx.x == 0) selected[v] = 1u;
-  const int64_t lo = inv_off[v], hi = inv_off[v + 1];
-  for (int64_t i0 = lo + (int64_t)blockIdx.x * kTileSets; i0 < hi; i0 += (int64_t)gridDim.x * kTileSets) {
-    const int ni = (int)min((int64_t)kTileSets, hi - i0);
+  for (uint64_t t0 = (uint64_t)blockIdx.x * kTileEntries; t0 < total; t0 += (uint64_t)gridDim.x * kTileEntries) {
     agg_clear(s_key, s_cnt);
-    // newly covered sets of this tile and their sizes
-    uint32_t len = 0;
-    int64_t start = 0;
-    if (threadIdx.x < ni) {
-      const uint32_t sid = inv_sets[i0 + threadIdx.x];
-      if (!covered[sid]) {
-        covered[sid] = 1u;
-        start = set_off[sid];
-        len = (uint32_t)(set_off[sid + 1] - start);
-      }
-    }
-    tile_prefix(len, start, s_start, s_pre, s_wtot);
-    tile_decrement(nodes, s_start, s_pre, v, s_key, s_cnt, cnt);
-  }
-}
-
-__global__ void select_kernel(const unsigned long long* best, uint8_t* selected) {
-  if (threadIdx.x == 0 && *best != 0ull) selected[node_of_key(*best)] = 1u;
-}
-
-// cnt[u] += number of pool sets containing u.
-__global__ __launch_bounds__(kThreads) void pool_hist_kernel(const int32_t* pool, const uint64_t* set_start,
-                                                             const uint32_t* set_len, uint64_t nsets, uint32_t* cnt) {
-  __shared__ int64_t s_start[kTileSets];
-  __shared__ int64_t s_pre[kTileSets + 1];
-  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
-  __shared__ uint32_t s_wtot[kThreads / 64];
-  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
-    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
-    agg_clear(s_key, s_cnt);
-    uint32_t len = 0;
-    int64_t start = 0;
-    if (threadIdx.x < ns) {
-      start = (int64_t)set_start[s0 + threadIdx.x];
-      len = set_len[s0 + threadIdx.x];
-    }
-    tile_prefix(len, start, s_start, s_pre, s_wtot);
-    const int64_t tot = s_pre[kTileSets];
-    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
-      const int j = tile_set_of(s_pre, kTileSets, e);
-      const uint32_t u = (uint32_t)pool[s_start[j] + (e - s_pre[j])];
+    __syncthreads();
+    const uint64_t t1 = min(t0 + (uint64_t)kTileEntries, total);
+    for (uint64_t e = t0 + threadIdx.x; e < t1; e += kThreads) {
+      const uint32_t u = (uint32_t)nodes[e];
       const int slot = agg_slot(s_key, u, true);
       if (slot >= 0) atomicAdd(&s_cnt[slot], 1u);
       else atomicAdd(&cnt[u], 1u);
@@ -387,34 +282,171 @@ __global__ __launch_bounds__(kThreads) void pool_hist_kernel(const int32_t* pool
   }
 }
 
-// Pool sets not covered yet that contain the chosen node v: mark them and
-// take them out of the counts of their members.
-__global__ __launch_bounds__(kThreads) void pool_cover_kernel(const unsigned long long* best, const int32_t* pool,
-                                                              const uint64_t* set_start, const uint32_t* set_len,
+// cnt[u] += number of sets containing u, in tiles of sets.
+template <class V>
+__global__ __launch_bounds__(kThreads) void hist_sets_kernel(V sets, uint64_t nsets, uint32_t* cnt) {
+  __shared__ TileShared t;
+  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
+    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
+    agg_clear(t.key, t.cnt);
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < ns) {
+      start = sets.start(s0 + threadIdx.x);
+      len = sets.len(s0 + threadIdx.x);
+    }
+    tile_prefix(len, start, t.start, t.pre, t.wtot);
+    tile_apply<true>(sets.nodes, t, -1, cnt);
+  }
+}
+
+// inv_sets[inv_off[u] ..] = the sets containing u, in no particular order.
+template <class V>
+__global__ __launch_bounds__(kThreads) void scatter_kernel(V sets, uint64_t nsets, const int64_t* inv_off,
+                                                           uint32_t* fill, uint32_t* inv_sets) {
+  __shared__ TileShared t;
+  __shared__ uint32_t s_base[kAgg];
+  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
+    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
+    agg_clear(t.key, t.cnt);
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < ns) {
+      start = sets.start(s0 + threadIdx.x);
+      len = sets.len(s0 + threadIdx.x);
+    }
+    tile_prefix(len, start, t.start, t.pre, t.wtot);
+    const int64_t tot = t.pre[kTileSets];
+    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+      const int j = tile_set_of(t.pre, kTileSets, e);
+      const int slot = agg_slot(t.key, (uint32_t)sets.nodes[t.start[j] + (e - t.pre[j])], true);
+      if (slot >= 0) atomicAdd(&t.cnt[slot], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAgg; i += kThreads) {
+      if (t.key[i]) s_base[i] = atomicAdd(&fill[t.key[i] - 1u], t.cnt[i]);
+      t.cnt[i] = 0u;
+    }
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+      const int j = tile_set_of(t.pre, kTileSets, e);
+      const uint32_t u = (uint32_t)sets.nodes[t.start[j] + (e - t.pre[j])];
+      const uint32_t sid = (uint32_t)(s0 + (uint64_t)j);
+      const int slot = agg_slot(t.key, u, false);
+      uint64_t pos;
+      if (slot >= 0) pos = (uint64_t)inv_off[u] + s_base[slot] + atomicAdd(&t.cnt[slot], 1u);
+      else pos = (uint64_t)inv_off[u] + atomicAdd(&fill[u], 1u);
+      inv_sets[pos] = sid;
+    }
+    __syncthreads();
+  }
+}
+
+// Key of node u: 0 if selected, else count<<32 | (0xFFFFFFFF - u), so the
+// maximum key is the largest count with the lowest id; unselected keys > 0.
+// Few blocks, 4 nodes per thread and load: one atomicMax per block.
+__global__ __launch_bounds__(kThreads) void argmax_kernel(const uint32_t* cnt, const uint8_t* selected, int64_t n,
+                                                          unsigned long long* best) {
+  unsigned long long key = 0;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t n4 = n >> 2;
+  const uint4* c4 = reinterpret_cast<const uint4*>(cnt);
+  const uint32_t* s4 = reinterpret_cast<const uint32_t*>(selected);
+  for (int64_t i = tid; i < n4; i += stride) {
+    const uint4 c = c4[i];
+    const uint32_t sel = s4[i];
+    const uint32_t cv[4] = {c.x, c.y, c.z, c.w};
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      const unsigned long long u = (unsigned long long)(4 * i + w);
+      const unsigned long long k = ((unsigned long long)cv[w] << 32) | (0xFFFFFFFFull - u);
+      if (!((sel >> (8 * w)) & 0xFFu)) key = k > key ? k : key;
+    }
+  }
+  for (int64_t u = 4 * n4 + tid; u < n; u += stride) {
+    if (selected[u]) continue;
+    const unsigned long long k = ((unsigned long long)cnt[u] << 32) | (0xFFFFFFFFull - (unsigned long long)u);
+    key = k > key ? k : key;
+  }
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    const unsigned long long y = __shfl_xor(key, o, 64);
+    key = y > key ? y : key;
+  }
+  __shared__ unsigned long long red[kThreads / 64];
+  const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
+  if (lane == 0) red[wv] = key;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 0; w < kThreads / 64; ++w) key = red[w] > key ? red[w] : key;
+    if (key) atomicMax(best, key);
+  }
+}
+
+__device__ __forceinline__ int64_t node_of_key(unsigned long long key) {
+  return (int64_t)(0xFFFFFFFFull - (key & 0xFFFFFFFFull));
+}
+
+// The chosen node v covers the sets listed in inv_sets[inv_off[v] ..]: mark
+// those not covered yet and take them out of the counts of their members
+// (v's own count is left alone: v is never chosen again).
+template <class V>
+__global__ __launch_bounds__(kThreads) void cover_kernel(const unsigned long long* best, const int64_t* inv_off,
+                                                         const uint32_t* inv_sets, V sets, uint8_t* covered,
+                                                         uint8_t* selected, uint32_t* cnt) {
+  __shared__ TileShared t;
+  if (*best == 0ull) return;  // no unselected node (cannot happen for k <= n)
+  const int64_t v = node_of_key(*best);
+  if (blockIdx.x == 0 && threadIdx.x == 0) selected[v] = 1u;
+  const int64_t lo = inv_off[v], hi = inv_off[v + 1];
+  for (int64_t i0 = lo + (int64_t)blockIdx.x * kTileSets; i0 < hi; i0 += (int64_t)gridDim.x * kTileSets) {
+    const int ni = (int)min((int64_t)kTileSets, hi - i0);
+    agg_clear(t.key, t.cnt);
+    // newly covered sets of this tile and their sizes
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < ni) {
+      const uint32_t sid = inv_sets[i0 + threadIdx.x];
+      if (!covered[sid]) {
+        covered[sid] = 1u;
+        start = sets.start(sid);
+        len = sets.len(sid);
+      }
+    }
+    tile_prefix(len, start, t.start, t.pre, t.wtot);
+    tile_apply<false>(sets.nodes, t, v, cnt);
+  }
+}
+
+__global__ void select_kernel(const unsigned long long* best, uint8_t* selected) {
+  if (threadIdx.x == 0 && *best != 0ull) selected[node_of_key(*best)] = 1u;
+}
+
+// Sets (pool layout) not covered yet that contain the chosen node v: mark
+// them and take them out of the counts of their members.
+__global__ __launch_bounds__(kThreads) void scan_cover_kernel(const unsigned long long* best, PoolSets sets,
                                                               uint64_t nsets, uint8_t* covered, uint32_t* cnt) {
-  __shared__ int64_t s_start[kTileSets];
-  __shared__ int64_t s_pre[kTileSets + 1];
-  __shared__ uint32_t s_key[kAgg], s_cnt[kAgg];
-  __shared__ uint32_t s_wtot[kThreads / 64];
+  __shared__ TileShared t;
   __shared__ uint32_t s_hit[kTileSets];
   if (*best == 0ull) return;
   const int64_t v = node_of_key(*best);
   for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
     const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
-    agg_clear(s_key, s_cnt);
+    agg_clear(t.key, t.cnt);
     uint32_t len = 0;
     int64_t start = 0;
     if (threadIdx.x < ns && !covered[s0 + threadIdx.x]) {
-      start = (int64_t)set_start[s0 + threadIdx.x];
-      len = set_len[s0 + threadIdx.x];
+      start = sets.start(s0 + threadIdx.x);
+      len = sets.len(s0 + threadIdx.x);
     }
     if (threadIdx.x < kTileSets) s_hit[threadIdx.x] = 0u;
-    tile_prefix(len, start, s_start, s_pre, s_wtot);
+    tile_prefix(len, start, t.start, t.pre, t.wtot);
     // membership of v
-    const int64_t tot = s_pre[kTileSets];
+    const int64_t tot = t.pre[kTileSets];
     for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
-      const int j = tile_set_of(s_pre, kTileSets, e);
-      if (pool[s_start[j] + (e - s_pre[j])] == v) s_hit[j] = 1u;
+      const int j = tile_set_of(t.pre, kTileSets, e);
+      if (sets.nodes[t.start[j] + (e - t.pre[j])] == v) s_hit[j] = 1u;
     }
     __syncthreads();
     bool hit = false;
@@ -422,8 +454,8 @@ __global__ __launch_bounds__(kThreads) void pool_cover_kernel(const unsigned lon
       hit = s_hit[threadIdx.x] != 0u;
       if (hit) covered[s0 + threadIdx.x] = 1u;
     }
-    tile_prefix(hit ? len : 0u, start, s_start, s_pre, s_wtot);
-    tile_decrement(pool, s_start, s_pre, v, s_key, s_cnt, cnt);
+    tile_prefix(hit ? len : 0u, start, t.start, t.pre, t.wtot);
+    tile_apply<false>(sets.nodes, t, v, cnt);
   }
 }
 
@@ -463,21 +495,44 @@ void launch_set_sizes(const int64_t* set_off, uint32_t* sizes, uint64_t nsets, h
   hipLaunchKernelGGL(set_sizes_kernel, dim3(grid_for(nsets, 8192)), dim3(kThreads), 0, s, set_off, sizes, nsets);
 }
 
-void launch_index(const GreedyArgs& a, hipStream_t s) {
+namespace {
+
+CsrSets csr_of(const GreedyArgs& a) { return CsrSets{a.set_off, a.nodes}; }
+PoolSets pool_of(const GreedyArgs& a) { return PoolSets{a.set_start, a.set_len, a.nodes}; }
+
+unsigned tile_grid(uint64_t items, uint64_t per_tile) {
+  return (unsigned)std::max<uint64_t>(1, std::min<uint64_t>((items + per_tile - 1) / per_tile, 8192));
+}
+
+}  // namespace
+
+void launch_counts(const GreedyArgs& a, hipStream_t s) {
   const uint64_t n = (uint64_t)a.n;
   hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.cnt, n);
+  if (!a.nsets) return;
+  if (a.set_off) {
+    if (a.total)
+      hipLaunchKernelGGL(hist_flat_kernel, dim3(tile_grid(a.total, kTileEntries)), dim3(kThreads), 0, s, a.nodes,
+                         a.total, a.cnt);
+  } else {
+    hipLaunchKernelGGL(hist_sets_kernel<PoolSets>, dim3(tile_grid(a.nsets, kTileSets)), dim3(kThreads), 0, s,
+                       pool_of(a), a.nsets, a.cnt);
+  }
+}
+
+void launch_index(const GreedyArgs& a, hipStream_t s) {
+  const uint64_t n = (uint64_t)a.n;
+  launch_counts(a, s);
   hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.fill, n);
-  if (a.total) {
-    const uint64_t tiles = (a.total + kTileEntries - 1) / kTileEntries;
-    hipLaunchKernelGGL(hist_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s, a.nodes,
-                       a.total, a.cnt);
-  }
   launch_scan_u32_to_i64(a.cnt, a.inv_off, n, a.scan_temp, s);
-  if (a.nsets) {
-    const uint64_t tiles = (a.nsets + kTileSets - 1) / kTileSets;
-    hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s,
-                       a.set_off, a.nodes, a.nsets, a.inv_off, a.fill, a.inv_sets);
-  }
+  if (!a.nsets) return;
+  const unsigned grid = tile_grid(a.nsets, kTileSets);
+  if (a.set_off)
+    hipLaunchKernelGGL(scatter_kernel<CsrSets>, dim3(grid), dim3(kThreads), 0, s, csr_of(a), a.nsets, a.inv_off,
+                       a.fill, a.inv_sets);
+  else
+    hipLaunchKernelGGL(scatter_kernel<PoolSets>, dim3(grid), dim3(kThreads), 0, s, pool_of(a), a.nsets, a.inv_off,
+                       a.fill, a.inv_sets);
 }
 
 void launch_zero_counts(uint32_t* cnt, int64_t n, hipStream_t s) {
@@ -492,46 +547,49 @@ void launch_greedy_init(const GreedyArgs& a, uint64_t covered_len, int k, hipStr
   hipLaunchKernelGGL(zero_u64, dim3(1), dim3(kThreads), 0, s, a.best, (uint64_t)k);
 }
 
+namespace {
+void launch_argmax(const GreedyArgs& a, int j, hipStream_t s) {
+  const uint64_t n4 = ((uint64_t)a.n + 3) / 4;
+  hipLaunchKernelGGL(argmax_kernel, dim3(grid_for(n4, 256)), dim3(kThreads), 0, s, a.cnt, a.selected, a.n,
+                     a.best + j);
+}
+}  // namespace
+
 void launch_argmax_step(const GreedyArgs& a, int j, hipStream_t s) {
-  hipLaunchKernelGGL(argmax_kernel, dim3(grid_for((uint64_t)a.n, 2048)), dim3(kThreads), 0, s, a.cnt, a.selected,
-                     a.n, a.best + j);
+  launch_argmax(a, j, s);
   hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a.best + j, a.selected);
 }
 
 void launch_cover_step(const GreedyArgs& a, int j, hipStream_t s) {
   if (!a.nsets) return;
-  hipLaunchKernelGGL(cover_kernel, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets, a.set_off,
-                     a.nodes, a.covered, a.selected, a.cnt);
+  if (a.set_off)
+    hipLaunchKernelGGL(cover_kernel<CsrSets>, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
+                       csr_of(a), a.covered, a.selected, a.cnt);
+  else
+    hipLaunchKernelGGL(cover_kernel<PoolSets>, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
+                       pool_of(a), a.covered, a.selected, a.cnt);
 }
 
 void launch_pool_hist(const int32_t* pool, const uint64_t* set_start, const uint32_t* set_len, uint64_t nsets,
                       uint32_t* cnt, hipStream_t s) {
   if (!nsets) return;
-  const uint64_t tiles = (nsets + kTileSets - 1) / kTileSets;
-  hipLaunchKernelGGL(pool_hist_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s, pool,
-                     set_start, set_len, nsets, cnt);
+  hipLaunchKernelGGL(hist_sets_kernel<PoolSets>, dim3(tile_grid(nsets, kTileSets)), dim3(kThreads), 0, s,
+                     PoolSets{set_start, set_len, pool}, nsets, cnt);
 }
 
 void launch_pool_cover(const unsigned long long* best, const int32_t* pool, const uint64_t* set_start,
                        const uint32_t* set_len, uint64_t nsets, uint8_t* covered, uint32_t* cnt, hipStream_t s) {
   if (!nsets) return;
-  const uint64_t tiles = (nsets + kTileSets - 1) / kTileSets;
-  hipLaunchKernelGGL(pool_cover_kernel, dim3((unsigned)std::min<uint64_t>(tiles, 8192)), dim3(kThreads), 0, s, best,
-                     pool, set_start, set_len, nsets, covered, cnt);
+  hipLaunchKernelGGL(scan_cover_kernel, dim3(tile_grid(nsets, kTileSets)), dim3(kThreads), 0, s, best,
+                     PoolSets{set_start, set_len, pool}, nsets, covered, cnt);
 }
 
 void launch_greedy(const GreedyArgs& a, int k, hipStream_t s) {
-  const uint64_t n = (uint64_t)a.n;
-  if (a.nsets) hipLaunchKernelGGL(zero_u8, dim3(grid_for(a.nsets, 4096)), dim3(kThreads), 0, s, a.covered, a.nsets);
-  hipLaunchKernelGGL(zero_u8, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.selected, n);
-  hipLaunchKernelGGL(zero_u64, dim3(1), dim3(kThreads), 0, s, a.best, (uint64_t)k);
-  const unsigned gmax = grid_for(n, 2048);
+  launch_greedy_init(a, a.nsets, k, s);
   for (int j = 0; j < k; ++j) {
-    hipLaunchKernelGGL(argmax_kernel, dim3(gmax), dim3(kThreads), 0, s, a.cnt, a.selected, a.n, a.best + j);
+    launch_argmax(a, j, s);
     // the last choice changes no later step: its cover pass is skipped
-    if (j + 1 < k)
-      hipLaunchKernelGGL(cover_kernel, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
-                         a.set_off, a.nodes, a.covered, a.selected, a.cnt);
+    if (j + 1 < k) launch_cover_step(a, j, s);
   }
 }
 

@@ -110,8 +110,12 @@ void launch_set_sizes(const int64_t* set_off, uint32_t* sizes, uint64_t nsets, h
 struct GreedyArgs {
   int64_t n;
   uint64_t nsets;
-  uint64_t total;      // entries of the collection (set_off[nsets])
+  uint64_t total;      // entries of the collection
+  // layout: CSR (set_off, n+1 offsets into nodes) if set_off is set, else the
+  // node pool of an emit launch (set s: set_len[s] nodes from nodes[set_start[s]])
   const int64_t* set_off;
+  const uint64_t* set_start;
+  const uint32_t* set_len;
   const int32_t* nodes;
   uint32_t* cnt;       // n: coverage counts
   uint32_t* fill;      // n: scatter cursors
@@ -122,6 +126,8 @@ struct GreedyArgs {
   unsigned long long* best;  // k packed (count, ~id) keys
   void* scan_temp;
 };
+// Coverage counts only (the greedy of k = 1 needs no index).
+void launch_counts(const GreedyArgs& a, hipStream_t s);
 void launch_index(const GreedyArgs& a, hipStream_t s);
 void launch_greedy(const GreedyArgs& a, int k, hipStream_t s);
 // The same greedy one step at a time, for collections of which only sets

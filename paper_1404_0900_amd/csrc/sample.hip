@@ -132,6 +132,9 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
   return -1;
 }
 
+// One bit of a 64-bit membership signature: a clear bit proves absence.
+__device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
+
 struct Acc {
   u128 kappa = 0;
   unsigned long long width = 0, nodes = 0, covered = 0;
@@ -321,6 +324,7 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
   unsigned long long rel = 0;
   SetStream st = make_set_stream(a.phase, a.first);
   int head = 0, tail_r = 0;                  // queue cursor; queue length (hash-free variant)
+  uint64_t ssig = 0;                         // signature of the queued nodes (hash-free variant)
   uint32_t G = 0, done_items = 0, gsum = 0;  // groups of the current batch / done / of the set so far
   // lane state: this lane's node of the current batch
   uint32_t ea = 0, d = 0, ng = 0, incl = 0;
@@ -346,6 +350,7 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
           }
         }
         tail_r = 1;
+        ssig = sig_bit(root);
         has = true;
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
         bad = false;
@@ -513,25 +518,62 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
           }
         }
       } else if (seg_bits<S>(__ballot(live[0] || live[1] || live[2] || live[3]), sw) != 0ull) {
-        // the segment's live edges, one at a time: append the source unless
-        // the queue already holds it
+        // A live source whose signature bit is clear in the set's signature
+        // and used by no other live source of this step is new: those are
+        // appended at once.  The rest are looked up in the queue one at a time.
+        uint64_t bits[4], once = 0ull, twice = 0ull;
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          uint64_t m = seg_bits<S>(__ballot(live[w]), sw);
-          while (m) {
-            const int src_lane = __ffsll((unsigned long long)m) - 1;
-            m &= m - 1ull;
-            const int32_t u = __shfl(sv[w], src_lane, S);
-            bool found = false;
-            for (int i = sl; i < tail_r; i += S) found |= q[i] == u;
-            if (seg_bits<S>(__ballot(found), sw) == 0ull) {
-              if (tail_r < Q) {
-                if (is_leader) q[tail_r] = u;
-                ++tail_r;
-                wave_sync();
-                if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
-              } else {
-                lbad = true;
+          bits[w] = live[w] ? sig_bit(sv[w]) : 0ull;
+          twice |= once & bits[w];
+          once |= bits[w];
+        }
+#pragma unroll
+        for (int o = 1; o < S; o <<= 1) {
+          const uint64_t o2 = __shfl_xor(once, o, S), t2 = __shfl_xor(twice, o, S);
+          twice |= t2 | (once & o2);
+          once |= o2;
+        }
+        bool fast[4];
+        uint32_t nfast = 0;
+#pragma unroll
+        for (int w = 0; w < 4; ++w) {
+          fast[w] = live[w] && ((ssig | twice) & bits[w]) == 0ull;
+          nfast += fast[w] ? 1u : 0u;
+        }
+        const uint32_t fincl = seg_incl_scan<S>(nfast, sl);
+        const uint32_t ftot = __shfl(fincl, S - 1, S);
+        ssig |= once;
+        if (tail_r + (int)ftot > Q) {
+          lbad = true;
+        } else {
+          int pos = tail_r + (int)(fincl - nfast);
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            if (!fast[w]) continue;
+            q[pos++] = sv[w];
+            if (MODE == kModeCover && in_seed(a.seed_bits, sv[w])) lhit = true;
+          }
+          tail_r += (int)ftot;
+          wave_sync();
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            uint64_t m = seg_bits<S>(__ballot(live[w] && !fast[w]), sw);
+            while (m) {
+              const int src_lane = __ffsll((unsigned long long)m) - 1;
+              m &= m - 1ull;
+              const int32_t u = __shfl(sv[w], src_lane, S);
+              bool found = false;
+              for (int i = sl; i < tail_r; i += S) found |= q[i] == u;
+              if (seg_bits<S>(__ballot(found), sw) == 0ull) {
+                if (tail_r < Q) {
+                  if (is_leader) q[tail_r] = u;
+                  ++tail_r;
+                  wave_sync();
+                  if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+                } else {
+                  lbad = true;
+                }
               }
             }
           }
@@ -563,7 +605,6 @@ __global__ __launch_bounds__(kSegThreads) void kappa_reduce_kernel(SampleArgs a)
 // ------------------------------------------------------------------------
 // LT, tier 0: one chain per lane.
 // ------------------------------------------------------------------------
-__device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
 
 template <int MODE>
 __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, TierIO io) {
