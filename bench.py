@@ -27,13 +27,14 @@ import hashlib
 KS = (1, 10, 50)
 EPS, ELL, SEED = 0.2, 1.0, 2
 HBM_PEAK_GBS = 8000.0
+SEG_GROUPS = 1  # 4-edge groups per lane and step of the IC segment kernels (kSegGroups)
 MODES = ("widths", "store", "cover")
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs of this benchmark (scaled by a plain-copy calibration; see
 # profiles/ic_seg_kernel_chunglu_n1e6_m1e7.md).  Valid only for the kernel
 # sources they were taken on.
-TRAFFIC = {"kernel": "ic_seg_kernel<0, true, 8, 128, 0, 256> (widths)", "sources_sha256_16": "becfcd9cfdcd9bc9",
-           "fetch_bytes": 554121180, "write_bytes": 16698417}
+TRAFFIC = {"kernel": "ic_seg_kernel<0, true, 8, 128, 0, 256, 1> (widths)", "sources_sha256_16": "52dee0384f87f702",
+           "fetch_bytes": 553491447, "write_bytes": 16634294}
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/engine.hpp")
 
@@ -47,7 +48,8 @@ def sources_sha():
 
 
 def kernel_name(model, mode):
-    """Tier-0 sampler kernel of (model, mode) as rocprofv3 lists it (template arguments: mode, WC, S, Q, log2 H)."""
+    """Tier-0 sampler kernel of (model, mode) as rocprofv3 lists it (template arguments: mode, WC, lanes per set,
+    queue length, log2 of the hash size, group limit, groups per lane)."""
     if model == 1:
         return f"lt_lane_kernel<{mode}> ({MODES[mode]})"
     lanes = int(os.environ.get("TIM_IC_SEG_LANES", "8"))
@@ -55,7 +57,7 @@ def kernel_name(model, mode):
     q = {4: 64, 8: 128, 16: 128, 32: 256, 64: 512}[lanes]
     hlog = {4: 0, 8: 0, 16: 8, 32: 9, 64: 10}[lanes]
     gmax = {4: 256, 8: 256, 16: 512, 32: 1024, 64: 2048}[lanes]
-    return f"ic_seg_kernel<{mode}, true, {lanes}, {q}, {hlog}, {gmax}> ({MODES[mode]})"
+    return f"ic_seg_kernel<{mode}, true, {lanes}, {q}, {hlog}, {gmax}, {SEG_GROUPS}> ({MODES[mode]})"
 
 
 def log(msg):

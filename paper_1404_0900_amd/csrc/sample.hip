@@ -38,6 +38,7 @@ constexpr int kSegThreads = 256;   // block size of the IC segment kernels
 constexpr int kLtWaves = 2;        // wavefronts per block, LT lane-level pass
 constexpr int kChain = 64;         // LT chain length held in LDS
 constexpr int kBigThreads = 512;   // IC last-tier block size
+constexpr int kSegGroups = 1;      // 4-edge groups a lane decides per step (IC tiers 0 and 1)
 
 typedef unsigned __int128 u128;
 
@@ -290,7 +291,7 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
 // lanes scan Q/S entries), which leaves the LDS to more sets in flight.
 // Width mode writes w(R) per set; kappa is summed by kappa_reduce_kernel.
 // ------------------------------------------------------------------------
-template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX>
+template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
 __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
   constexpr bool kHash = HLOG > 0;
   constexpr int H = kHash ? (1 << HLOG) : 4;
@@ -467,44 +468,55 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
       }
     }
 
-    // ---- C: segments with work process S groups of their batch
+    // ---- C: segments with work process R*S groups of their batch (R per lane)
     bool lhit = false, lbad = false;
     if (has && done_items < G) {
-      const uint32_t item = done_items + (uint32_t)sl;
-      int owner = 0;
+      int32_t sv[4 * R];
+      bool live[4 * R];
 #pragma unroll
-      for (int step = S / 2; step > 0; step >>= 1) {
-        const uint32_t c = __shfl(incl, owner + step - 1, S);
-        if (c <= item) owner += step;
-      }
-      owner = min(owner, S - 1);
-      const uint32_t oa = __shfl(ea, owner, S);
-      const uint32_t od = __shfl(d, owner, S);
-      const uint32_t oex = __shfl(incl - ng, owner, S);
-      int32_t sv[4] = {0, 0, 0, 0};
-      bool live[4] = {false, false, false, false};
-      if (item < G) {
-        const uint32_t grp = (oa >> 2) + (item - oex);
-        const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
-        uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
-        if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
-        const uint4 x = draw(key, st, kKindCoin, (uint64_t)grp);
-        sv[0] = s4.x;
-        sv[1] = s4.y;
-        sv[2] = s4.z;
-        sv[3] = s4.w;
-        const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
-        const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
-        const uint32_t e0 = grp << 2;
+      for (int r = 0; r < R; ++r) {
+        const uint32_t item = done_items + (uint32_t)(r * S + sl);
+        int owner = 0;
+#pragma unroll
+        for (int step = S / 2; step > 0; step >>= 1) {
+          const uint32_t c = __shfl(incl, owner + step - 1, S);
+          if (c <= item) owner += step;
+        }
+        owner = min(owner, S - 1);
+        const uint32_t oa = __shfl(ea, owner, S);
+        const uint32_t od = __shfl(d, owner, S);
+        const uint32_t oex = __shfl(incl - ng, owner, S);
 #pragma unroll
         for (int w = 0; w < 4; ++w) {
-          const uint32_t e = e0 + (uint32_t)w;
-          live[w] = e - oa < od && edge_live<WC>(xv[w], tv[w], od);
+          sv[4 * r + w] = 0;
+          live[4 * r + w] = false;
+        }
+        if (item < G) {
+          const uint32_t grp = (oa >> 2) + (item - oex);
+          const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
+          uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
+          if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
+          const uint4 x = draw(key, st, kKindCoin, (uint64_t)grp);
+          sv[4 * r + 0] = s4.x;
+          sv[4 * r + 1] = s4.y;
+          sv[4 * r + 2] = s4.z;
+          sv[4 * r + 3] = s4.w;
+          const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+          const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
+          const uint32_t e0 = grp << 2;
+#pragma unroll
+          for (int w = 0; w < 4; ++w) {
+            const uint32_t e = e0 + (uint32_t)w;
+            live[4 * r + w] = e - oa < od && edge_live<WC>(xv[w], tv[w], od);
+          }
         }
       }
+      bool any_live = false;
+#pragma unroll
+      for (int w = 0; w < 4 * R; ++w) any_live |= live[w];
       if (kHash) {
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < 4 * R; ++w) {
           if (!live[w]) continue;
           const int32_t u = sv[w];
           const int r = lds_insert<(kHash ? HLOG : 1)>(h, (uint32_t)u);
@@ -517,13 +529,13 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
             if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
           }
         }
-      } else if (seg_bits<S>(__ballot(live[0] || live[1] || live[2] || live[3]), sw) != 0ull) {
+      } else if (seg_bits<S>(__ballot(any_live), sw) != 0ull) {
         // A live source whose signature bit is clear in the set's signature
         // and used by no other live source of this step is new: those are
         // appended at once.  The rest are looked up in the queue one at a time.
-        uint64_t bits[4], once = 0ull, twice = 0ull;
+        uint64_t bits[4 * R], once = 0ull, twice = 0ull;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < 4 * R; ++w) {
           bits[w] = live[w] ? sig_bit(sv[w]) : 0ull;
           twice |= once & bits[w];
           once |= bits[w];
@@ -534,10 +546,10 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
           twice |= t2 | (once & o2);
           once |= o2;
         }
-        bool fast[4];
+        bool fast[4 * R];
         uint32_t nfast = 0;
 #pragma unroll
-        for (int w = 0; w < 4; ++w) {
+        for (int w = 0; w < 4 * R; ++w) {
           fast[w] = live[w] && ((ssig | twice) & bits[w]) == 0ull;
           nfast += fast[w] ? 1u : 0u;
         }
@@ -549,7 +561,7 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
         } else {
           int pos = tail_r + (int)(fincl - nfast);
 #pragma unroll
-          for (int w = 0; w < 4; ++w) {
+          for (int w = 0; w < 4 * R; ++w) {
             if (!fast[w]) continue;
             q[pos++] = sv[w];
             if (MODE == kModeCover && in_seed(a.seed_bits, sv[w])) lhit = true;
@@ -557,7 +569,7 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
           tail_r += (int)ftot;
           wave_sync();
 #pragma unroll
-          for (int w = 0; w < 4; ++w) {
+          for (int w = 0; w < 4 * R; ++w) {
             uint64_t m = seg_bits<S>(__ballot(live[w] && !fast[w]), sw);
             while (m) {
               const int src_lane = __ffsll((unsigned long long)m) - 1;
@@ -579,7 +591,7 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
           }
         }
       }
-      done_items += (uint32_t)S;
+      done_items += (uint32_t)(R * S);
     }
     wave_sync();
     const uint64_t hm = __ballot(lhit), bm = __ballot(lbad);
@@ -976,28 +988,28 @@ template <int MODE, bool WC, int S>
 struct SegKernel;
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 4> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 4, 64, 0, 256>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 4, 64, 0, 256, kSegGroups>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 8> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 8, 128, 0, 256>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 8, 128, 0, 256, kSegGroups>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 16> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 16, 128, 8, 512>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 16, 128, 8, 512, kSegGroups>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 32> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 32, 256, 9, 1024>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 32, 256, 9, 1024, kSegGroups>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 64> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 2048>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 2048, kSegGroups>;
 };
 // tier 1: one set per wavefront
 template <int MODE, bool WC>
 struct Tier1Kernel {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 64 * 64>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 64, 512, 10, 64 * 64, kSegGroups>;
 };
 
 void launch_kappa_reduce(const SampleArgs& a, hipStream_t s) {
