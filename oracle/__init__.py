@@ -90,6 +90,8 @@ def _load():
                                                   ctypes.c_uint64, _P, _P, ctypes.c_int64, _P]),
         "orc_rr_single": (ctypes.c_int64, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, _P,
                                                 _P]),
+        "orc_round_sum": (ctypes.c_int, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                              ctypes.c_uint64, ctypes.c_int, _P]),
         "orc_kappa": (ctypes.c_double, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int]),
         "orc_kappa_fixed": (ctypes.c_uint64, [ctypes.c_uint64, ctypes.c_int64, ctypes.c_int]),
         "orc_ln_binom": (ctypes.c_double, [ctypes.c_int64, ctypes.c_int]),
@@ -199,6 +201,18 @@ def rr_set(g, model, seed, phase, set_id, thr=None):
 
 
 # ---- kappa and scalars -----------------------------------------------------
+def round_sum(g, model, seed, phase, first, count, k, thr=None) -> dict:
+    """One KptEstimation round over set ids [first, first+count) (Algorithm 2; Equation (8)):
+    exact sum S of kappa(R) * 2^53, total width and total size."""
+    lib = _load()
+    off, src, t = _garr(g, thr)
+    out = np.zeros(4, dtype=np.uint64)
+    rc = lib.orc_round_sum(*_gargs(g, off, src, t), model, seed, phase, first, count, k, _ptr(out))
+    if rc != 0:
+        raise RuntimeError(f"orc_round_sum failed ({rc})")
+    return dict(sum=(int(out[1]) << 64) | int(out[0]), width=int(out[2]), nodes=int(out[3]))
+
+
 def kappa(w, m, k) -> float:
     return float(_load().orc_kappa(w, m, k))
 

@@ -376,6 +376,38 @@ static int valid_graph(const orc_graph *g) {
   return 1;
 }
 
+/* One round of Algorithm 2 (lines 3-7): sets [first, first+count) of phase
+ * `phase`, the exact sum of kappa(R) * 2^53 (Equation (8)) and the widths and
+ * sizes of the sets. */
+static void round_sum(const orc_graph *g, int model, uint64_t seed, uint32_t phase, uint64_t first, uint64_t count,
+                      int k, orc_ws *w, u128 *sum, uint64_t *wsum, uint64_t *nsum) {
+  *sum = 0;
+  *wsum = 0;
+  *nsum = 0;
+  for (uint64_t s = first; s < first + count; ++s) {
+    uint64_t wd;
+    int64_t len = rr_set(g, model, seed, phase, s, w, &wd);
+    *sum += orc_kappa_fixed(wd, g->m, k);
+    *wsum += wd;
+    *nsum += (uint64_t)len;
+  }
+}
+
+/* round_sum over a range of set ids: out = {S low, S high, width, size}. */
+int orc_round_sum(int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr, int model,
+                  uint64_t seed, uint32_t phase, uint64_t first, uint64_t count, int k, uint64_t out[4]) {
+  orc_graph g = {n, m, off, src, thr};
+  if (!valid_graph(&g) || k < 1) return -1;
+  orc_ws *w = ws_new(n);
+  if (!w) return -2;
+  u128 sum;
+  round_sum(&g, model, seed, phase, first, count, k, w, &sum, &out[2], &out[3]);
+  out[0] = (uint64_t)sum;
+  out[1] = (uint64_t)(sum >> 64);
+  ws_free(w);
+  return 0;
+}
+
 int orc_kpt_estimate(int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr, int model,
                      uint64_t seed, int k, double ell, orc_report *rep) {
   orc_graph g = {n, m, off, src, thr};
@@ -389,15 +421,9 @@ int orc_kpt_estimate(int64_t n, int64_t m, const int64_t *off, const int32_t *sr
   rep->c_last = imax >= 1 ? orc_c_i(n, ell, imax) : 0;
   for (int i = 1; i <= imax; ++i) {
     uint64_t ci = orc_c_i(n, ell, i);
-    u128 sum = 0;
-    uint64_t wsum = 0, nsum = 0;
-    for (uint64_t s = 0; s < ci; ++s) {
-      uint64_t wd;
-      int64_t len = rr_set(&g, model, seed, (uint32_t)i, s, w, &wd);
-      sum += orc_kappa_fixed(wd, m, k);
-      wsum += wd;
-      nsum += (uint64_t)len;
-    }
+    u128 sum;
+    uint64_t wsum, nsum;
+    round_sum(&g, model, seed, (uint32_t)i, 0, ci, k, w, &sum, &wsum, &nsum);
     rep->round_c[i] = ci;
     rep->round_sum_lo[i] = (uint64_t)sum;
     rep->round_sum_hi[i] = (uint64_t)(sum >> 64);
@@ -417,7 +443,6 @@ int orc_kpt_estimate(int64_t n, int64_t m, const int64_t *off, const int32_t *sr
   return 0;
 }
 
-/* Sample sets [0, count) of a phase into freshly allocated arrays. */
 static int collect_sets(const orc_graph *g, int model, uint64_t seed, uint32_t phase, uint64_t count,
                         int64_t **set_off_out, int32_t **nodes_out, uint64_t *width_total) {
   orc_ws *w = ws_new(g->n);

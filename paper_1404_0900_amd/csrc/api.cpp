@@ -71,6 +71,7 @@ struct tim_ctx {
   int num_cu = 0;
   int seg_lanes = 8;
   uint32_t slice_cap = tim::kPoolChunk;  // largest node-pool slice of a wavefront
+  uint32_t emit_wave_sets = 0;           // emit launches: at least this many sets per tier-0 wavefront
   uint32_t slice = tim::kPoolChunk;      // slice of the current emit launches
   uint64_t resident_limit = ~0ull;       // most sets a greedy keeps resident
   int grid_ic[3][2] = {};
@@ -181,7 +182,9 @@ struct Totals {
 uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t count, uint64_t* waves) {
   const int per_cu = model == TIM_MODEL_IC ? c->grid_ic[mode][wc ? 1 : 0] : c->grid_lt[mode];
   const uint64_t waves_per_block = model == TIM_MODEL_IC ? 4 : 2;
-  const uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)c->seg_lanes) : 128;
+  uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)c->seg_lanes) : 128;
+  if (mode == tim::kModeEmit && c->emit_wave_sets)
+    sets_per_block = std::max<uint64_t>(sets_per_block, waves_per_block * c->emit_wave_sets);
   uint64_t grid = (uint64_t)per_cu * (uint64_t)c->num_cu;
   grid = std::min<uint64_t>(grid, (count + sets_per_block - 1) / sets_per_block);
   if (grid < 1) grid = 1;
@@ -198,19 +201,32 @@ uint64_t emit_waves(const tim_ctx* c, int model, uint64_t count) {
   return std::max(waves, w2);
 }
 
+// Largest set tier 0 stores (its LDS queue or chain).
+uint64_t tier0_cap(const tim_ctx* c, int model) { return tim::tier0_set_cap(model, c->seg_lanes); }
+
 // Node-pool slice for launches of `count` sets holding about `nodes`
-// entries: about a quarter of a wavefront's share, a power of two in
-// [64, slice_cap].
+// entries: about a quarter of a wavefront's share, a power of two between
+// four times the largest tier-0 set and max(slice_cap, that).
 uint32_t pick_slice(const tim_ctx* c, int model, uint64_t count, uint64_t nodes) {
   const uint64_t per_wave = nodes / std::max<uint64_t>(1, emit_waves(c, model, std::min(count, kMaxLaunchSets)));
-  uint32_t s = 64;
-  while (s < c->slice_cap && (uint64_t)s * 8 <= per_wave) s <<= 1;
-  return std::min(s, c->slice_cap);
+  const uint32_t lo = (uint32_t)(4 * tier0_cap(c, model));
+  const uint32_t hi = std::max(lo, c->slice_cap);
+  uint32_t s = lo;
+  while (s < hi && (uint64_t)s * 8 <= per_wave) s <<= 1;
+  return std::min(s, hi);
 }
 
-// Node-pool entries that part-used slices can leave empty in one launch.
-uint64_t pool_slack(const tim_ctx* c, int model, uint64_t count, uint32_t slice) {
-  return emit_waves(c, model, std::min(count, kMaxLaunchSets)) * (uint64_t)slice;
+// Node-pool entries that emit launches of `count` sets with `nodes` entries
+// need at most with slices of `slice` entries.  A wavefront leaves unused
+// less than one set (at most `cap` entries) at a slice boundary, and it
+// crosses a boundary once per slice - cap entries stored plus once more
+// after its last slice, whose rest (at most a slice) is also lost.
+uint64_t pool_need(const tim_ctx* c, int model, uint64_t count, uint64_t nodes, uint32_t slice) {
+  const uint64_t cap = tier0_cap(c, model);
+  const uint64_t launches = (count + kMaxLaunchSets - 1) / kMaxLaunchSets;
+  const uint64_t waves = emit_waves(c, model, std::min(count, kMaxLaunchSets));
+  const uint64_t boundary = (nodes * cap + (slice - cap) - 1) / (slice - cap);
+  return nodes + boundary + launches * waves * ((uint64_t)slice + cap);
 }
 
 // One sampling launch pair (wave/lane-level pass, then the large-set pass)
@@ -330,14 +346,14 @@ tim_status sample_counts(tim_ctx* c, const tim_graph* g, int model, int mode, ui
 
 // Emit mode: sets [first, first+count) into the node pool (set_start /
 // set_len per set).  expect_nodes sizes the pool; a short pool is regrown to
-// the exact need (nodes plus per-wavefront slack) and the sets regenerated.
+// what the exact total guarantees (pool_need) and the sets regenerated.
 tim_status emit_sets(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
                      uint64_t count, uint64_t expect_nodes, uint64_t* widths, Totals* t_out) {
   TIM_TRY(ensure(c, c->set_start, count * 8, "set offsets"));
   TIM_TRY(ensure(c, c->set_len, count * 4, "set sizes"));
   c->slice = pick_slice(c, model, count, expect_nodes);
-  const uint64_t slack = pool_slack(c, model, count, c->slice) * ((count + kMaxLaunchSets - 1) / kMaxLaunchSets);
-  TIM_TRY(ensure(c, c->pool, (std::max<uint64_t>(expect_nodes, 1024) + slack) * 4, "RR node pool"));
+  TIM_TRY(ensure(c, c->pool, pool_need(c, model, count, std::max<uint64_t>(expect_nodes, 1024), c->slice) * 4,
+                 "RR node pool"));
   for (int attempt = 0; attempt < 2; ++attempt) {
     Totals t;
     for (uint64_t done = 0; done < count;) {
@@ -350,7 +366,7 @@ tim_status emit_sets(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, u
       *t_out = t;
       return TIM_OK;
     }
-    TIM_TRY(ensure(c, c->pool, (t.nodes + slack) * 4, "RR node pool"));
+    TIM_TRY(ensure(c, c->pool, pool_need(c, model, count, t.nodes, c->slice) * 4, "RR node pool"));
   }
   return fail(TIM_EDEVICE, "node pool still short after regrowing");
 }
@@ -500,10 +516,8 @@ uint64_t lists_per_set(int model) { return model == TIM_MODEL_IC ? 16 : 8; }
 // Peak bytes of the all-resident path for `count` sets of `nodes` entries
 // (node pool, per-set starts and sizes, inverted index).
 uint64_t resident_bytes(const tim_ctx* c, int64_t n, int model, uint64_t count, uint64_t nodes, int k) {
-  const uint64_t launches = (count + kMaxLaunchSets - 1) / kMaxLaunchSets;
   const uint64_t lists = std::min(count, kMaxLaunchSets) * lists_per_set(model);
-  const uint64_t emit = count * 12 + (nodes + pool_slack(c, model, count, pick_slice(c, model, count, nodes)) *
-                                                 launches) * 4;
+  const uint64_t emit = count * 12 + pool_need(c, model, count, nodes, pick_slice(c, model, count, nodes)) * 4;
   const uint64_t index = (uint64_t)n * 17 + 8 + nodes * 4 + count + 8 * (uint64_t)k +
                          tim::scan_temp_bytes((uint64_t)n + 1) + 17 * 256;
   return lists + emit + index;
@@ -570,22 +584,28 @@ tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t
   TIM_TRY(collection_room(c, &room));
   struct SliceScope {
     tim_ctx* c;
-    ~SliceScope() { c->slice_cap = tim::kPoolChunk; }
+    ~SliceScope() {
+      c->slice_cap = tim::kPoolChunk;
+      c->emit_wave_sets = 0;
+    }
   } scope{c};
-  c->slice_cap = 64;  // small pool slices: the pool is sized for one chunk
+  // small slices, and enough sets per wavefront to fill them: the pool is
+  // sized for one chunk
+  c->slice_cap = 0;
+  c->emit_wave_sets = 64;
   const double nps = count ? std::max(1.0, (double)expect_nodes / (double)count) : 1.0;
   const uint64_t fixed = (uint64_t)n * 5 + count + 8 * (uint64_t)k + 8 * 256;  // cnt, selected, covered, best
   if (fixed >= room)
     return fail(TIM_EBUDGET, "budget too small for the coverage counts of %llu sets (%llu bytes needed, %llu left)",
                 (unsigned long long)count, (unsigned long long)fixed, (unsigned long long)room);
   const uint64_t avail = room - fixed;
-  // per chunk set: offsets and size, deferral lists, its nodes, and the
-  // slack of its tier-0 wavefronts' slices
-  const uint64_t slack_fixed = pool_slack(c, model, 0, 64) * 4 + 8 * 256;
-  const double waves_per_set =
-      model == TIM_MODEL_IC ? (double)c->seg_lanes / 64.0 : 2.0 / 128.0;  // tier-0 wavefronts per set
-  const double slice_per_set = 64.0 * 4.0 * waves_per_set;
-  const double per_chunk_set = 12.0 + (double)lists_per_set(model) + 4.0 * nps + slice_per_set;
+  // per chunk set: offsets and size, deferral lists, its nodes with their
+  // slice-boundary loss, and its share of the last slices of the wavefronts
+  const double cap = (double)tier0_cap(c, model), slice = 4.0 * cap;
+  const double node_bytes = 4.0 * nps * (1.0 + cap / (slice - cap));
+  const double slice_per_set = 4.0 * (slice + cap) / (double)c->emit_wave_sets;
+  const uint64_t slack_fixed = 4 * (uint64_t)(slice + cap) * 8 + 8 * 256;
+  const double per_chunk_set = 12.0 + (double)lists_per_set(model) + node_bytes + slice_per_set;
   uint64_t chunk = avail / 4 > slack_fixed ? (uint64_t)((double)(avail / 4 - slack_fixed) / per_chunk_set) : 0;
   chunk = std::min({chunk, count, kMaxLaunchSets});
   if (chunk < 64 && chunk < count)
@@ -594,7 +614,7 @@ tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t
   const uint64_t chunk_cost = (uint64_t)((double)chunk * per_chunk_set) + slack_fixed;
   const uint64_t idx_fixed = (uint64_t)n * 12 + 8 + 6 * 256 + tim::scan_temp_bytes(count);  // fill, inv_off, scan
   const double per_res_steady = 8.0 + 8.0 * nps;
-  const double per_res_peak = 20.0 + (double)lists_per_set(model) + 8.0 * nps + slice_per_set;
+  const double per_res_peak = 20.0 + (double)lists_per_set(model) + 4.0 * nps + node_bytes + slice_per_set;
   uint64_t resident = 0;
   if (avail > chunk_cost + idx_fixed) {
     const uint64_t r1 = (uint64_t)((double)(avail - chunk_cost - idx_fixed) / per_res_steady);

@@ -92,6 +92,9 @@ int ic_seg_lanes();
 int ic_blocks_per_cu(int mode, bool wc, int seg_lanes);
 int ic_tier1_blocks_per_cu(int mode, bool wc);
 int lt_lane_blocks_per_cu(int mode);
+// Largest set the first tier keeps in LDS (IC: its queue for seg_lanes lanes
+// per set; LT: its chain); larger sets go on to the next tier.
+uint32_t tier0_set_cap(int model, int seg_lanes);
 // Tier 0 (grid0 blocks; IC with seg_lanes lanes per set), then the deferral
 // tiers (IC tier 1 with grid1 blocks).  after_tier0, if given, is recorded
 // between tier 0 and the rest.

@@ -141,6 +141,36 @@ struct Acc {
   unsigned long long width = 0, nodes = 0, covered = 0;
 };
 
+// Places a wavefront's sets finished in one step in its node-pool slice
+// [pool_next, pool_end).  `mine` is this lane's entry count (0 if none),
+// `winc` its inclusive prefix over the wavefront and `tot` the total.  The
+// sets whose prefix fits the slice go there; the rest go to a new slice of
+// max(slice, rest) entries, so what is left unused of the old slice is
+// shorter than the first set that did not fit.  Returns this lane's offset.
+__device__ __forceinline__ unsigned long long pool_place(const SampleArgs& a, unsigned long long slice, uint32_t mine,
+                                                         uint32_t winc, uint32_t tot, unsigned long long& pool_next,
+                                                         unsigned long long& pool_end, int lane) {
+  const unsigned long long room = pool_end - pool_next;
+  const bool fits = (unsigned long long)winc <= room;
+  const uint64_t fm = __ballot(fits);  // a prefix of the lanes: winc grows with the lane
+  const int nfit = __popcll(fm);
+  const uint32_t used = nfit ? __shfl(winc, nfit - 1) : 0u;
+  unsigned long long pos = pool_next + (unsigned long long)(winc - mine);
+  if (used == tot) {
+    pool_next += tot;
+    return pos;
+  }
+  const unsigned long long rest = (unsigned long long)(tot - used);
+  const unsigned long long want = max(slice, rest);
+  unsigned long long got = 0;
+  if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want);
+  got = __shfl(got, 0);
+  if (!fits) pos = got + (unsigned long long)(winc - mine - used);
+  pool_next = got + rest;
+  pool_end = got + want;
+  return pos;
+}
+
 // Sum of every lane's accumulators, added to the counters by lane 0.
 __device__ __forceinline__ void wave_flush(const SampleArgs& a, const Acc& acc, int tier, int lane) {
   const unsigned long long lo = (unsigned long long)acc.kappa, hi = (unsigned long long)(acc.kappa >> 64);
@@ -441,18 +471,9 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
       if (fm) {
         const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
         const uint32_t tot = __shfl(winc, kWave - 1);
-        if (pool_next + tot > pool_end) {
-          // tier 0 reserves slices; the deferral tier (large sets, few) exactly what it stores
-          const unsigned long long slice = io.acc == 0 ? (unsigned long long)a.pool_chunk : 0ull;
-          const unsigned long long want_n = max(slice, (unsigned long long)tot);
-          unsigned long long got = 0;
-          if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want_n);
-          got = __shfl(got, 0);
-          pool_next = got;
-          pool_end = got + want_n;
-        }
-        const unsigned long long my_base = pool_next + (unsigned long long)(winc - mine);
-        pool_next += tot;
+        // tier 0 reserves slices; the deferral tier (large sets, few) exactly what it stores
+        const unsigned long long slice = io.acc == 0 ? (unsigned long long)a.pool_chunk : 0ull;
+        const unsigned long long my_base = pool_place(a, slice, mine, winc, tot, pool_next, pool_end, lane);
         const unsigned long long base = __shfl(my_base, leader);
         if (fin) {
           if (base + fin_len <= a.pool_cap)
@@ -712,16 +733,8 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
       const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
       const uint32_t tot = __shfl(winc, kWave - 1);
       if (tot) {
-        if (pool_next + tot > pool_end) {
-          const unsigned long long want_n = max((unsigned long long)a.pool_chunk, (unsigned long long)tot);
-          unsigned long long got = 0;
-          if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want_n);
-          got = __shfl(got, 0);
-          pool_next = got;
-          pool_end = got + want_n;
-        }
-        const unsigned long long base = pool_next + (unsigned long long)(winc - mine);
-        pool_next += tot;
+        const unsigned long long base =
+            pool_place(a, (unsigned long long)a.pool_chunk, mine, winc, tot, pool_next, pool_end, lane);
         if (fin) {
           if (base + (unsigned long long)len <= a.pool_cap)
             for (int i = 0; i < len; ++i) a.pool[base + i] = chain[i][lane];
@@ -1097,6 +1110,17 @@ int lt_lane_blocks_per_cu(int mode) {
     case 0: return blocks_per_cu(lt_lane_kernel<kModeWidth>, kLtWaves * kWave);
     case 1: return blocks_per_cu(lt_lane_kernel<kModeEmit>, kLtWaves * kWave);
     default: return blocks_per_cu(lt_lane_kernel<kModeCover>, kLtWaves * kWave);
+  }
+}
+
+uint32_t tier0_set_cap(int model, int seg_lanes) {
+  if (model == 1) return (uint32_t)kChain;
+  switch (seg_lanes) {
+    case 4: return 64;
+    case 8: return 128;
+    case 16: return 128;
+    case 32: return 256;
+    default: return 512;
   }
 }
 

@@ -37,6 +37,8 @@ def _load():
         lib.synth_chung_lu.restype = ctypes.c_int
         lib.synth_chung_lu.argtypes = [ctypes.c_int64, ctypes.c_int64, ctypes.c_double, ctypes.c_uint64,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.synth_set_verbose.restype = None
+        lib.synth_set_verbose.argtypes = [ctypes.c_int]
         _lib = lib
     return _lib
 
@@ -57,6 +59,7 @@ class Graph:
 def chung_lu(n: int, m: int, alpha: float = 2.1, seed: int = 1, name: str = "") -> Graph:
     """Directed Chung-Lu power-law graph with exactly m distinct edges, no self-loops."""
     lib = _load()
+    lib.synth_set_verbose(1 if m >= 100_000_000 else 0)  # progress lines on stderr for large graphs
     off = np.empty(n + 1, dtype=np.int64)
     src = np.empty(m, dtype=np.int32)
     i0 = ctypes.c_int64(0)

@@ -20,10 +20,28 @@
  * in this order: out-permutation, in-permutation, then two words per endpoint
  * of each candidate edge (u first, then v).
  */
+#define _POSIX_C_SOURCE 199309L /* clock_gettime under -std=c11 */
 #include <math.h>
 #include <stdint.h>
+#include <stdio.h>
 #include <stdlib.h>
 #include <string.h>
+#include <time.h>
+
+/* Progress lines on stderr for large graphs (synth_set_verbose). */
+static int g_verbose = 0;
+static struct timespec g_t0;
+
+void synth_set_verbose(int on) { g_verbose = on; }
+
+static void progress(const char *what, int64_t count) {
+  if (!g_verbose) return;
+  struct timespec t;
+  clock_gettime(CLOCK_MONOTONIC, &t);
+  double s = (double)(t.tv_sec - g_t0.tv_sec) + 1e-9 * (double)(t.tv_nsec - g_t0.tv_nsec);
+  fprintf(stderr, "[synth] %7.1f s  %s %lld\n", s, what, (long long)count);
+  fflush(stderr);
+}
 
 typedef struct {
   uint64_t key; /* (dst << 32) | src */
@@ -94,6 +112,7 @@ static int radix_sort(cand_t *a, int64_t len, int by_idx, int bits) {
       dst[cnt[(f >> shift) & 0xFFFF]++] = src[i];
     }
     cand_t *t = src; src = dst; dst = t;
+    progress("radix pass done, items", len);
   }
   if (src != a) memcpy(a, src, sizeof(cand_t) * (size_t)len);
   free(tmp); free(cnt);
@@ -111,6 +130,8 @@ int synth_chung_lu(int64_t n, int64_t m, double alpha, uint64_t seed,
                    int64_t *off, int32_t *src, int64_t *realized_i0) {
   if (n < 2 || n > 0x7FFFFFFF || m < 1 || m > n * (n - 1) || !(alpha > 1.0)) return -1;
   const double beta = 1.0 / (alpha - 1.0);
+  clock_gettime(CLOCK_MONOTONIC, &g_t0);
+  progress("start: edges wanted", m);
   double *b = (double *)malloc(sizeof(double) * (size_t)n);
   double *wo = (double *)malloc(sizeof(double) * (size_t)n);
   double *wi = (double *)malloc(sizeof(double) * (size_t)n);
@@ -143,6 +164,7 @@ int synth_chung_lu(int64_t n, int64_t m, double alpha, uint64_t seed,
     double t = wi[i]; wi[i] = wi[j]; wi[j] = t;
   }
   if (build_alias(wo, n, po, ao) || build_alias(wi, n, pi, ai)) { rc = -2; goto done; }
+  progress("alias tables built, nodes", n);
 
   const int key_bits = 32 + bit_length((uint64_t)(n - 1));
   have = (cand_t *)malloc(sizeof(cand_t) * (size_t)m);
@@ -160,11 +182,13 @@ int synth_chung_lu(int64_t n, int64_t m, double alpha, uint64_t seed,
       int32_t u = alias_draw(&st, n, po, ao);
       int32_t v = alias_draw(&st, n, pi, ai);
       uint64_t idx = drawn++;
+      if ((idx & ((1ull << 28) - 1)) == 0 && idx) progress("candidates drawn so far", (int64_t)idx);
       if (u == v) continue;
       cand[nc].key = ((uint64_t)(uint32_t)v << 32) | (uint32_t)u;
       cand[nc].idx = idx;
       ++nc;
     }
+    progress("candidates drawn", nc);
     if (radix_sort(cand, nc, 0, key_bits)) { rc = -2; goto done; }
     /* keep the first draw of every key, then drop keys already kept earlier */
     int64_t nu = 0, h = 0;
@@ -188,6 +212,7 @@ int synth_chung_lu(int64_t n, int64_t m, double alpha, uint64_t seed,
     }
     nhave += nu;
     free(cand); cand = NULL;
+    progress("distinct edges kept", nhave);
   }
   memset(off, 0, sizeof(int64_t) * (size_t)(n + 1));
   for (int64_t e = 0; e < m; ++e) {
@@ -196,6 +221,7 @@ int synth_chung_lu(int64_t n, int64_t m, double alpha, uint64_t seed,
     src[e] = (int32_t)(uint32_t)(have[e].key & 0xFFFFFFFFu);
   }
   for (int64_t v = 0; v < n; ++v) off[v + 1] += off[v];
+  progress("in-CSR written, edges", m);
 
 done:
   free(b); free(wo); free(wi); free(po); free(pi); free(ao); free(ai);

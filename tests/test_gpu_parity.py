@@ -398,6 +398,23 @@ def test_node_select_under_budget_uses_many_chunks(cfg1, model):
     _select_equal(sel, seeds, gains, want)
 
 
+@pytest.mark.parametrize("limit", [None, 0])
+def test_node_select_pool_regrowth(cfg1, limit):
+    # supercritical probabilities: sets far larger than NodeSelection's size
+    # estimate, so the node pool is regrown (resident and regenerated paths)
+    import paper_1404_0900_amd as tim
+    thr = np.full(cfg1.m, (1 << 31) - 1, dtype=np.uint32)  # p = 1/2
+    k, theta = 10, 3000
+    want = oracle.node_select(cfg1, IC, 21, k, theta, thr=thr)
+    with tim.Engine(0) as e:
+        e.set_resident_limit(limit)
+        dg = e.upload(cfg1, thr=thr)
+        _say(f"node_select regrowth: limit={limit}")
+        seeds, gains, sel = e.node_select(dg, IC, 21, k, theta)
+    assert sel.nodes > 16 * theta
+    _select_equal(sel, seeds, gains, want)
+
+
 def test_tim_plus_under_budget_cfg1(cfg1):
     # whole TIM+ (RefineKPT's greedy and NodeSelection) under a small budget
     import paper_1404_0900_amd as tim

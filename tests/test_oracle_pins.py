@@ -572,6 +572,24 @@ def test_stop_test_is_strict(model):
 
 
 @pytest.mark.parametrize("model", [IC, LT])
+def test_round_sum_adds_kappa_of_the_sets(model):
+    # one round's exact sum, width and size are those of its sets (Equation (8)),
+    # split anywhere, and the rounds of KptEstimation are such sums
+    g = synth.chung_lu(3000, 12000, 2.1, 5)
+    k, seed = 7, 11
+    so, nodes, w = oracle.sample_sets(g, model, seed, 2, 0, 500)
+    want = sum(oracle.kappa_fixed(int(x), g.m, k) for x in w)
+    r = oracle.round_sum(g, model, seed, 2, 0, 500, k)
+    assert r["sum"] == want and r["width"] == int(np.sum(w)) and r["nodes"] == len(nodes)
+    a = oracle.round_sum(g, model, seed, 2, 0, 123, k)
+    b = oracle.round_sum(g, model, seed, 2, 123, 377, k)
+    assert a["sum"] + b["sum"] == r["sum"] and a["width"] + b["width"] == r["width"]
+    kp = oracle.kpt_estimate(g, model, seed, k, 1.0)
+    for i, s in kp["round_sums"].items():
+        assert oracle.round_sum(g, model, seed, i, 0, kp["round_c"][i], k)["sum"] == s
+
+
+@pytest.mark.parametrize("model", [IC, LT])
 def test_pipeline_is_composed_of_its_phases(model):
     # TIM+ = Algorithm 2, then Algorithm 3 on regenerated round-i_last sets and
     # fresh phase-63 sets, then Algorithm 1 on phase-64 sets.
