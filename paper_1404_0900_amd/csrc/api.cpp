@@ -74,6 +74,15 @@ struct tim_ctx {
   uint32_t emit_wave_sets = 0;           // emit launches: at least this many sets per tier-0 wavefront
   uint32_t slice = tim::kPoolChunk;      // slice of the current emit launches
   uint64_t resident_limit = ~0ull;       // most sets a greedy keeps resident
+  int emit_kappa_k = 0;                  // emit launches also sum kappa(R) for this k (0: no)
+  // the node pool holds the sets of one KptEstimation round (Algorithm 3, line 1 reuses them)
+  struct Stored {
+    bool valid = false;
+    const void* graph = nullptr;
+    int model = 0;
+    uint64_t seed = 0, count = 0, nodes = 0, width = 0;
+    uint32_t phase = 0;
+  } stored;
   int grid_ic[3][2] = {};
   int grid_ic64[3][2] = {};
   int grid_lt[3] = {};
@@ -254,9 +263,10 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   a.ctr = c->ctr;
   a.widths = widths;
   a.sizes = sizes;
-  if (mode == tim::kModeWidth) {
+  if (mode == tim::kModeWidth || (mode == tim::kModeEmit && c->emit_kappa_k > 0)) {
     TIM_TRY(ensure(c, c->wbuf, count * 4, "width buffer"));
     a.wbuf = c->wbuf.as<uint32_t>();
+    if (mode == tim::kModeEmit) a.k = c->emit_kappa_k;
   }
   if (mode == tim::kModeEmit) {
     const uint64_t cap = c->pool.bytes / 4;
@@ -349,6 +359,7 @@ tim_status sample_counts(tim_ctx* c, const tim_graph* g, int model, int mode, ui
 // what the exact total guarantees (pool_need) and the sets regenerated.
 tim_status emit_sets(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,
                      uint64_t count, uint64_t expect_nodes, uint64_t* widths, Totals* t_out) {
+  c->stored.valid = false;
   TIM_TRY(ensure(c, c->set_start, count * 8, "set offsets"));
   TIM_TRY(ensure(c, c->set_len, count * 4, "set sizes"));
   c->slice = pick_slice(c, model, count, expect_nodes);
@@ -490,6 +501,7 @@ uint64_t transient_bytes(tim_ctx* c) {
 }
 
 void release_transients(tim_ctx* c) {
+  c->stored.valid = false;
   size_t nb = 0;
   DevBuf* const* b = transient_bufs(c, &nb);
   (void)hipStreamSynchronize(c->stream);
@@ -768,18 +780,43 @@ float elapsed_ms(tim_ctx* c) {
   return ms;
 }
 
+// Algorithm 2.  With keep_last, a round that the previous one predicts to be
+// the last (its mean kappa already above 0.8 * 2^-i) is stored in the node
+// pool while its widths are summed, so that RefineKPT can take its sets
+// without generating them again.
 tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double ell,
-                             tim_kpt_result* out, uint64_t* sets, uint64_t* width) {
+                             bool keep_last, tim_kpt_result* out, uint64_t* sets, uint64_t* width) {
   memset(out, 0, sizeof(*out));
   const int imax = rounds_of(g->n);
   out->i_max = imax;
   out->i_last = imax;
   out->c_last = imax >= 1 ? round_size(g->n, ell, imax) : 0;
   out->kpt_star = 1.0;
+  u128 prev_sum = 0;
+  uint64_t prev_c = 0, prev_nodes = 0;
   for (int i = 1; i <= imax; ++i) {
     const uint64_t ci = round_size(g->n, ell, i);
     Totals t;
-    TIM_TRY(sample_counts(c, g, model, tim::kModeWidth, seed, (uint32_t)i, 0, ci, k, nullptr, nullptr, &t));
+    // predicted last: S_{i-1} * 2^i > 0.8 * c_{i-1} * 2^53, evaluated as 5 * S * 2^i > 4 * c * 2^53
+    const bool predicted = keep_last && prev_c > 0 && ci <= kMaxLaunchSets &&
+                           ((prev_sum * 5) << i) > (((u128)prev_c * 4) << 53);
+    bool stored = false;
+    if (predicted) {
+      const uint64_t expect = (uint64_t)((double)prev_nodes / (double)prev_c * 1.25 * (double)ci) + 4096;
+      uint64_t room = 0;
+      TIM_TRY(collection_room(c, &room));
+      if (resident_bytes(c, g->n, model, ci, expect, k) + ci * 4 <= room) {
+        struct KappaScope {
+          tim_ctx* c;
+          ~KappaScope() { c->emit_kappa_k = 0; }
+        } scope{c};
+        c->emit_kappa_k = k;
+        TIM_TRY(emit_sets(c, g, model, seed, (uint32_t)i, 0, ci, expect, nullptr, &t));
+        stored = true;
+      }
+    }
+    if (!stored)
+      TIM_TRY(sample_counts(c, g, model, tim::kModeWidth, seed, (uint32_t)i, 0, ci, k, nullptr, nullptr, &t));
     out->round_c[i] = ci;
     out->round_sum_lo[i] = (uint64_t)t.kappa;
     out->round_sum_hi[i] = (uint64_t)(t.kappa >> 64);
@@ -787,12 +824,25 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
     out->round_nodes[i] = t.nodes;
     if (sets) *sets += ci;
     if (width) *width += t.width;
+    prev_sum = t.kappa;
+    prev_c = ci;
+    prev_nodes = t.nodes;
     // sum/c_i > 2^-i with sum = S * 2^-53 exactly: S * 2^i > c_i * 2^53
     if ((t.kappa << i) > ((u128)ci << 53)) {
       const double sum = std::ldexp((double)t.kappa, -53);
       out->kpt_star = (sum * (double)g->n) / (2.0 * (double)ci);
       out->i_last = i;
       out->c_last = ci;
+      if (stored) {
+        c->stored.valid = true;
+        c->stored.graph = g;
+        c->stored.model = model;
+        c->stored.seed = seed;
+        c->stored.phase = (uint32_t)i;
+        c->stored.count = ci;
+        c->stored.nodes = t.nodes;
+        c->stored.width = t.width;
+      }
       break;
     }
   }
@@ -803,15 +853,22 @@ tim_status refine_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed,
                        double kpt_star, int i_last, uint64_t c_last, uint64_t expect_nodes, int32_t* s_prime,
                        tim_refine_result* out, uint64_t* sets, uint64_t* width) {
   memset(out, 0, sizeof(*out));
-  // lines 1-6: greedy on the sets of the last round of Algorithm 2
+  // lines 1-6: greedy on the sets of the last round of Algorithm 2 - still in
+  // the node pool when KptEstimation kept them, else generated again
   CollectionStats cs;
-  if (c_last > 0) {
+  const tim_ctx::Stored& kept = c->stored;
+  if (c_last > 0 && kept.valid && kept.graph == g && kept.model == model && kept.seed == seed &&
+      kept.phase == (uint32_t)i_last && kept.count == c_last) {
+    TIM_TRY(greedy(c, g->n, c_last, nullptr, c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
+                   c->pool.as<int32_t>(), kept.nodes, k, s_prime, nullptr));
+  } else if (c_last > 0) {
     TIM_TRY(collection_greedy(c, g, model, seed, (uint32_t)i_last, c_last, k, expect_nodes, s_prime, nullptr, &cs));
+    if (sets) *sets += c_last;
+    if (width) *width += cs.width;
   } else {
     for (int j = 0; j < k; ++j) s_prime[j] = j;
   }
-  if (sets) *sets += c_last;
-  if (width) *width += cs.width;
+  c->stored.valid = false;
   // lines 7-10
   const double nd = (double)g->n;
   const double eps_p = 5.0 * std::cbrt(ell * eps * eps / ((double)k + ell));
@@ -1108,7 +1165,7 @@ tim_status tim_kpt_estimate(tim_ctx* c, const tim_graph* g, int model, uint64_t 
   TIM_TRY(check_phase_args(c, g, model, k));
   if (!out || !(ell >= 0.5)) return fail(TIM_EINVAL, "ell must be >= 0.5");
   HIP_TRY(hipSetDevice(c->device));
-  return kpt_estimate_impl(c, g, model, seed, k, ell, out, nullptr, nullptr);
+  return kpt_estimate_impl(c, g, model, seed, k, ell, false, out, nullptr, nullptr);
 }
 
 tim_status tim_refine_kpt(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double eps, double ell,
@@ -1157,7 +1214,8 @@ tim_status tim_run(tim_ctx* c, const tim_graph* g, int model, int k, double eps,
     (void)hipEventRecord(t0, c->stream);
   };
   (void)hipEventRecord(t0, c->stream);
-  tim_status st = kpt_estimate_impl(c, g, model, seed, k, ell_used, &r->kpt, &r->sets_total, &r->width_total);
+  tim_status st =
+      kpt_estimate_impl(c, g, model, seed, k, ell_used, !plain, &r->kpt, &r->sets_total, &r->width_total);
   if (st == TIM_OK) lap(&r->ms_kpt);
   // mean set size of the stopping round sizes the node pools
   const int il = r->kpt.i_last;

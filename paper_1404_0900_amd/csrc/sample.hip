@@ -482,6 +482,7 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
             a.set_start[rel] = a.pool_base + base;
             a.set_len[rel] = fin_len;
             if (a.widths) a.widths[rel] = fin_width;
+            if (a.wbuf) a.wbuf[rel] = fin_width;
             acc.width += fin_width;
             acc.nodes += fin_len;
           }
@@ -741,6 +742,7 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
           a.set_start[rel] = a.pool_base + base;
           a.set_len[rel] = (uint32_t)len;
           if (a.widths) a.widths[rel] = width;
+          if (a.wbuf) a.wbuf[rel] = (uint32_t)width;
           acc.width += width;
           acc.nodes += (unsigned long long)len;
         }
@@ -891,6 +893,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
         a.set_start[rel] = a.pool_base + b;
         a.set_len[rel] = len;
         if (a.widths) a.widths[rel] = width;
+        if (a.wbuf) a.wbuf[rel] = (uint32_t)width;
         acc.width += width;
         acc.nodes += len;
       }
@@ -969,6 +972,7 @@ __global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) 
       a.set_start[rel] = a.pool_base + b;
       a.set_len[rel] = (uint32_t)len;
       if (a.widths) a.widths[rel] = width;
+      if (a.wbuf) a.wbuf[rel] = (uint32_t)width;
       acc.width += width;
       acc.nodes += (unsigned long long)len;
     } else {
@@ -1005,7 +1009,7 @@ struct SegKernel<MODE, WC, 4> {
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 8> {
-  static constexpr auto fn = ic_seg_kernel<MODE, WC, 8, 128, 0, 256, kSegGroups>;
+  static constexpr auto fn = ic_seg_kernel<MODE, WC, 8, 128, 0, 512, kSegGroups>;
 };
 template <int MODE, bool WC>
 struct SegKernel<MODE, WC, 16> {
@@ -1047,7 +1051,7 @@ void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, 
   if (after0) (void)hipEventRecord(after0, s);
   hipLaunchKernelGGL((Tier1Kernel<MODE, WC>::fn), dim3(grid1), blk, 0, s, a, t1);
   hipLaunchKernelGGL((ic_big_kernel<MODE, WC>), dim3(a.big_slots), dim3(kBigThreads), 0, s, a, t2);
-  if (MODE == kModeWidth) launch_kappa_reduce(a, s);
+  if (MODE == kModeWidth || (MODE == kModeEmit && a.wbuf)) launch_kappa_reduce(a, s);
 }
 
 template <int MODE>
@@ -1057,7 +1061,7 @@ void launch_lt(const SampleArgs& a, int grid0, hipStream_t s, hipEvent_t after0)
   hipLaunchKernelGGL((lt_lane_kernel<MODE>), dim3(grid0), dim3(kLtWaves * kWave), 0, s, a, t0);
   if (after0) (void)hipEventRecord(after0, s);
   hipLaunchKernelGGL((lt_big_kernel<MODE>), dim3((a.big_slots + kWave - 1) / kWave), dim3(kWave), 0, s, a, t2);
-  if (MODE == kModeWidth) launch_kappa_reduce(a, s);
+  if (MODE == kModeWidth || (MODE == kModeEmit && a.wbuf)) launch_kappa_reduce(a, s);
 }
 
 template <int MODE, bool WC>
