@@ -13,6 +13,14 @@ generating them again, as Algorithm 3 prescribes, so they count once), edges
 examined per second, TIM+ seconds per k, the roofline of the dominant sampler
 kernel (algorithmic bytes over its event-timed duration), and the CPU oracle
 timed on the host on one TIM+ run of the same graph (k = 50).
+
+--workload batch64: 64 independent TIM+ queries, each on a Chung-Lu graph of
+its own (n log-uniform in [10^4, 2*10^6], average degree uniform in [4, 40];
+even queries IC with per-edge p from {0.1, 0.01, 0.001}, odd ones LT; k
+uniform in [1, 50], eps from {0.1, 0.2, 0.5}, ell = 1), all graphs resident.
+A step runs the 64 queries one after the other (tim_run) and then as one
+batch (tim_run_batch); value is the batch's queries per second, beside the
+sequential rate, and the two must return identical results.
 """
 import argparse
 import json
@@ -72,12 +80,16 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--workload", choices=("timplus", "batch64"), default="timplus")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path (run with --gpus 1)",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "batch64":
+        return batch_main(args)
 
     import torch
 
@@ -125,26 +137,12 @@ def main():
     eng.profile(False)
 
     # dominant sampler kernel: the one with the most GPU time in the timed steps
-    best = None
-    for model in (0, 1):
-        for mode in (0, 1, 2):
-            kp = prof.sampler[model][mode]
-            if kp.launches and (best is None or kp.kernel_ms > best[2].kernel_ms):
-                best = (model, mode, kp)
-    model, mode, kp = best
-    achieved = kp.bytes / (kp.kernel_ms * 1e-3) / 1e9
-    traffic = None
-    if kernel_name(model, mode) == TRAFFIC["kernel"] and sources_sha() == TRAFFIC["sources_sha256_16"]:
-        traffic = TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+    def traffic_of(model, mode):
+        if kernel_name(model, mode) == TRAFFIC["kernel"] and sources_sha() == TRAFFIC["sources_sha256_16"]:
+            return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+        return None
+    roofline = dominant_roofline(prof, kernel_name, traffic_of)
     sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
-    roofline = {
-        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic,
-        "kernel": kernel_name(model, mode), "launches": int(kp.launches),
-        "avg_launch_us": round(kp.kernel_ms * 1e3 / kp.launches, 3),
-        "bytes_per_launch": int(kp.bytes // kp.launches),
-        "edges_per_s": round(kp.edges / (kp.kernel_ms * 1e-3), 1),
-    }
 
     line = {
         "metric": "RR sets/s (IC, 1 GPU, TIM+ on 1M-node Chung-Lu, k in {1,10,50})",
@@ -191,6 +189,119 @@ def main():
             "value": round(osets / dt, 1), "unit": "RR sets/s", "cores": 1, "kind": "oracle",
             "sample": f"one oracle TIM+ run (IC, k=50) on the same graph: {osets} RR sets in {dt:.2f} s",
         }
+    eng.close()
+    print(json.dumps(line), flush=True)
+
+
+def dominant_roofline(prof, name_of, traffic_of=lambda model, mode: None):
+    """Roofline object of the sampler kernel with the most event time in a profile."""
+    best = None
+    for model in (0, 1):
+        for mode in (0, 1, 2):
+            kp = prof.sampler[model][mode]
+            if kp.launches and (best is None or kp.kernel_ms > best[2].kernel_ms):
+                best = (model, mode, kp)
+    model, mode, kp = best
+    achieved = kp.bytes / (kp.kernel_ms * 1e-3) / 1e9
+    return {
+        "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 5), "traffic": traffic_of(model, mode),
+        "kernel": name_of(model, mode), "launches": int(kp.launches),
+        "avg_launch_us": round(kp.kernel_ms * 1e3 / kp.launches, 3),
+        "bytes_per_launch": int(kp.bytes // kp.launches),
+        "edges_per_s": round(kp.edges / (kp.kernel_ms * 1e-3), 1),
+    }
+
+
+def batch_kernel_name(model, mode):
+    """Tier-0 kernel of the batched launches as rocprofv3 lists it."""
+    if model == 1:
+        return f"lt_lane_batch_kernel<{mode}> ({MODES[mode]})"
+    return f"ic_seg_batch_kernel<{mode}, false, 8, 128, 0, 512, {SEG_GROUPS}> ({MODES[mode]})"
+
+
+def batch_main(args):
+    import statistics
+
+    import numpy as np
+    import torch
+
+    import paper_1404_0900_amd as tim
+    import synth
+
+    queries = synth.batch_queries(64)
+    log("generating the 64 graphs of the batched workload")
+    graphs = synth.batch_graphs(queries, workers=16)
+    eng = tim.Engine(0)
+    dgs = [eng.upload(g, thr=thr) for g, thr in graphs]
+    batch = [(dg, q["model"], q["k"], q["eps"], q["ell"], q["seed"]) for dg, q in zip(dgs, queries)]
+    log(f"64 graphs resident: {sum(g.m for g, _ in graphs)} edges")
+
+    def sequential():
+        return [eng.run(*b) for b in batch]
+
+    def same(seq, bat):
+        for (s1, g1, r1), (s2, g2, r2) in zip(seq, bat):
+            if not (np.array_equal(s1, s2) and np.array_equal(g1, g2) and r1.select.theta == r2.select.theta
+                    and r1.kpt.kpt_star == r2.kpt.kpt_star and r1.refine.kpt_plus == r2.refine.kpt_plus
+                    and r1.select.nodes == r2.select.nodes and r1.select.width == r2.select.width):
+                return False
+        return True
+
+    for i in range(args.warmup):
+        sequential()
+        eng.run_batch(batch)
+        log(f"warmup {i + 1}/{args.warmup} done")
+    t_seq, t_bat, identical, info = [], [], True, None
+    sets = 0
+    for i in range(args.steps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seq = sequential()
+        t_seq.append(time.perf_counter() - t0)
+        t0 = time.perf_counter()
+        bat, info = eng.run_batch(batch)
+        t_bat.append(time.perf_counter() - t0)
+        identical = identical and same(seq, bat)
+        sets = sum(int(r.sets_total) for _, _, r in bat)
+        log(f"step {i + 1}/{args.steps}: sequential {t_seq[-1]:.3f} s, batched {t_bat[-1]:.3f} s "
+            f"({info.rounds} rounds, {info.launches} launches, up to {info.max_jobs} jobs), identical={identical}")
+    ts, tb = statistics.median(t_seq), statistics.median(t_bat)
+
+    # one more batch with per-launch timing, for the roofline of the dominant batched kernel
+    eng.profile(True)
+    eng.run_batch(batch)
+    prof = eng.read_profile()
+    eng.profile(False)
+    roofline = dominant_roofline(prof, batch_kernel_name)
+
+    slow = sorted(((r.ms_total, q["name"]) for (_, _, r), q in zip(seq, queries)), reverse=True)[:5]
+    line = {
+        "metric": "TIM+ queries/s, 64 mixed queries batched on 1 GPU (vs the same queries run one by one)",
+        "value": round(64 / tb, 3),
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(tb * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 integer, f64 kappa",
+        "data": "synthetic (64 seeded directed Chung-Lu graphs, alpha=2.1)",
+        "config": {"workload": "batch64_chunglu_ic_trivalency_lt", "queries": 64, "n_range": [10_000, 2_000_000],
+                   "avg_degree_range": [4, 40], "ic_p": list(synth.TRIVALENCY_P), "k_range": [1, 50],
+                   "eps": [0.1, 0.2, 0.5], "ell": 1.0, "seeds": "1000+j",
+                   "edges_total": int(sum(g.m for g, _ in graphs))},
+        "sequential": {"value": round(64 / ts, 3), "unit": "queries/s", "ms_per_step": round(ts * 1e3, 3)},
+        "speedup_vs_sequential": round(ts / tb, 3),
+        "identical_outputs": identical,
+        "rounds": int(info.rounds), "launches": int(info.launches), "max_jobs": int(info.max_jobs),
+        "rr_sets_per_step": sets,
+        "rr_sets_per_s": round(sets / tb, 1),
+        "slowest_alone_ms": {name: round(ms, 3) for ms, name in slow},
+        "roofline": roofline,
+    }
     eng.close()
     print(json.dumps(line), flush=True)
 

@@ -287,6 +287,55 @@ tim_status tim_node_select(tim_ctx *ctx, const tim_graph *g, int model, uint64_t
 tim_status tim_run(tim_ctx *ctx, const tim_graph *g, int model, int k, double eps, double ell, uint64_t seed,
                    uint32_t flags, int32_t *seeds, uint64_t *gains, tim_report *rep);
 
+/* ---- batches of queries -------------------------------------------------- */
+
+/* One TIM / TIM+ query of a batch: tim_run's arguments and results. */
+typedef struct {
+  const tim_graph *graph; /* uploaded to the context passed to tim_run_batch */
+  int model;
+  int k;
+  double eps;
+  double ell;
+  uint64_t seed;
+  uint32_t flags;
+  int32_t *seeds;     /* out: host int32[k] */
+  uint64_t *gains;    /* out: host uint64[k], or NULL */
+  tim_report *report; /* out, or NULL (its times are wall times inside the batch) */
+  tim_status status;  /* out: this query's status */
+} tim_query;
+
+/* What a batch did. */
+typedef struct {
+  uint64_t rounds;       /* batched sampling rounds */
+  uint64_t jobs;         /* sampling requests served by them */
+  uint64_t launches;     /* multi-job launches (one per model, mode and up to 64 requests) */
+  uint64_t max_jobs;     /* largest round */
+  uint64_t workers;      /* queries run at once */
+  uint64_t budget_bytes; /* device memory of the batch */
+  uint64_t member_budget_bytes; /* each query's share of it */
+  double ms_wall;
+} tim_batch_info;
+
+/* Runs `count` independent TIM / TIM+ queries (Sections 3.3 and 4.1) at
+ * once, at most max_concurrent at a time (0: all).  Each query runs the
+ * steps of tim_run in a host thread of its own with buffers of its own;
+ * the RR sets every query needs at the same point (a KptEstimation round,
+ * RefineKPT's sets, NodeSelection's sets) are gathered into one GPU launch
+ * whose wavefronts move from query to query as their work runs out.  Each
+ * query's seeds, gains and report values other than times and memory
+ * figures are those tim_run gives it alone.  The batch's memory is the
+ * context's budget less what it holds (without one: 85% of the free device
+ * memory); after the large-set slots, each query running at once gets an
+ * equal share as its budget, and one whose collection does not fit its
+ * share processes it in regenerated chunks, with the same results.  The
+ * context's resident-set limit applies to every query.  The graphs must
+ * belong to ctx.  Arguments are checked first (TIM_EINVAL, nothing run);
+ * then every query runs and the first failing one's status is returned.
+ * info (host, nullable) receives the batch's statistics.  The window a
+ * round waits for the queries in flight to join it is 1 ms (environment
+ * variable TIM_BATCH_WINDOW_US, read per call). */
+tim_status tim_run_batch(tim_ctx *ctx, tim_query *queries, int count, int max_concurrent, tim_batch_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,7 @@ EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_devi
             "tim_graph_upload",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
-            "tim_profile_read")
+            "tim_profile_read", "tim_run_batch")
 
 U64, I64, U32, I32, DBL, P = (ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
                               ctypes.c_void_p)
@@ -85,6 +85,16 @@ class Profile(ctypes.Structure):
     _fields_ = [("sampler", (KernelProfile * 3) * 2), ("index_calls", U64), ("index_ms", DBL), ("greedy_ms", DBL)]
 
 
+class Query(ctypes.Structure):
+    _fields_ = [("graph", P), ("model", ctypes.c_int), ("k", ctypes.c_int), ("eps", DBL), ("ell", DBL),
+                ("seed", U64), ("flags", U32), ("seeds", P), ("gains", P), ("report", P), ("status", ctypes.c_int)]
+
+
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("rounds", U64), ("jobs", U64), ("launches", U64), ("max_jobs", U64), ("workers", U64),
+                ("budget_bytes", U64), ("member_budget_bytes", U64), ("ms_wall", DBL)]
+
+
 MODE_NAMES = ("widths", "store", "cover")
 MODEL_NAMES = ("ic", "lt")
 
@@ -124,6 +134,8 @@ def load_library():
                                    ctypes.POINTER(Report)]),
         "tim_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "tim_profile_read": (ctypes.c_int, [P, ctypes.POINTER(Profile)]),
+        "tim_run_batch": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.c_int, ctypes.c_int,
+                                         ctypes.POINTER(BatchInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -306,6 +318,26 @@ class Engine:
         _check(self.lib.tim_run(self.ctx, g.handle, model, k, eps, ell, seed, flags, seeds.ctypes.data,
                                 gains.ctypes.data, ctypes.byref(rep)))
         return seeds, gains, rep
+
+    def run_batch(self, queries, max_concurrent: int = 0):
+        """Runs queries [(graph, model, k, eps, ell, seed[, flags]), ...] as one batch.
+
+        Returns ([(seeds, gains, Report) per query], BatchInfo)."""
+        nq = len(queries)
+        arr = (Query * max(nq, 1))()
+        keep = []
+        for i, q in enumerate(queries):
+            g, model, k, eps, ell, seed = q[:6]
+            flags = q[6] if len(q) > 6 else 0
+            seeds = np.zeros(k, dtype=np.int32)
+            gains = np.zeros(k, dtype=np.uint64)
+            rep = Report()
+            keep.append((seeds, gains, rep))
+            arr[i] = Query(g.handle, model, k, eps, ell, seed, flags, seeds.ctypes.data, gains.ctypes.data,
+                           ctypes.addressof(rep), 0)
+        info = BatchInfo()
+        _check(self.lib.tim_run_batch(self.ctx, arr, nq, max_concurrent, ctypes.byref(info)))
+        return keep, info
 
 
 def report_dict(rep: Report, k: int) -> dict:

@@ -10,11 +10,17 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
+#include <chrono>
 #include <cmath>
+#include <condition_variable>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "engine.hpp"
@@ -60,6 +66,8 @@ struct DevBuf {
 // Sets per sampling launch: bounds the deferred-set list of one launch.
 constexpr uint64_t kMaxLaunchSets = 1ull << 26;
 
+struct Hub;
+
 }  // namespace
 
 struct tim_ctx {
@@ -94,6 +102,14 @@ struct tim_ctx {
   int64_t big_n = -1;
   DevBuf rr_off, rr_nodes, sizes, cnt, fill, inv_off, inv_sets, covered, selected, best, scan_tmp, seed_bits;
   hipEvent_t ev[2] = {nullptr, nullptr};
+  // batch member: its sampling launches go to the hub
+  Hub* hub = nullptr;
+  const tim_ctx* parent = nullptr;  // whose graphs it may use
+  // batches run on this context: the hub and its member contexts, kept
+  // (with their buffers) from one tim_run_batch call to the next
+  Hub* batch = nullptr;
+  std::vector<tim_ctx*> members;
+  hipEvent_t ready_ev = nullptr;
   bool prof_on = false;
   hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
   tim_profile prof = {};
@@ -147,11 +163,13 @@ void release(tim_ctx* c, DevBuf& b) {
 }
 
 tim_graph const* check_graph(const tim_ctx* c, const tim_graph* g) {
-  return (c && g && g->ctx == c) ? g : nullptr;
+  return (c && g && (g->ctx == c || (c->parent && g->ctx == c->parent))) ? g : nullptr;
 }
 
-// Per-slot visited stamps and queues of the large-set pass, sized for n.
+// Per-slot visited stamps and queues of the large-set pass, sized for n
+// (batch members use the hub's slots).
 tim_status ensure_big(tim_ctx* c, int64_t n) {
+  if (c->hub) return TIM_OK;
   if (c->big_n == n) return TIM_OK;
   release(c, c->big_stamp);
   release(c, c->big_queue);
@@ -187,6 +205,72 @@ struct Totals {
   u128 kappa = 0;
 };
 
+// ---- batches: one sampling launch for the requests of many queries ----
+//
+// Each query of a batch runs the same host code as tim_run on a context of
+// its own, in a thread of its own.  Where that code would launch a sampler,
+// it hands its SampleArgs to the hub and waits.  The hub's scheduler thread
+// gathers the requests (until every query in flight has one waiting, or a
+// short window after the first has passed), lays them out as a job table
+// and runs them as one multi-job launch per (model, mode) on its stream,
+// then returns each query its counters.  Every set is a function of its own
+// keys, so each query's results are those of tim_run alone.
+
+struct Pending {
+  int model = 0, mode = 0;
+  bool wc = true;
+  SampleArgs a;
+  hipEvent_t ready = nullptr;  // the query's stream has reached the request
+  bool done = false;
+  tim_status st = TIM_OK;
+  std::string err;
+  unsigned long long h[tim::kCtrCount];
+};
+
+struct Hub {
+  int device = 0, num_cu = 0;
+  hipStream_t stream = nullptr;
+  std::mutex mu;
+  std::condition_variable cv_sched, cv_done;
+  std::vector<Pending*> waiting;
+  std::chrono::steady_clock::time_point first_wait;
+  int alive = 0;  // workers that have not run out of queries
+  bool stop = false;
+  std::chrono::microseconds window{1000};
+  uint64_t limit = 0;         // device memory of the batch
+  uint64_t member_budget = 0; // each query's share
+  // job table and counters of a round (pinned host mirrors)
+  SampleArgs* d_jobs = nullptr;
+  SampleArgs* h_jobs = nullptr;
+  unsigned long long* d_ctr = nullptr;
+  unsigned long long* h_ctr = nullptr;
+  size_t cap = 0;
+  // last-tier slots shared by every job
+  uint32_t* big_stamp = nullptr;
+  int32_t* big_queue = nullptr;
+  uint32_t* big_epoch = nullptr;
+  int big_slots = 0;
+  uint64_t big_stride = 0;
+  uint64_t big_bytes = 0;
+  int grid0[2][3][2] = {};  // tier-0 blocks per CU [model][mode][wc]
+  int grid1[3][2] = {};     // IC tier-1 blocks per CU
+  uint64_t emit_waves[2] = {0, 0};
+  // per-launch timing into the owning context's profile (when it is on)
+  tim_ctx* owner = nullptr;
+  hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
+  // statistics
+  uint64_t rounds = 0, jobs = 0, launches = 0, max_jobs = 0;
+};
+
+// Blocks a request waits in until its round has run.
+void hub_submit(Hub* h, Pending* p) {
+  std::unique_lock<std::mutex> lk(h->mu);
+  if (h->waiting.empty()) h->first_wait = std::chrono::steady_clock::now();
+  h->waiting.push_back(p);
+  h->cv_sched.notify_one();
+  h->cv_done.wait(lk, [&] { return p->done; });
+}
+
 // Blocks of the tier-0 sampler over `count` sets (and its wavefronts).
 uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t count, uint64_t* waves) {
   const int per_cu = model == TIM_MODEL_IC ? c->grid_ic[mode][wc ? 1 : 0] : c->grid_lt[mode];
@@ -204,6 +288,7 @@ uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t co
 // Wavefronts of the tier-0 launch over `count` sets (the only tier that
 // reserves node-pool slices; the others reserve exactly what they store).
 uint64_t emit_waves(const tim_ctx* c, int model, uint64_t count) {
+  if (c->hub) return c->hub->emit_waves[model];  // any wavefront of a batched launch may visit a job
   uint64_t waves = 0, w2 = 0;
   sample_grid(c, model, tim::kModeEmit, true, count, &waves);
   sample_grid(c, model, tim::kModeEmit, false, count, &w2);
@@ -284,19 +369,35 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   a.big_queue = c->big_queue.as<int32_t>();
   a.big_epoch = c->big_epoch.as<uint32_t>();
   a.big_slots = c->big_slots;
+  a.big_stride = (uint64_t)c->big_n;
   const bool wc = g->thr == nullptr;
-  const uint64_t grid0 = sample_grid(c, model, mode, wc, count, nullptr);
-  const uint64_t grid1 = (uint64_t)c->grid_ic64[mode][wc ? 1 : 0] * (uint64_t)c->num_cu;
-  tim::launch_clear_counters(c->ctr, c->stream);
-  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
-  tim::launch_sample(model, mode, a, c->seg_lanes, (int)grid0, (int)grid1, c->stream,
-                     c->prof_on ? c->pev[1] : nullptr);
-  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[2], c->stream));
-  HIP_TRY(hipGetLastError());
-  HIP_TRY(hipMemcpyAsync(c->ctr_host, c->ctr, tim::kCtrCount * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                         c->stream));
-  HIP_TRY(hipStreamSynchronize(c->stream));
   const unsigned long long* h = c->ctr_host;
+  Pending req;
+  if (c->hub) {
+    // counters and last-tier slots are filled in by the hub
+    a.ctr = nullptr;
+    req.model = model;
+    req.mode = mode;
+    req.wc = wc;
+    req.a = a;
+    HIP_TRY(hipEventRecord(c->ready_ev, c->stream));
+    req.ready = c->ready_ev;
+    hub_submit(c->hub, &req);
+    if (req.st != TIM_OK) return fail(req.st, "%s", req.err.c_str());
+    h = req.h;
+  } else {
+    const uint64_t grid0 = sample_grid(c, model, mode, wc, count, nullptr);
+    const uint64_t grid1 = (uint64_t)c->grid_ic64[mode][wc ? 1 : 0] * (uint64_t)c->num_cu;
+    tim::launch_clear_counters(c->ctr, c->stream);
+    if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
+    tim::launch_sample(model, mode, a, c->seg_lanes, (int)grid0, (int)grid1, c->stream,
+                       c->prof_on ? c->pev[1] : nullptr);
+    if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[2], c->stream));
+    HIP_TRY(hipGetLastError());
+    HIP_TRY(hipMemcpyAsync(c->ctr_host, c->ctr, tim::kCtrCount * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                           c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
   if (h[tim::kCtrList1] > count || h[tim::kCtrList2] > count) return fail(TIM_EDEVICE, "deferred-set list overflow");
   t->count += count;
   t->deferred += h[tim::kCtrList1];
@@ -308,7 +409,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
     t->covered += acc[tim::kAccCovered];
   }
   t->pool_used += h[tim::kCtrPoolCursor];
-  if (c->prof_on) {
+  if (c->prof_on && !c->hub) {
     float ms_main = 0.f, ms_big = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms_main, c->pev[0], c->pev[1]));
     HIP_TRY(hipEventElapsedTime(&ms_big, c->pev[1], c->pev[2]));
@@ -921,6 +1022,342 @@ tim_status node_select_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t 
   return TIM_OK;
 }
 
+tim_status run_impl(tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell, uint64_t seed,
+                    uint32_t flags, int32_t* seeds, uint64_t* gains, tim_report* rep) {
+  tim_report local;
+  tim_report* r = rep ? rep : &local;
+  memset(r, 0, sizeof(*r));
+  const bool plain = (flags & TIM_FLAG_PLAIN) != 0;
+  double ell_used = ell;
+  if (flags & TIM_FLAG_ELL_ADJUST) ell_used = ell * (1.0 + std::log(plain ? 2.0 : 3.0) / std::log((double)g->n));
+  r->ell_used = ell_used;
+  hipEvent_t t0, t1;
+  HIP_TRY(hipEventCreate(&t0));
+  HIP_TRY(hipEventCreate(&t1));
+  auto lap = [&](double* slot) {
+    (void)hipEventRecord(t1, c->stream);
+    (void)hipEventSynchronize(t1);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, t0, t1);
+    *slot = ms;
+    (void)hipEventRecord(t0, c->stream);
+  };
+  (void)hipEventRecord(t0, c->stream);
+  tim_status st =
+      kpt_estimate_impl(c, g, model, seed, k, ell_used, !plain, &r->kpt, &r->sets_total, &r->width_total);
+  if (st == TIM_OK) lap(&r->ms_kpt);
+  // mean set size of the stopping round sizes the node pools
+  const int il = r->kpt.i_last;
+  const double mean_nodes =
+      (il >= 1 && r->kpt.round_c[il]) ? (double)r->kpt.round_nodes[il] / (double)r->kpt.round_c[il] : 16.0;
+  double lb = r->kpt.kpt_star;
+  std::vector<int32_t> sp((size_t)k);
+  if (st == TIM_OK && !plain) {
+    st = refine_impl(c, g, model, seed, k, eps, ell_used, r->kpt.kpt_star, r->kpt.i_last, r->kpt.c_last,
+                     (uint64_t)(mean_nodes * 1.25 * (double)r->kpt.c_last) + 4096, sp.data(), &r->refine,
+                     &r->sets_total, &r->width_total);
+    if (st == TIM_OK) {
+      lap(&r->ms_refine);
+      lb = r->refine.kpt_plus;
+      for (int j = 0; j < k && j < 128; ++j) r->s_prime[j] = sp[(size_t)j];
+    }
+  }
+  if (st == TIM_OK) {
+    r->lambda = lambda_eq4(g->n, k, eps, ell_used);
+    const uint64_t theta = (uint64_t)std::ceil(r->lambda / lb);
+    SelectTimes times;
+    st = node_select_impl(c, g, model, seed, k, theta, (uint64_t)(mean_nodes * 1.25 * (double)theta) + 4096, seeds,
+                          gains, &r->select, &times);
+    if (st == TIM_OK) {
+      r->ms_select_sample = times.sample;
+      r->ms_select_index = 0.0;
+      r->ms_select_greedy = times.index_greedy;
+      r->sets_total += theta;
+      r->width_total += r->select.width;
+      r->ms_total = r->ms_kpt + r->ms_refine + r->ms_select_sample + r->ms_select_greedy;
+    }
+  }
+  (void)hipEventDestroy(t0);
+  (void)hipEventDestroy(t1);
+  return st;
+}
+
+tim_status check_run_args(const tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell,
+                          const int32_t* seeds) {
+  TIM_TRY(check_phase_args(c, g, model, k));
+  if (!seeds) return fail(TIM_EINVAL, "seeds is null");
+  if (!(eps > 0.0 && eps <= 1.0)) return fail(TIM_EINVAL, "eps must be in (0, 1]");
+  if (!(ell >= 0.5)) return fail(TIM_EINVAL, "ell must be >= 0.5");
+  return TIM_OK;
+}
+
+// ---- batch rounds ----
+
+// One round: the requests in `subs` as one job table, one multi-job launch
+// per run of at most kMaxBatchJobs requests of the same (model, mode,
+// thresholds), all on the hub's stream.
+tim_status hub_round(Hub* h, std::vector<Pending*>& subs) {
+  auto cls = [](const Pending* p) { return (p->model * 3 + p->mode) * 2 + (p->wc ? 1 : 0); };
+  std::stable_sort(subs.begin(), subs.end(), [&](const Pending* x, const Pending* y) { return cls(x) < cls(y); });
+  const size_t J = subs.size();
+  if (J > h->cap) {
+    (void)hipStreamSynchronize(h->stream);
+    if (h->d_jobs) (void)hipFree(h->d_jobs);
+    if (h->h_jobs) (void)hipHostFree(h->h_jobs);
+    if (h->d_ctr) (void)hipFree(h->d_ctr);
+    if (h->h_ctr) (void)hipHostFree(h->h_ctr);
+    h->d_jobs = h->h_jobs = nullptr;
+    h->d_ctr = h->h_ctr = nullptr;
+    h->cap = 0;
+    const size_t cap = std::max<size_t>(J, 64);
+    HIP_TRY(hipMalloc(&h->d_jobs, cap * sizeof(SampleArgs)));
+    HIP_TRY(hipHostMalloc(&h->h_jobs, cap * sizeof(SampleArgs), hipHostMallocDefault));
+    HIP_TRY(hipMalloc(&h->d_ctr, cap * tim::kCtrCount * sizeof(unsigned long long)));
+    HIP_TRY(hipHostMalloc(&h->h_ctr, cap * tim::kCtrCount * sizeof(unsigned long long), hipHostMallocDefault));
+    h->cap = cap;
+  }
+  for (size_t i = 0; i < J; ++i) {
+    SampleArgs& a = subs[i]->a;
+    if ((uint64_t)a.g.n > h->big_stride) return fail(TIM_EINVAL, "graph larger than the batch's slots");
+    a.ctr = h->d_ctr + i * tim::kCtrCount;
+    a.big_stamp = h->big_stamp;
+    a.big_queue = h->big_queue;
+    a.big_epoch = h->big_epoch;
+    a.big_slots = h->big_slots;
+    a.big_stride = h->big_stride;
+    h->h_jobs[i] = a;
+    HIP_TRY(hipStreamWaitEvent(h->stream, subs[i]->ready, 0));
+  }
+  HIP_TRY(hipMemcpyAsync(h->d_jobs, h->h_jobs, J * sizeof(SampleArgs), hipMemcpyHostToDevice, h->stream));
+  tim::launch_clear_counters_batch(tim::JobTable{h->d_jobs, (int)J}, h->stream);
+  for (size_t lo = 0; lo < J;) {
+    size_t hi = lo + 1;
+    while (hi < J && cls(subs[hi]) == cls(subs[lo]) && hi - lo < (size_t)tim::kMaxBatchJobs) ++hi;
+    const Pending* p = subs[lo];
+    uint64_t total = 0, maxc = 0;
+    for (size_t i = lo; i < hi; ++i) {
+      total += subs[i]->a.count;
+      maxc = std::max<uint64_t>(maxc, subs[i]->a.count);
+    }
+    const uint64_t per_block = p->model == TIM_MODEL_IC ? 32 : 128;  // sets a tier-0 block holds at once
+    const uint64_t full = (uint64_t)h->grid0[p->model][p->mode][p->wc ? 1 : 0] * (uint64_t)h->num_cu;
+    const uint64_t grid0 = std::max<uint64_t>(1, std::min(full, (total + per_block - 1) / per_block));
+    const uint64_t grid1 = (uint64_t)h->grid1[p->mode][p->wc ? 1 : 0] * (uint64_t)h->num_cu;
+    const bool prof = h->owner && h->owner->prof_on;
+    if (prof) HIP_TRY(hipEventRecord(h->pev[0], h->stream));
+    tim::launch_sample_batch(p->model, p->mode, p->wc, tim::JobTable{h->d_jobs + lo, (int)(hi - lo)}, (int)grid0,
+                             (int)grid1, h->big_slots, maxc, h->stream, prof ? h->pev[1] : nullptr);
+    if (prof) {
+      // the profile needs this launch's counters: wait for it
+      HIP_TRY(hipEventRecord(h->pev[2], h->stream));
+      HIP_TRY(hipMemcpyAsync(h->h_ctr + lo * tim::kCtrCount, h->d_ctr + lo * tim::kCtrCount,
+                             (hi - lo) * tim::kCtrCount * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                             h->stream));
+      HIP_TRY(hipStreamSynchronize(h->stream));
+      float ms_main = 0.f, ms_big = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms_main, h->pev[0], h->pev[1]));
+      HIP_TRY(hipEventElapsedTime(&ms_big, h->pev[1], h->pev[2]));
+      tim_kernel_profile& kp = h->owner->prof.sampler[p->model][p->mode];
+      for (size_t i = lo; i < hi; ++i) {
+        const unsigned long long* hc = h->h_ctr + i * tim::kCtrCount;
+        const unsigned long long* acc0 = hc + tim::kCtrAcc;
+        const uint64_t sets = subs[i]->a.count - hc[tim::kCtrList1];
+        const uint64_t nodes = acc0[tim::kAccNodes], edges = acc0[tim::kAccWidth];
+        uint64_t bytes = p->model == TIM_MODEL_IC ? 16 * nodes + (p->wc ? 4 : 8) * edges : 20 * nodes;
+        if (p->mode == tim::kModeEmit) bytes += 4 * nodes + 12 * sets;
+        kp.sets += sets;
+        kp.nodes += nodes;
+        kp.edges += edges;
+        kp.bytes += bytes;
+        kp.deferred += hc[tim::kCtrList1];
+      }
+      kp.launches += 1;
+      kp.kernel_ms += ms_main;
+      kp.large_launches += 1;
+      kp.large_ms += ms_big;
+    }
+    h->launches += 1;
+    lo = hi;
+  }
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(h->h_ctr, h->d_ctr, J * tim::kCtrCount * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                         h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (size_t i = 0; i < J; ++i)
+    memcpy(subs[i]->h, h->h_ctr + i * tim::kCtrCount, sizeof(subs[i]->h));
+  h->rounds += 1;
+  h->jobs += J;
+  h->max_jobs = std::max<uint64_t>(h->max_jobs, J);
+  return TIM_OK;
+}
+
+void hub_scheduler(Hub* h) {
+  (void)hipSetDevice(h->device);
+  std::unique_lock<std::mutex> lk(h->mu);
+  for (;;) {
+    h->cv_sched.wait(lk, [&] { return h->stop || !h->waiting.empty(); });
+    if (h->waiting.empty()) break;  // stop with nothing pending
+    // gather until every worker still running waits, or the window has passed
+    h->cv_sched.wait_until(lk, h->first_wait + h->window, [&] { return (int)h->waiting.size() >= h->alive; });
+    std::vector<Pending*> subs;
+    subs.swap(h->waiting);
+    lk.unlock();
+    const tim_status st = hub_round(h, subs);
+    const std::string err = st == TIM_OK ? std::string() : g_error;
+    lk.lock();
+    for (Pending* p : subs) {
+      p->st = st;
+      p->err = err;
+      p->done = true;
+    }
+    // requests that came in during the round get a fresh window, so that the
+    // queries this round releases can join them
+    if (!h->waiting.empty()) h->first_wait = std::chrono::steady_clock::now();
+    h->cv_done.notify_all();
+  }
+}
+
+void hub_leave(Hub* h) {
+  std::lock_guard<std::mutex> lk(h->mu);
+  h->alive -= 1;
+  h->cv_sched.notify_one();
+}
+
+// A member context of the hub: its own stream and buffers, and 8 lanes per
+// IC set in tier 0 (the batched kernels' shape).
+tim_status hub_member(Hub* h, const tim_ctx* parent, tim_ctx** out) {
+  tim_ctx* c = nullptr;
+  TIM_TRY(tim_ctx_create(parent->device, nullptr, 0, &c));
+  c->hub = h;
+  c->parent = parent;
+  c->seg_lanes = 8;
+  if (hipEventCreateWithFlags(&c->ready_ev, hipEventDisableTiming) != hipSuccess) {
+    tim_ctx_destroy(c);
+    return fail(TIM_EDEVICE, "hipEventCreate failed");
+  }
+  *out = c;
+  return TIM_OK;
+}
+
+void batch_worker(Hub* h, tim_ctx* c, tim_query* qs, int nq, std::atomic<int>* next,
+                  std::vector<std::string>* errs) {
+  (void)hipSetDevice(c->device);
+  for (;;) {
+    const int i = next->fetch_add(1);
+    if (i >= nq) break;
+    tim_query& q = qs[i];
+    q.status = run_impl(c, q.graph, q.model, q.k, q.eps, q.ell, q.seed, q.flags, q.seeds, q.gains, q.report);
+    if (q.status != TIM_OK) (*errs)[(size_t)i] = g_error;
+  }
+  c->stored.valid = false;
+  hub_leave(h);
+}
+
+// The hub's stream and launch shapes (once per context).
+tim_status hub_setup(Hub* h, tim_ctx* parent) {
+  h->owner = parent;
+  h->device = parent->device;
+  h->num_cu = parent->num_cu;
+  HIP_TRY(hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking));
+  for (hipEvent_t& e : h->pev) HIP_TRY(hipEventCreate(&e));
+  for (int model = 0; model < 2; ++model)
+    for (int mode = 0; mode < 3; ++mode)
+      for (int wc = 0; wc < 2; ++wc) h->grid0[model][mode][wc] = tim::batch_blocks_per_cu(model, mode, wc != 0, 0);
+  for (int mode = 0; mode < 3; ++mode)
+    for (int wc = 0; wc < 2; ++wc) h->grid1[mode][wc] = tim::batch_blocks_per_cu(0, mode, wc != 0, 1);
+  h->emit_waves[0] = (uint64_t)std::max(h->grid0[0][1][0], h->grid0[0][1][1]) * (uint64_t)h->num_cu * 4;
+  h->emit_waves[1] = (uint64_t)h->grid0[1][1][0] * (uint64_t)h->num_cu * 2;
+  return TIM_OK;
+}
+
+void hub_free_slots(Hub* h) {
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  void* dev[] = {h->big_stamp, h->big_queue, h->big_epoch};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  h->big_stamp = nullptr;
+  h->big_queue = nullptr;
+  h->big_epoch = nullptr;
+  h->big_slots = 0;
+  h->big_stride = 0;
+  h->big_bytes = 0;
+}
+
+// Memory of one call: the batch gets the context's budget less what the
+// context itself holds (without a budget: 85% of the device memory that is
+// free or already held by the hub and its members); the last-tier slots for
+// the largest graph come first (one per CU where a quarter of it allows),
+// and every query running at once gets an equal share of the rest.
+tim_status hub_prepare(Hub* h, tim_ctx* parent, const tim_query* qs, int nq, int workers) {
+  uint64_t limit = 0;
+  if (parent->budget) {
+    limit = parent->budget > parent->held ? parent->budget - parent->held : 0;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+    uint64_t ours = h->big_bytes;
+    for (const tim_ctx* m : parent->members) ours += m->held;
+    limit = (uint64_t)(0.85 * (double)(free_b + ours));
+  }
+  h->limit = limit;
+  int64_t maxn = 2;
+  for (int i = 0; i < nq; ++i) maxn = std::max<int64_t>(maxn, qs[i].graph->n);
+  const uint64_t per = (uint64_t)maxn * 8;
+  const int slots = (int)std::min<uint64_t>((uint64_t)std::max(h->num_cu, 64), limit / 4 / per);
+  if (slots < 1) return fail(TIM_EBUDGET, "budget too small for the large-set pass of the batch");
+  if (h->big_stride < (uint64_t)maxn || h->big_slots != slots) {
+    hub_free_slots(h);
+    HIP_TRY(hipMalloc(&h->big_stamp, (size_t)slots * (size_t)maxn * 4));
+    HIP_TRY(hipMalloc(&h->big_queue, (size_t)slots * (size_t)maxn * 4));
+    HIP_TRY(hipMalloc(&h->big_epoch, (size_t)slots * 4));
+    HIP_TRY(hipMemsetAsync(h->big_stamp, 0, (size_t)slots * (size_t)maxn * 4, h->stream));
+    HIP_TRY(hipMemsetAsync(h->big_epoch, 0, (size_t)slots * 4, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->big_stride = (uint64_t)maxn;
+    h->big_slots = slots;
+    h->big_bytes = (uint64_t)slots * per + (uint64_t)slots * 4;
+  }
+  h->member_budget = (limit - std::min(limit, h->big_bytes)) / (uint64_t)workers;
+  if (h->member_budget < (1u << 20)) return fail(TIM_EBUDGET, "budget too small for %d queries at once", workers);
+  while ((int)parent->members.size() < workers) {
+    tim_ctx* m = nullptr;
+    TIM_TRY(hub_member(h, parent, &m));
+    parent->members.push_back(m);
+  }
+  for (int w = 0; w < workers; ++w) {
+    tim_ctx* m = parent->members[(size_t)w];
+    m->budget = h->member_budget;
+    m->resident_limit = parent->resident_limit;
+    if (m->held > m->budget) release_transients(m);
+  }
+  // this call's state
+  const char* env = getenv("TIM_BATCH_WINDOW_US");
+  h->window = std::chrono::microseconds(env ? std::max(0L, atol(env)) : 1000L);
+  h->waiting.clear();
+  h->stop = false;
+  h->alive = workers;
+  h->rounds = h->jobs = h->launches = h->max_jobs = 0;
+  return TIM_OK;
+}
+
+void hub_destroy(tim_ctx* parent) {
+  for (tim_ctx* m : parent->members) tim_ctx_destroy(m);
+  parent->members.clear();
+  Hub* h = parent->batch;
+  if (!h) return;
+  hub_free_slots(h);
+  void* dev[] = {h->d_jobs, h->d_ctr};
+  for (void* p : dev)
+    if (p) (void)hipFree(p);
+  if (h->h_jobs) (void)hipHostFree(h->h_jobs);
+  if (h->h_ctr) (void)hipHostFree(h->h_ctr);
+  for (hipEvent_t e : h->pev)
+    if (e) (void)hipEventDestroy(e);
+  if (h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+  parent->batch = nullptr;
+}
+
 }  // namespace
 
 // =========================================================================
@@ -978,6 +1415,7 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
 void tim_ctx_destroy(tim_ctx* c) {
   if (!c) return;
   (void)hipSetDevice(c->device);
+  hub_destroy(c);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->list1, &c->list2, &c->wbuf, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
                     &c->rr_off, &c->rr_nodes, &c->sizes, &c->cnt, &c->fill, &c->inv_off, &c->inv_sets, &c->covered,
@@ -989,6 +1427,7 @@ void tim_ctx_destroy(tim_ctx* c) {
     if (e) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->pev)
     if (e) (void)hipEventDestroy(e);
+  if (c->ready_ev) (void)hipEventDestroy(c->ready_ev);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -1190,67 +1629,61 @@ tim_status tim_node_select(tim_ctx* c, const tim_graph* g, int model, uint64_t s
 
 tim_status tim_run(tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell, uint64_t seed,
                    uint32_t flags, int32_t* seeds, uint64_t* gains, tim_report* rep) {
-  TIM_TRY(check_phase_args(c, g, model, k));
-  if (!seeds) return fail(TIM_EINVAL, "seeds is null");
-  if (!(eps > 0.0 && eps <= 1.0)) return fail(TIM_EINVAL, "eps must be in (0, 1]");
-  if (!(ell >= 0.5)) return fail(TIM_EINVAL, "ell must be >= 0.5");
+  TIM_TRY(check_run_args(c, g, model, k, eps, ell, seeds));
   HIP_TRY(hipSetDevice(c->device));
-  tim_report local;
-  tim_report* r = rep ? rep : &local;
-  memset(r, 0, sizeof(*r));
-  const bool plain = (flags & TIM_FLAG_PLAIN) != 0;
-  double ell_used = ell;
-  if (flags & TIM_FLAG_ELL_ADJUST) ell_used = ell * (1.0 + std::log(plain ? 2.0 : 3.0) / std::log((double)g->n));
-  r->ell_used = ell_used;
-  hipEvent_t t0, t1;
-  HIP_TRY(hipEventCreate(&t0));
-  HIP_TRY(hipEventCreate(&t1));
-  auto lap = [&](double* slot) {
-    (void)hipEventRecord(t1, c->stream);
-    (void)hipEventSynchronize(t1);
-    float ms = 0.f;
-    (void)hipEventElapsedTime(&ms, t0, t1);
-    *slot = ms;
-    (void)hipEventRecord(t0, c->stream);
-  };
-  (void)hipEventRecord(t0, c->stream);
-  tim_status st =
-      kpt_estimate_impl(c, g, model, seed, k, ell_used, !plain, &r->kpt, &r->sets_total, &r->width_total);
-  if (st == TIM_OK) lap(&r->ms_kpt);
-  // mean set size of the stopping round sizes the node pools
-  const int il = r->kpt.i_last;
-  const double mean_nodes =
-      (il >= 1 && r->kpt.round_c[il]) ? (double)r->kpt.round_nodes[il] / (double)r->kpt.round_c[il] : 16.0;
-  double lb = r->kpt.kpt_star;
-  std::vector<int32_t> sp((size_t)k);
-  if (st == TIM_OK && !plain) {
-    st = refine_impl(c, g, model, seed, k, eps, ell_used, r->kpt.kpt_star, r->kpt.i_last, r->kpt.c_last,
-                     (uint64_t)(mean_nodes * 1.25 * (double)r->kpt.c_last) + 4096, sp.data(), &r->refine,
-                     &r->sets_total, &r->width_total);
-    if (st == TIM_OK) {
-      lap(&r->ms_refine);
-      lb = r->refine.kpt_plus;
-      for (int j = 0; j < k && j < 128; ++j) r->s_prime[j] = sp[(size_t)j];
+  return run_impl(c, g, model, k, eps, ell, seed, flags, seeds, gains, rep);
+}
+
+tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_concurrent, tim_batch_info* info) {
+  if (!c || (count > 0 && !queries)) return fail(TIM_EINVAL, "null argument");
+  if (count < 0 || max_concurrent < 0) return fail(TIM_EINVAL, "negative count");
+  if (c->hub) return fail(TIM_EINVAL, "context is a batch member");
+  if (info) memset(info, 0, sizeof(*info));
+  for (int i = 0; i < count; ++i) {
+    tim_query& q = queries[i];
+    q.status = check_run_args(c, q.graph, q.model, q.k, q.eps, q.ell, q.seeds);
+    if (q.status != TIM_OK) return fail(q.status, "query %d: %s", i, g_error.c_str());
+  }
+  if (count == 0) return TIM_OK;
+  HIP_TRY(hipSetDevice(c->device));
+  const auto t0 = std::chrono::steady_clock::now();
+  const int workers = (max_concurrent == 0 || max_concurrent > count) ? count : max_concurrent;
+  if (!c->batch) {
+    c->batch = new Hub();
+    const tim_status st = hub_setup(c->batch, c);
+    if (st != TIM_OK) {
+      hub_destroy(c);
+      return st;
     }
   }
-  if (st == TIM_OK) {
-    r->lambda = lambda_eq4(g->n, k, eps, ell_used);
-    const uint64_t theta = (uint64_t)std::ceil(r->lambda / lb);
-    SelectTimes times;
-    st = node_select_impl(c, g, model, seed, k, theta, (uint64_t)(mean_nodes * 1.25 * (double)theta) + 4096, seeds,
-                          gains, &r->select, &times);
-    if (st == TIM_OK) {
-      r->ms_select_sample = times.sample;
-      r->ms_select_index = 0.0;
-      r->ms_select_greedy = times.index_greedy;
-      r->sets_total += theta;
-      r->width_total += r->select.width;
-      r->ms_total = r->ms_kpt + r->ms_refine + r->ms_select_sample + r->ms_select_greedy;
-    }
+  Hub& hub = *c->batch;
+  TIM_TRY(hub_prepare(&hub, c, queries, count, workers));
+  std::atomic<int> next{0};
+  std::vector<std::string> errs((size_t)count);
+  std::thread sched(hub_scheduler, &hub);
+  std::vector<std::thread> pool;
+  for (int w = 0; w < workers; ++w)
+    pool.emplace_back(batch_worker, &hub, c->members[(size_t)w], queries, count, &next, &errs);
+  for (std::thread& t : pool) t.join();
+  {
+    std::lock_guard<std::mutex> lk(hub.mu);
+    hub.stop = true;
+    hub.cv_sched.notify_one();
   }
-  (void)hipEventDestroy(t0);
-  (void)hipEventDestroy(t1);
-  return st;
+  sched.join();
+  if (info) {
+    info->rounds = hub.rounds;
+    info->jobs = hub.jobs;
+    info->launches = hub.launches;
+    info->max_jobs = hub.max_jobs;
+    info->workers = (uint64_t)workers;
+    info->budget_bytes = hub.limit;
+    info->member_budget_bytes = hub.member_budget;
+    info->ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  for (int i = 0; i < count; ++i)
+    if (queries[i].status != TIM_OK) return fail(queries[i].status, "query %d: %s", i, errs[(size_t)i].c_str());
+  return TIM_OK;
 }
 
 }  // extern "C"

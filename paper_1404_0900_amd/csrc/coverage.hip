@@ -163,16 +163,22 @@ struct PoolSets {  // node pool as the samplers leave it (per-set start and size
 // A tile's updates to the same node (hub nodes recur in many RR sets) are
 // summed in an LDS open-addressing table (at most about half full for a tile
 // of typical sets) and reach device memory as one atomic per distinct node
-// per tile.  Nodes that find the table full fall back to direct atomics.
+// per tile.  A node that finds no free slot among the first kAggProbes of its
+// probe sequence falls back to direct atomics: a tile holding a set larger
+// than the table (a set reaching a giant component) fills it, and without
+// the bound every later entry would scan the whole table.  Probe sequences
+// are fixed per node and slots are never freed within a tile, so a node is
+// either in the table for all of its entries of the tile or for none.
 constexpr int kAggLog = 12;
 constexpr int kAgg = 1 << kAggLog;
+constexpr int kAggProbes = 32;
 constexpr int kTileSets = 128;      // sets per tile (set-tiled kernels)
 constexpr int kTileEntries = 2048;  // entries per tile (flat histogram)
 
 __device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert) {
   const uint32_t key = u + 1u;
   uint32_t pos = (u * 0x9E3779B1u) >> (32 - kAggLog);
-  for (int i = 0; i < kAgg; ++i) {
+  for (int i = 0; i < kAggProbes; ++i) {
     const uint32_t cur = keys[pos];
     if (cur == key) return (int)pos;
     if (cur == 0u) {

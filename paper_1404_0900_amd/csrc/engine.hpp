@@ -82,6 +82,7 @@ struct SampleArgs {
   int32_t* big_queue;
   uint32_t* big_epoch;
   int big_slots;
+  uint64_t big_stride;  // entries per slot in big_stamp / big_queue (>= n)
 };
 
 // ---- sample.hip ----
@@ -100,6 +101,22 @@ uint32_t tier0_set_cap(int model, int seg_lanes);
 // between tier 0 and the rest.
 void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int grid0, int grid1, hipStream_t s,
                    hipEvent_t after_tier0);
+
+// Sampling jobs of several queries in one launch (device array of njobs
+// SampleArgs, 1 <= njobs <= 64, one mode and model; all jobs point at the
+// same last-tier slots).  Tier 0 of IC uses 8 lanes per set.
+struct JobTable {
+  const SampleArgs* jobs;
+  int njobs;
+};
+constexpr int kMaxBatchJobs = 64;
+// Occupancy of the batched tier-0 (tier 0) or tier-1 (tier 1, IC) kernel.
+int batch_blocks_per_cu(int model, int mode, bool wc, int tier);
+void launch_clear_counters_batch(const JobTable& t, hipStream_t s);
+// All tiers and the kappa sums; max_count is the largest job's count.
+// after_tier0, if given, is recorded between tier 0 and the rest.
+void launch_sample_batch(int model, int mode, bool wc, const JobTable& t, int grid0, int grid1, int slots,
+                         uint64_t max_count, hipStream_t s, hipEvent_t after_tier0);
 
 // ---- coverage.hip ----
 // out[0..len] = exclusive prefix sums of in[0..len), out[len] = total.

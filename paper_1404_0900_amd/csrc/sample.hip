@@ -322,7 +322,7 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
 // Width mode writes w(R) per set; kappa is summed by kappa_reduce_kernel.
 // ------------------------------------------------------------------------
 template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
-__global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
+__device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io) {
   constexpr bool kHash = HLOG > 0;
   constexpr int H = kHash ? (1 << HLOG) : 4;
   constexpr int NSEG = kSegThreads / S;
@@ -623,6 +623,11 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierI
   wave_flush(a, acc, io.acc, lane);
 }
 
+template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
+__global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
+  ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, io);
+}
+
 // Exact sum of kappa(R) * 2^53 over the widths a width-mode launch wrote
 // (Equation (8)); optionally copies the widths out as uint64.
 __global__ __launch_bounds__(kSegThreads) void kappa_reduce_kernel(SampleArgs a) {
@@ -641,7 +646,7 @@ __global__ __launch_bounds__(kSegThreads) void kappa_reduce_kernel(SampleArgs a)
 // ------------------------------------------------------------------------
 
 template <int MODE>
-__global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, TierIO io) {
+__device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& io) {
   __shared__ int32_t s_chain[kLtWaves][kChain][kWave];
   const int wv = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -765,13 +770,18 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, 
   wave_flush(a, acc, io.acc, lane);
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, TierIO io) {
+  lt_lane_run<MODE>(a, io);
+}
+
 // ------------------------------------------------------------------------
 // Last tier.
 // ------------------------------------------------------------------------
 
 // IC: one 256-thread block per set, visited stamps and queue in device memory.
 template <int MODE, bool WC>
-__global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierIO io) {
+__device__ __forceinline__ void ic_big_run(const SampleArgs& a, const TierIO& io, int slot) {
   constexpr int T = kBigThreads;
   __shared__ uint32_t s_incl[T];
   __shared__ int64_t s_ea[T];
@@ -785,9 +795,8 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
   const int lane = tid % kWave, wv = tid / kWave;
   const GraphView g = a.g;
   const Key key = make_key(a.seed);
-  const int slot = blockIdx.x;
-  uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)g.n;
-  int32_t* queue = a.big_queue + (size_t)slot * (size_t)g.n;
+  uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)a.big_stride;
+  int32_t* queue = a.big_queue + (size_t)slot * (size_t)a.big_stride;
   const unsigned long long ndef = list_len(a, io.in_len_ctr);
   Acc acc;
 
@@ -801,7 +810,7 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
     if (idx >= ndef) break;
     uint32_t epoch = s_epoch;
     if (epoch == 0u) {  // stamp counter wrapped: start the slot afresh
-      for (int64_t i = tid; i < g.n; i += T) stamp[i] = 0u;
+      for (uint64_t i = tid; i < a.big_stride; i += T) stamp[i] = 0u;
       epoch = 1u;
     }
     const unsigned long long rel = io.in_list[idx];
@@ -920,23 +929,26 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
   if (tid == 0) block_flush(a, acc, io.acc);
 }
 
-// LT: one lane per set, visited stamps and chain in device memory.
+template <int MODE, bool WC>
+__global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierIO io) {
+  ic_big_run<MODE, WC>(a, io, blockIdx.x);
+}
+
+// LT: one lane per set, visited stamps and chain in device memory.  `epoch`
+// is the slot's stamp epoch, carried from set to set.
 template <int MODE>
-__global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) {
-  const int slot = blockIdx.x * kWave + threadIdx.x;
-  if (slot >= a.big_slots) return;
+__device__ __forceinline__ void lt_big_run(const SampleArgs& a, const TierIO& io, int slot, uint32_t& epoch) {
   const GraphView g = a.g;
   const Key key = make_key(a.seed);
-  uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)g.n;
-  int32_t* chain = a.big_queue + (size_t)slot * (size_t)g.n;
+  uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)a.big_stride;
+  int32_t* chain = a.big_queue + (size_t)slot * (size_t)a.big_stride;
   const unsigned long long ndef = list_len(a, io.in_len_ctr);
-  uint32_t epoch = a.big_epoch[slot];
   Acc acc;
   for (;;) {
     const unsigned long long idx = atomicAdd(&a.ctr[io.next_ctr], 1ull);
     if (idx >= ndef) break;
     if (++epoch == 0u) {
-      for (int64_t i = 0; i < g.n; ++i) stamp[i] = 0u;
+      for (uint64_t i = 0; i < a.big_stride; ++i) stamp[i] = 0u;
       epoch = 1u;
     }
     const unsigned long long rel = io.in_list[idx];
@@ -981,11 +993,154 @@ __global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) 
       if (hit) acc.covered += 1;
     }
   }
-  a.big_epoch[slot] = epoch;
   block_flush(a, acc, io.acc);
 }
 
+template <int MODE>
+__global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) {
+  const int slot = blockIdx.x * kWave + threadIdx.x;
+  if (slot >= a.big_slots) return;
+  uint32_t epoch = a.big_epoch[slot];
+  lt_big_run<MODE>(a, io, slot, epoch);
+  a.big_epoch[slot] = epoch;
+}
+
 __global__ void clear_counters_kernel(unsigned long long* ctr) {
+  for (int i = threadIdx.x; i < kCtrCount; i += blockDim.x) ctr[i] = 0ull;
+}
+
+// ------------------------------------------------------------------------
+// Several sampling jobs in one launch: the RR sets that many TIM+ queries
+// need at one point of their runs.  A job is a whole SampleArgs (its own
+// graph, keys, range of set ids, counters, node pool and deferral lists); the
+// jobs of a launch share its mode and model and the last-tier slots.  Every
+// wavefront (IC last tier: every block) starts on a different job and, once
+// that job's cursor is spent, moves on to the next job that still has sets
+// for its tier: short jobs do not leave the chip idle, and the longest job
+// has every wavefront at the end.
+// ------------------------------------------------------------------------
+
+// Where tier `tier` of a job reads and sends its sets (IC: tiers 0, 1, 2;
+// LT: tiers 0 and 2).
+template <int MODEL>
+__device__ __forceinline__ TierIO tier_io(const SampleArgs& a, int tier) {
+  if (tier == 0) return TierIO{nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
+  if (MODEL == 0 && tier == 1) return TierIO{a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1};
+  if (MODEL == 0) return TierIO{a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2};
+  return TierIO{a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2};
+}
+
+__device__ __forceinline__ unsigned long long load_ctr(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Bit j set: job j still has unclaimed sets in `tier` (lane j looks).  A
+// stale counter is never larger than the true one, so a job is never skipped
+// while it has work; at worst a spent job is visited once more.
+template <int MODEL>
+__device__ __forceinline__ uint64_t jobs_with_work(const JobTable& t, int tier, int lane) {
+  bool w = false;
+  if (lane < t.njobs) {
+    const SampleArgs* a = t.jobs + lane;
+    unsigned long long total = a->count;
+    int next = kCtrNext0;
+    if (tier > 0) {
+      const int len_ctr = (MODEL == 0 && tier == 2) ? kCtrList2 : kCtrList1;
+      const unsigned long long d = load_ctr(a->ctr + len_ctr);
+      total = d < total ? d : total;
+      next = tier == 1 ? kCtrNext1 : kCtrNext2;
+    }
+    w = load_ctr(a->ctr + next) < total;
+  }
+  return __ballot(w);
+}
+
+// The first job of mask m at or after `from`, cyclically; -1 if none.
+__device__ __forceinline__ int next_job(uint64_t m, int from) {
+  if (!m) return -1;
+  const uint64_t hi = from < 64 ? m & (~0ull << from) : 0ull;
+  return __ffsll((unsigned long long)(hi ? hi : m)) - 1;
+}
+
+template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
+__global__ __launch_bounds__(kSegThreads) void ic_seg_batch_kernel(JobTable t, int tier) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = blockIdx.x * (kSegThreads / kWave) + threadIdx.x / kWave;
+  int from = wave % t.njobs;
+  for (;;) {
+    const int j = __builtin_amdgcn_readfirstlane(next_job(jobs_with_work<0>(t, tier, lane), from));
+    if (j < 0) break;
+    const SampleArgs& a = t.jobs[j];
+    ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, tier_io<0>(a, tier));
+    from = j + 1;
+  }
+}
+
+template <int MODE, bool WC>
+__global__ __launch_bounds__(kBigThreads) void ic_big_batch_kernel(JobTable t) {
+  __shared__ int s_job;
+  int from = blockIdx.x % t.njobs;
+  for (;;) {
+    if (threadIdx.x < kWave) {
+      const int j = next_job(jobs_with_work<0>(t, 2, threadIdx.x), from);
+      if (threadIdx.x == 0) s_job = j;
+    }
+    __syncthreads();
+    const int j = __builtin_amdgcn_readfirstlane(s_job);
+    __syncthreads();
+    if (j < 0) break;
+    const SampleArgs& a = t.jobs[j];
+    ic_big_run<MODE, WC>(a, tier_io<0>(a, 2), blockIdx.x);
+    from = j + 1;
+  }
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_batch_kernel(JobTable t) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = blockIdx.x * kLtWaves + threadIdx.x / kWave;
+  int from = wave % t.njobs;
+  for (;;) {
+    const int j = __builtin_amdgcn_readfirstlane(next_job(jobs_with_work<1>(t, 0, lane), from));
+    if (j < 0) break;
+    const SampleArgs& a = t.jobs[j];
+    lt_lane_run<MODE>(a, tier_io<1>(a, 0));
+    from = j + 1;
+  }
+}
+
+// One lane per slot; every lane visits every job once (its deferred chains
+// are few), starting at a different one.
+template <int MODE>
+__global__ __launch_bounds__(kWave) void lt_big_batch_kernel(JobTable t, int slots) {
+  const int slot = blockIdx.x * kWave + threadIdx.x;
+  if (slot >= slots) return;
+  uint32_t* epochs = t.jobs[0].big_epoch;
+  uint32_t epoch = epochs[slot];
+  for (int i = 0; i < t.njobs; ++i) {
+    const SampleArgs& a = t.jobs[(i + slot) % t.njobs];
+    lt_big_run<MODE>(a, tier_io<1>(a, 2), slot, epoch);
+  }
+  epochs[slot] = epoch;
+}
+
+// kappa sums of the jobs (blockIdx.y = job); emit launches only for jobs
+// that asked for them (wbuf set).
+__global__ __launch_bounds__(kSegThreads) void kappa_reduce_batch_kernel(JobTable t, int emit) {
+  const SampleArgs& a = t.jobs[blockIdx.y];
+  if (emit && !a.wbuf) return;
+  Acc acc;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count; i += stride) {
+    const uint32_t w = a.wbuf[i];
+    acc.kappa += kappa_fixed(w, a.g.m, a.k);
+    if (a.widths) a.widths[i] = w;
+  }
+  wave_flush(a, acc, 0, threadIdx.x % kWave);
+}
+
+__global__ void clear_counters_batch_kernel(JobTable t) {
+  unsigned long long* ctr = t.jobs[blockIdx.x].ctr;
   for (int i = threadIdx.x; i < kCtrCount; i += blockDim.x) ctr[i] = 0ull;
 }
 
@@ -1064,6 +1219,35 @@ void launch_lt(const SampleArgs& a, int grid0, hipStream_t s, hipEvent_t after0)
   if (MODE == kModeWidth || (MODE == kModeEmit && a.wbuf)) launch_kappa_reduce(a, s);
 }
 
+// Batched launches: 8 lanes per set in tier 0, as SegKernel<., ., 8>.
+template <int MODE, bool WC>
+struct BatchKernels {
+  static constexpr auto seg0 = ic_seg_batch_kernel<MODE, WC, 8, 128, 0, 512, kSegGroups>;
+  static constexpr auto seg1 = ic_seg_batch_kernel<MODE, WC, 64, 512, 10, 64 * 64, kSegGroups>;
+};
+
+template <int MODE, bool WC>
+void launch_ic_batch(const JobTable& t, int grid0, int grid1, int slots, unsigned kappa_blocks, hipStream_t s,
+                     hipEvent_t after0) {
+  const dim3 blk(kSegThreads);
+  hipLaunchKernelGGL((BatchKernels<MODE, WC>::seg0), dim3(grid0), blk, 0, s, t, 0);
+  if (after0) (void)hipEventRecord(after0, s);
+  hipLaunchKernelGGL((BatchKernels<MODE, WC>::seg1), dim3(grid1), blk, 0, s, t, 1);
+  hipLaunchKernelGGL((ic_big_batch_kernel<MODE, WC>), dim3(slots), dim3(kBigThreads), 0, s, t);
+  if (MODE == kModeWidth || MODE == kModeEmit)
+    hipLaunchKernelGGL(kappa_reduce_batch_kernel, dim3(kappa_blocks, t.njobs), blk, 0, s, t, MODE == kModeEmit ? 1 : 0);
+}
+
+template <int MODE>
+void launch_lt_batch(const JobTable& t, int grid0, int slots, unsigned kappa_blocks, hipStream_t s, hipEvent_t after0) {
+  hipLaunchKernelGGL((lt_lane_batch_kernel<MODE>), dim3(grid0), dim3(kLtWaves * kWave), 0, s, t);
+  if (after0) (void)hipEventRecord(after0, s);
+  hipLaunchKernelGGL((lt_big_batch_kernel<MODE>), dim3((slots + kWave - 1) / kWave), dim3(kWave), 0, s, t, slots);
+  if (MODE == kModeWidth || MODE == kModeEmit)
+    hipLaunchKernelGGL(kappa_reduce_batch_kernel, dim3(kappa_blocks, t.njobs), dim3(kSegThreads), 0, s, t,
+                       MODE == kModeEmit ? 1 : 0);
+}
+
 template <int MODE, bool WC>
 int ic_occupancy(int S) {
   switch (S) {
@@ -1125,6 +1309,56 @@ uint32_t tier0_set_cap(int model, int seg_lanes) {
     case 16: return 128;
     case 32: return 256;
     default: return 512;
+  }
+}
+
+int batch_blocks_per_cu(int model, int mode, bool wc, int tier) {
+  if (model == 1) {
+    switch (mode) {
+      case 0: return blocks_per_cu(lt_lane_batch_kernel<kModeWidth>, kLtWaves * kWave);
+      case 1: return blocks_per_cu(lt_lane_batch_kernel<kModeEmit>, kLtWaves * kWave);
+      default: return blocks_per_cu(lt_lane_batch_kernel<kModeCover>, kLtWaves * kWave);
+    }
+  }
+  switch (mode * 2 + (wc ? 1 : 0) + (tier ? 6 : 0)) {
+    case 0: return blocks_per_cu((BatchKernels<kModeWidth, false>::seg0), kSegThreads);
+    case 1: return blocks_per_cu((BatchKernels<kModeWidth, true>::seg0), kSegThreads);
+    case 2: return blocks_per_cu((BatchKernels<kModeEmit, false>::seg0), kSegThreads);
+    case 3: return blocks_per_cu((BatchKernels<kModeEmit, true>::seg0), kSegThreads);
+    case 4: return blocks_per_cu((BatchKernels<kModeCover, false>::seg0), kSegThreads);
+    case 5: return blocks_per_cu((BatchKernels<kModeCover, true>::seg0), kSegThreads);
+    case 6: return blocks_per_cu((BatchKernels<kModeWidth, false>::seg1), kSegThreads);
+    case 7: return blocks_per_cu((BatchKernels<kModeWidth, true>::seg1), kSegThreads);
+    case 8: return blocks_per_cu((BatchKernels<kModeEmit, false>::seg1), kSegThreads);
+    case 9: return blocks_per_cu((BatchKernels<kModeEmit, true>::seg1), kSegThreads);
+    case 10: return blocks_per_cu((BatchKernels<kModeCover, false>::seg1), kSegThreads);
+    default: return blocks_per_cu((BatchKernels<kModeCover, true>::seg1), kSegThreads);
+  }
+}
+
+void launch_clear_counters_batch(const JobTable& t, hipStream_t s) {
+  hipLaunchKernelGGL(clear_counters_batch_kernel, dim3(t.njobs), dim3(64), 0, s, t);
+}
+
+void launch_sample_batch(int model, int mode, bool wc, const JobTable& t, int grid0, int grid1, int slots,
+                         uint64_t max_count, hipStream_t s, hipEvent_t after_tier0) {
+  uint64_t kb = (max_count + kSegThreads - 1) / kSegThreads;
+  const unsigned kappa_blocks = (unsigned)(kb < 1 ? 1 : (kb > 4096 ? 4096 : kb));
+  if (model == 0) {
+    switch (mode * 2 + (wc ? 1 : 0)) {
+      case 0: launch_ic_batch<kModeWidth, false>(t, grid0, grid1, slots, kappa_blocks, s, after_tier0); break;
+      case 1: launch_ic_batch<kModeWidth, true>(t, grid0, grid1, slots, kappa_blocks, s, after_tier0); break;
+      case 2: launch_ic_batch<kModeEmit, false>(t, grid0, grid1, slots, kappa_blocks, s, after_tier0); break;
+      case 3: launch_ic_batch<kModeEmit, true>(t, grid0, grid1, slots, kappa_blocks, s, after_tier0); break;
+      case 4: launch_ic_batch<kModeCover, false>(t, grid0, grid1, slots, kappa_blocks, s, after_tier0); break;
+      default: launch_ic_batch<kModeCover, true>(t, grid0, grid1, slots, kappa_blocks, s, after_tier0); break;
+    }
+  } else {
+    switch (mode) {
+      case 0: launch_lt_batch<kModeWidth>(t, grid0, slots, kappa_blocks, s, after_tier0); break;
+      case 1: launch_lt_batch<kModeEmit>(t, grid0, slots, kappa_blocks, s, after_tier0); break;
+      default: launch_lt_batch<kModeCover>(t, grid0, slots, kappa_blocks, s, after_tier0); break;
+    }
   }
 }
 

@@ -110,6 +110,62 @@ def random_small_graph(n: int, m: int, seed: int) -> Graph:
     return from_edges(n, [pairs[i] for i in pick], name=f"small_n{n}_m{m}_s{seed}")
 
 
+# Trivalency edge probabilities: IC where each edge's p is one of three values.
+TRIVALENCY_P = (0.1, 0.01, 0.001)
+
+
+def threshold_of(p: float) -> int:
+    """uint32 threshold t = floor(p * 2^32) - 1 of an edge probability p in (0, 1] (exact in p's binary value)."""
+    from fractions import Fraction
+    t = int(Fraction(p) * 2**32) - 1
+    if not 0 <= t <= 0xFFFFFFFF:
+        raise ValueError(f"p={p} has no uint32 threshold")
+    return t
+
+
+def batch_queries(count: int = 64, base_seed: int = 1000, n_range=(10_000, 2_000_000), deg_range=(4.0, 40.0),
+                  k_max: int = 50, eps_choices=(0.1, 0.2, 0.5)) -> list:
+    """Parameters of a batch of independent TIM+ queries, each on a graph of its own.
+
+    Query j draws from numpy's default_rng(base_seed + j), in this order: n log-uniform in n_range
+    (rounded), the average degree uniform in deg_range (m = round(n * degree)), k uniform in
+    [1, k_max], eps from eps_choices.  Even j use IC with per-edge probabilities drawn uniformly from
+    TRIVALENCY_P (thresholds seeded with base_seed + j), odd j LT with in-weights 1/indeg.  The graph is
+    the directed Chung-Lu graph (alpha 2.1) seeded with base_seed + j; ell = 1; the algorithm seed is
+    base_seed + j.
+    """
+    import math
+    out = []
+    for j in range(count):
+        r = np.random.default_rng(base_seed + j)
+        n = int(round(math.exp(r.uniform(math.log(n_range[0]), math.log(n_range[1])))))
+        deg = float(r.uniform(deg_range[0], deg_range[1]))
+        m = int(round(n * deg))
+        k = int(r.integers(1, k_max + 1))
+        eps = float(r.choice(np.asarray(eps_choices, dtype=np.float64)))
+        model = 0 if j % 2 == 0 else 1
+        out.append(dict(name=f"q{j}", n=n, m=m, alpha=2.1, graph_seed=base_seed + j, model=model, k=k, eps=eps,
+                        ell=1.0, seed=base_seed + j, thr_seed=(base_seed + j) if model == 0 else None))
+    return out
+
+
+def batch_graph(q: dict):
+    """(Graph, thresholds or None) of one query of batch_queries()."""
+    g = chung_lu(q["n"], q["m"], q["alpha"], q["graph_seed"], name=q["name"])
+    thr = None
+    if q["thr_seed"] is not None:
+        thr = random_thresholds(g.m, q["thr_seed"], choices=[threshold_of(p) for p in TRIVALENCY_P])
+    return g, thr
+
+
+def batch_graphs(queries, workers: int = 8) -> list:
+    """batch_graph() of every query, generated by `workers` threads (the generator releases the GIL)."""
+    from concurrent.futures import ThreadPoolExecutor
+    _load()
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return list(ex.map(batch_graph, queries))
+
+
 # Configurations of the synthetic workloads (graph part only).
 CONFIGS = {
     "cfg1": dict(n=15_000, m=60_000, alpha=2.1, seed=1),

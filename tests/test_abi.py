@@ -40,9 +40,10 @@ def test_struct_layouts_match_header():
 #include <stddef.h>
 #include "tim.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(tim_report), sizeof(tim_kpt_result), sizeof(tim_batch_stats),
-         sizeof(tim_refine_result), sizeof(tim_select_result), offsetof(tim_report, s_prime),
-         offsetof(tim_report, ms_kpt), offsetof(tim_report, sets_total));
+  printf("%zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu %zu\n", sizeof(tim_report), sizeof(tim_kpt_result),
+         sizeof(tim_batch_stats), sizeof(tim_refine_result), sizeof(tim_select_result), offsetof(tim_report, s_prime),
+         offsetof(tim_report, ms_kpt), offsetof(tim_report, sets_total), sizeof(tim_query),
+         offsetof(tim_query, status), sizeof(tim_batch_info), offsetof(tim_batch_info, ms_wall));
   return 0;
 }
 '''
@@ -54,7 +55,8 @@ int main(void) {
         got = [int(x) for x in subprocess.check_output([exe]).split()]
     want = [ctypes.sizeof(tim.Report), ctypes.sizeof(tim.KptResult), ctypes.sizeof(tim.BatchStats),
             ctypes.sizeof(tim.RefineResult), ctypes.sizeof(tim.SelectResult), tim.Report.s_prime.offset,
-            tim.Report.ms_kpt.offset, tim.Report.sets_total.offset]
+            tim.Report.ms_kpt.offset, tim.Report.sets_total.offset, ctypes.sizeof(tim.Query), tim.Query.status.offset,
+            ctypes.sizeof(tim.BatchInfo), tim.BatchInfo.ms_wall.offset]
     assert got == want
 
 
