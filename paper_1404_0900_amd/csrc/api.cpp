@@ -94,6 +94,7 @@ struct tim_ctx {
   int grid_ic[3][2] = {};
   int grid_ic64[3][2] = {};
   int grid_lt[3] = {};
+  int grid_lt_chain[3] = {};
   unsigned long long* ctr = nullptr;       // device counters of the current launch
   unsigned long long* ctr_host = nullptr;  // pinned mirror
   DevBuf list1, list2, wbuf, pool, set_start, set_len;
@@ -254,6 +255,7 @@ struct Hub {
   uint64_t big_bytes = 0;
   int grid0[2][3][2] = {};  // tier-0 blocks per CU [model][mode][wc]
   int grid1[3][2] = {};     // IC tier-1 blocks per CU
+  int grid_chain[3] = {};   // LT long-chain tier blocks per CU
   uint64_t emit_waves[2] = {0, 0};
   // per-launch timing into the owning context's profile (when it is on)
   tim_ctx* owner = nullptr;
@@ -330,7 +332,7 @@ uint64_t pool_need(const tim_ctx* c, int model, uint64_t count, uint64_t nodes, 
 tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, uint64_t seed, uint32_t phase,
                          uint64_t first, uint64_t count, int k, uint64_t* widths, uint32_t* sizes,
                          uint64_t set_offset, uint64_t pool_base, Totals* t) {
-  TIM_TRY(ensure_big(c, g->n));
+  if (model == TIM_MODEL_IC) TIM_TRY(ensure_big(c, g->n));  // the LT long-chain tier needs no slots
   TIM_TRY(ensure(c, c->list1, count * 8, "deferred-set list"));
   if (model == TIM_MODEL_IC) TIM_TRY(ensure(c, c->list2, count * 8, "deferred-set list"));
   SampleArgs a;
@@ -387,7 +389,9 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
     h = req.h;
   } else {
     const uint64_t grid0 = sample_grid(c, model, mode, wc, count, nullptr);
-    const uint64_t grid1 = (uint64_t)c->grid_ic64[mode][wc ? 1 : 0] * (uint64_t)c->num_cu;
+    const uint64_t grid1 =
+        (uint64_t)(model == TIM_MODEL_IC ? c->grid_ic64[mode][wc ? 1 : 0] : c->grid_lt_chain[mode]) *
+        (uint64_t)c->num_cu;
     tim::launch_clear_counters(c->ctr, c->stream);
     if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
     tim::launch_sample(model, mode, a, c->seg_lanes, (int)grid0, (int)grid1, c->stream,
@@ -1142,7 +1146,9 @@ tim_status hub_round(Hub* h, std::vector<Pending*>& subs) {
     const uint64_t per_block = p->model == TIM_MODEL_IC ? 32 : 128;  // sets a tier-0 block holds at once
     const uint64_t full = (uint64_t)h->grid0[p->model][p->mode][p->wc ? 1 : 0] * (uint64_t)h->num_cu;
     const uint64_t grid0 = std::max<uint64_t>(1, std::min(full, (total + per_block - 1) / per_block));
-    const uint64_t grid1 = (uint64_t)h->grid1[p->mode][p->wc ? 1 : 0] * (uint64_t)h->num_cu;
+    const uint64_t grid1 =
+        (uint64_t)(p->model == TIM_MODEL_IC ? h->grid1[p->mode][p->wc ? 1 : 0] : h->grid_chain[p->mode]) *
+        (uint64_t)h->num_cu;
     const bool prof = h->owner && h->owner->prof_on;
     if (prof) HIP_TRY(hipEventRecord(h->pev[0], h->stream));
     tim::launch_sample_batch(p->model, p->mode, p->wc, tim::JobTable{h->d_jobs + lo, (int)(hi - lo)}, (int)grid0,
@@ -1265,6 +1271,7 @@ tim_status hub_setup(Hub* h, tim_ctx* parent) {
       for (int wc = 0; wc < 2; ++wc) h->grid0[model][mode][wc] = tim::batch_blocks_per_cu(model, mode, wc != 0, 0);
   for (int mode = 0; mode < 3; ++mode)
     for (int wc = 0; wc < 2; ++wc) h->grid1[mode][wc] = tim::batch_blocks_per_cu(0, mode, wc != 0, 1);
+  for (int mode = 0; mode < 3; ++mode) h->grid_chain[mode] = tim::lt_chain_blocks_per_cu(mode, true);
   h->emit_waves[0] = (uint64_t)std::max(h->grid0[0][1][0], h->grid0[0][1][1]) * (uint64_t)h->num_cu * 4;
   h->emit_waves[1] = (uint64_t)h->grid0[1][1][0] * (uint64_t)h->num_cu * 2;
   return TIM_OK;
@@ -1399,6 +1406,7 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
       c->grid_ic64[mode][wc] = tim::ic_tier1_blocks_per_cu(mode, wc != 0);
     }
     c->grid_lt[mode] = tim::lt_lane_blocks_per_cu(mode);
+    c->grid_lt_chain[mode] = tim::lt_chain_blocks_per_cu(mode, false);
   }
   if (hipMalloc(&c->ctr, tim::kCtrCount * sizeof(unsigned long long)) != hipSuccess ||
       hipHostMalloc(&c->ctr_host, tim::kCtrCount * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||

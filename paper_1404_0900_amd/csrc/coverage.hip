@@ -244,25 +244,38 @@ struct TileShared {
   uint32_t key[kAgg], cnt[kAgg];
 };
 
+// Tiles without entries (a greedy step's cover pass mostly meets tiles whose
+// sets are all covered already) skip the LDS table altogether.  Smaller
+// tiles still aggregate: the nodes they share are hubs, whose direct atomics
+// would contend across the chip.
+constexpr int64_t kAggMin = 1;
+
 // Adds (sign +1) or subtracts the memberships of the tile's listed sets (prefix
 // from tile_prefix) to cnt, skipping node `skip`.
 template <bool kAdd>
 __device__ __forceinline__ void tile_apply(const int32_t* nodes, TileShared& t, int64_t skip, uint32_t* cnt) {
   const int64_t tot = t.pre[kTileSets];
+  const bool agg = tot >= kAggMin;
+  if (agg) {
+    agg_clear(t.key, t.cnt);
+    __syncthreads();
+  }
   for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
     const int j = tile_set_of(t.pre, kTileSets, e);
     const int32_t u = nodes[t.start[j] + (e - t.pre[j])];
     if (u == skip) continue;
-    const int slot = agg_slot(t.key, (uint32_t)u, true);
+    const int slot = agg ? agg_slot(t.key, (uint32_t)u, true) : -1;
     if (slot >= 0) atomicAdd(&t.cnt[slot], 1u);
     else if (kAdd) atomicAdd(&cnt[u], 1u);
     else atomicSub(&cnt[u], 1u);
   }
-  __syncthreads();
-  for (int i = threadIdx.x; i < kAgg; i += kThreads) {
-    if (t.key[i]) {
-      if (kAdd) atomicAdd(&cnt[t.key[i] - 1u], t.cnt[i]);
-      else atomicSub(&cnt[t.key[i] - 1u], t.cnt[i]);
+  if (agg) {
+    __syncthreads();
+    for (int i = threadIdx.x; i < kAgg; i += kThreads) {
+      if (t.key[i]) {
+        if (kAdd) atomicAdd(&cnt[t.key[i] - 1u], t.cnt[i]);
+        else atomicSub(&cnt[t.key[i] - 1u], t.cnt[i]);
+      }
     }
   }
   __syncthreads();
@@ -294,7 +307,6 @@ __global__ __launch_bounds__(kThreads) void hist_sets_kernel(V sets, uint64_t ns
   __shared__ TileShared t;
   for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
     const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
-    agg_clear(t.key, t.cnt);
     uint32_t len = 0;
     int64_t start = 0;
     if (threadIdx.x < ns) {
@@ -408,7 +420,6 @@ __global__ __launch_bounds__(kThreads) void cover_kernel(const unsigned long lon
   const int64_t lo = inv_off[v], hi = inv_off[v + 1];
   for (int64_t i0 = lo + (int64_t)blockIdx.x * kTileSets; i0 < hi; i0 += (int64_t)gridDim.x * kTileSets) {
     const int ni = (int)min((int64_t)kTileSets, hi - i0);
-    agg_clear(t.key, t.cnt);
     // newly covered sets of this tile and their sizes
     uint32_t len = 0;
     int64_t start = 0;
@@ -439,7 +450,6 @@ __global__ __launch_bounds__(kThreads) void scan_cover_kernel(const unsigned lon
   const int64_t v = node_of_key(*best);
   for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
     const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
-    agg_clear(t.key, t.cnt);
     uint32_t len = 0;
     int64_t start = 0;
     if (threadIdx.x < ns && !covered[s0 + threadIdx.x]) {

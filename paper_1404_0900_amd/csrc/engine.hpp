@@ -93,12 +93,14 @@ int ic_seg_lanes();
 int ic_blocks_per_cu(int mode, bool wc, int seg_lanes);
 int ic_tier1_blocks_per_cu(int mode, bool wc);
 int lt_lane_blocks_per_cu(int mode);
+// Occupancy of the LT long-chain tier (single or batched launches).
+int lt_chain_blocks_per_cu(int mode, bool batch);
 // Largest set the first tier keeps in LDS (IC: its queue for seg_lanes lanes
 // per set; LT: its chain); larger sets go on to the next tier.
 uint32_t tier0_set_cap(int model, int seg_lanes);
 // Tier 0 (grid0 blocks; IC with seg_lanes lanes per set), then the deferral
-// tiers (IC tier 1 with grid1 blocks).  after_tier0, if given, is recorded
-// between tier 0 and the rest.
+// tiers (grid1 blocks: IC tier 1, or the LT long-chain tier).  after_tier0,
+// if given, is recorded between tier 0 and the rest.
 void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int grid0, int grid1, hipStream_t s,
                    hipEvent_t after_tier0);
 
@@ -113,7 +115,8 @@ constexpr int kMaxBatchJobs = 64;
 // Occupancy of the batched tier-0 (tier 0) or tier-1 (tier 1, IC) kernel.
 int batch_blocks_per_cu(int model, int mode, bool wc, int tier);
 void launch_clear_counters_batch(const JobTable& t, hipStream_t s);
-// All tiers and the kappa sums; max_count is the largest job's count.
+// All tiers and the kappa sums; max_count is the largest job's count.  grid1
+// is the IC tier-1 or LT long-chain grid, slots the IC last-tier slots.
 // after_tier0, if given, is recorded between tier 0 and the rest.
 void launch_sample_batch(int model, int mode, bool wc, const JobTable& t, int grid0, int grid1, int slots,
                          uint64_t max_count, hipStream_t s, hipEvent_t after_tier0);

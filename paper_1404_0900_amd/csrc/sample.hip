@@ -321,8 +321,11 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
 // lanes scan Q/S entries), which leaves the LDS to more sets in flight.
 // Width mode writes w(R) per set; kappa is summed by kappa_reduce_kernel.
 // ------------------------------------------------------------------------
+// first_only: a launch of its own over one deferred list, whose wavefronts
+// beyond the first ones the list needs leave at once instead of each taking
+// a turn at the list's cursor.
 template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
-__device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io) {
+__device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io, bool first_only) {
   constexpr bool kHash = HLOG > 0;
   constexpr int H = kHash ? (1 << HLOG) : 4;
   constexpr int NSEG = kSegThreads / S;
@@ -344,6 +347,10 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   const uint32_t* off32 = nullptr;  // unused: offsets are read as int64 and narrowed
   (void)off32;
   const unsigned long long total = io.in_list ? list_len(a, io.in_len_ctr) : a.count;
+  if (first_only && io.in_list) {
+    const unsigned long long wave = (unsigned long long)blockIdx.x * (kSegThreads / kWave) + threadIdx.x / kWave;
+    if (wave * (unsigned long long)(kWave / S) >= total) return;
+  }
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
@@ -625,7 +632,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
 
 template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
 __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
-  ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, io);
+  ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, io, true);
 }
 
 // Exact sum of kappa(R) * 2^53 over the widths a width-mode launch wrote
@@ -934,75 +941,181 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
   ic_big_run<MODE, WC>(a, io, blockIdx.x);
 }
 
-// LT: one lane per set, visited stamps and chain in device memory.  `epoch`
-// is the slot's stamp epoch, carried from set to set.
+// LT, chains longer than the first tier's LDS chain: one lane per chain and
+// no visited marks at all.  The walk's pick at a node is a fixed function of
+// (set, node), so the walk is x_{i+1} = f(x_i): it ends at a node without
+// in-edges, or it enters a cycle and the first repeated node closes the set.
+// Brent's cycle detection (R. P. Brent, "An improved Monte Carlo
+// factorization algorithm", BIT 20, 1980) finds the cycle length lambda and
+// the tail length mu in O(1) memory; the set is x_0 .. x_{mu+lambda-1}, walked
+// once more for its widths (and, when stored, its nodes).  Coverage needs no
+// second walk: the hare of the search passes every node of the set.
+//
+// Every lane runs a small state machine that takes one step of f per
+// iteration, so lanes of one wavefront run chains of any lengths side by
+// side and take a new chain as soon as theirs is done.
+enum ChainPhase : int {
+  kSearch = 0,   // Brent's search: hare at position pos
+  kAdvance = 1,  // hare moves lambda steps from x_0
+  kTortoise = 2, // tortoise and hare step together until they meet (mu)
+  kHare = 3,
+  kWalk = 4,     // output walk over the mu + lambda nodes
+  kIdle = 5
+};
+
+// f(v) and indeg(v): the in-neighbour the walk moves to from v, or -1 at a
+// node without in-edges.
+__device__ __forceinline__ int32_t lt_next(const GraphView& g, const Key& key, const SetStream& st, int32_t v,
+                                           int64_t& d) {
+  const int64_t ea = g.off[v];
+  d = g.off[v + 1] - ea;
+  if (d == 0) return -1;
+  const uint64_t j = scale64(draw(key, st, kKindPick, (uint64_t)v), (uint64_t)d);
+  return g.src[ea + (int64_t)j];
+}
+
+constexpr int kChainWaves = 4;  // wavefronts per block of the long-chain tier
+
 template <int MODE>
-__device__ __forceinline__ void lt_big_run(const SampleArgs& a, const TierIO& io, int slot, uint32_t& epoch) {
+__device__ __forceinline__ void lt_chain_run(const SampleArgs& a, const TierIO& io, bool first_only) {
+  const int lane = threadIdx.x % kWave;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const GraphView g = a.g;
   const Key key = make_key(a.seed);
-  uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)a.big_stride;
-  int32_t* chain = a.big_queue + (size_t)slot * (size_t)a.big_stride;
-  const unsigned long long ndef = list_len(a, io.in_len_ctr);
+  const unsigned long long total = list_len(a, io.in_len_ctr);
+  if (first_only) {  // a chain per lane to start with: later wavefronts are not needed
+    const unsigned long long wave = (unsigned long long)blockIdx.x * kChainWaves + threadIdx.x / kWave;
+    if (wave * (unsigned long long)kWave >= total) return;
+  }
   Acc acc;
+  Reservoir res;
+  res.chunk = chunk_for(total, kChainWaves, kWave);
+  bool exhausted = false;
+  int phase = kIdle;
+  unsigned long long rel = 0, width = 0, base = 0;
+  SetStream st = make_set_stream(a.phase, a.first);
+  int32_t x0 = 0, cur = 0, tort = 0, hare = 0;
+  uint32_t pos = 0, power = 1, lam = 0, mu = 0, cnt = 0, len = 0;
   for (;;) {
-    const unsigned long long idx = atomicAdd(&a.ctr[io.next_ctr], 1ull);
-    if (idx >= ndef) break;
-    if (++epoch == 0u) {
-      for (uint64_t i = 0; i < a.big_stride; ++i) stamp[i] = 0u;
-      epoch = 1u;
+    {
+      unsigned long long item = 0;
+      if (take(a, io.next_ctr, total, res, phase == kIdle && !exhausted, true, below, lane, exhausted, item)) {
+        rel = io.in_list[item];
+        st = make_set_stream(a.phase, a.first + rel);
+        x0 = draw_root(key, st, g.n);
+        cur = x0;
+        pos = 0;
+        width = 0;
+        phase = kSearch;
+        if (MODE == kModeCover && in_seed(a.seed_bits, x0)) {
+          acc.covered += 1;
+          phase = kIdle;
+        }
+      }
     }
-    const unsigned long long rel = io.in_list[idx];
-    const SetStream st = make_set_stream(a.phase, a.first + rel);
-    int32_t v = draw_root(key, st, g.n);
-    stamp[v] = epoch;
-    chain[0] = v;
-    int64_t len = 1;
-    unsigned long long width = 0;
-    bool hit = (MODE == kModeCover) && in_seed(a.seed_bits, v);
-    while (!hit) {
-      const int64_t ea = g.off[v];
-      const int64_t d = g.off[v + 1] - ea;
+    if (__ballot(phase != kIdle) == 0) break;
+    if (phase == kIdle) continue;
+    const int ph = phase;  // this iteration's step is f(cur) of phase ph
+    int64_t d = 0;
+    const int32_t nx = lt_next(g, key, st, cur, d);
+    bool done = false, walk = false;
+    if (ph == kSearch) {
+      // cur is the hare, at position pos
+      if (nx < 0) {  // x_pos has no in-edges: the set is x_0 .. x_pos
+        len = pos + 1;
+        if (MODE == kModeCover) done = true;
+        else walk = true;
+      } else {
+        if (pos == 0) {
+          tort = x0;
+          power = 1;
+          lam = 1;
+        } else {
+          if (power == lam) {
+            tort = cur;
+            power <<= 1;
+            lam = 0;
+          }
+          ++lam;
+        }
+        ++pos;
+        cur = nx;
+        if (MODE == kModeCover && in_seed(a.seed_bits, nx)) {
+          acc.covered += 1;
+          done = true;
+        } else if (nx == tort) {  // a cycle of length lam; the hare has passed every node of the set
+          if (MODE == kModeCover) {
+            done = true;
+          } else {
+            phase = kAdvance;
+            cnt = 0;
+            cur = x0;
+          }
+        }
+      }
+    } else if (ph == kAdvance) {  // hare = x_cnt
+      cur = nx;
+      if (++cnt == lam) {
+        hare = nx;
+        tort = x0;
+        mu = 0;
+        if (tort == hare) {
+          len = lam;
+          walk = true;
+        } else {
+          phase = kTortoise;
+          cur = tort;
+        }
+      }
+    } else if (ph == kTortoise) {
+      tort = nx;
+      phase = kHare;
+      cur = hare;
+    } else if (ph == kHare) {
+      hare = nx;
+      ++mu;
+      if (tort == hare) {
+        len = mu + lam;
+        walk = true;
+      } else {
+        phase = kTortoise;
+        cur = tort;
+      }
+    } else {  // kWalk: cur = x_pos, with indeg d and successor nx
       width += (unsigned long long)d;
-      if (d == 0) break;
-      const uint64_t j = scale64(draw(key, st, kKindPick, (uint64_t)v), (uint64_t)d);
-      const int32_t u = g.src[ea + (int64_t)j];
-      if (stamp[u] == epoch) break;
-      stamp[u] = epoch;
-      chain[len++] = u;
-      v = u;
-      if (MODE == kModeCover && in_seed(a.seed_bits, u)) hit = true;
+      if (MODE == kModeEmit && base + len <= a.pool_cap) a.pool[base + pos] = cur;
+      if (++pos == len) done = true;
+      else cur = nx;
     }
-    if (MODE == kModeWidth) {
-      a.wbuf[rel] = (uint32_t)width;
-      acc.width += width;
-      acc.nodes += (unsigned long long)len;
-      if (a.sizes) a.sizes[rel] = (uint32_t)len;
-    } else if (MODE == kModeEmit) {
-      const unsigned long long b = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)len);
-      if (b + (unsigned long long)len <= a.pool_cap)
-        for (int64_t i = 0; i < len; ++i) a.pool[b + i] = chain[i];
-      a.set_start[rel] = a.pool_base + b;
-      a.set_len[rel] = (uint32_t)len;
-      if (a.widths) a.widths[rel] = width;
-      if (a.wbuf) a.wbuf[rel] = (uint32_t)width;
-      acc.width += width;
-      acc.nodes += (unsigned long long)len;
-    } else {
-      acc.width += width;
-      acc.nodes += (unsigned long long)len;
-      if (hit) acc.covered += 1;
+    if (walk) {
+      phase = kWalk;
+      cur = x0;
+      pos = 0;
+      if (MODE == kModeEmit) base = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)len);
+    }
+    if (done) {
+      phase = kIdle;
+      if (MODE == kModeWidth) {
+        a.wbuf[rel] = (uint32_t)width;
+        acc.width += width;
+        acc.nodes += len;
+        if (a.sizes) a.sizes[rel] = len;
+      } else if (MODE == kModeEmit) {
+        a.set_start[rel] = a.pool_base + base;
+        a.set_len[rel] = len;
+        if (a.widths) a.widths[rel] = width;
+        if (a.wbuf) a.wbuf[rel] = (uint32_t)width;
+        acc.width += width;
+        acc.nodes += len;
+      }
     }
   }
-  block_flush(a, acc, io.acc);
+  wave_flush(a, acc, io.acc, lane);
 }
 
 template <int MODE>
-__global__ __launch_bounds__(kWave) void lt_big_kernel(SampleArgs a, TierIO io) {
-  const int slot = blockIdx.x * kWave + threadIdx.x;
-  if (slot >= a.big_slots) return;
-  uint32_t epoch = a.big_epoch[slot];
-  lt_big_run<MODE>(a, io, slot, epoch);
-  a.big_epoch[slot] = epoch;
+__global__ __launch_bounds__(kChainWaves* kWave) void lt_chain_kernel(SampleArgs a, TierIO io) {
+  lt_chain_run<MODE>(a, io, true);
 }
 
 __global__ void clear_counters_kernel(unsigned long long* ctr) {
@@ -1071,7 +1184,7 @@ __global__ __launch_bounds__(kSegThreads) void ic_seg_batch_kernel(JobTable t, i
     const int j = __builtin_amdgcn_readfirstlane(next_job(jobs_with_work<0>(t, tier, lane), from));
     if (j < 0) break;
     const SampleArgs& a = t.jobs[j];
-    ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, tier_io<0>(a, tier));
+    ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, tier_io<0>(a, tier), false);
     from = j + 1;
   }
 }
@@ -1109,19 +1222,18 @@ __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_batch_kernel(JobTable
   }
 }
 
-// One lane per slot; every lane visits every job once (its deferred chains
-// are few), starting at a different one.
 template <int MODE>
-__global__ __launch_bounds__(kWave) void lt_big_batch_kernel(JobTable t, int slots) {
-  const int slot = blockIdx.x * kWave + threadIdx.x;
-  if (slot >= slots) return;
-  uint32_t* epochs = t.jobs[0].big_epoch;
-  uint32_t epoch = epochs[slot];
-  for (int i = 0; i < t.njobs; ++i) {
-    const SampleArgs& a = t.jobs[(i + slot) % t.njobs];
-    lt_big_run<MODE>(a, tier_io<1>(a, 2), slot, epoch);
+__global__ __launch_bounds__(kChainWaves* kWave) void lt_chain_batch_kernel(JobTable t) {
+  const int lane = threadIdx.x % kWave;
+  const int wave = blockIdx.x * kChainWaves + threadIdx.x / kWave;
+  int from = wave % t.njobs;
+  for (;;) {
+    const int j = __builtin_amdgcn_readfirstlane(next_job(jobs_with_work<1>(t, 2, lane), from));
+    if (j < 0) break;
+    const SampleArgs& a = t.jobs[j];
+    lt_chain_run<MODE>(a, tier_io<1>(a, 2), false);
+    from = j + 1;
   }
-  epochs[slot] = epoch;
 }
 
 // kappa sums of the jobs (blockIdx.y = job); emit launches only for jobs
@@ -1210,12 +1322,12 @@ void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, 
 }
 
 template <int MODE>
-void launch_lt(const SampleArgs& a, int grid0, hipStream_t s, hipEvent_t after0) {
+void launch_lt(const SampleArgs& a, int grid0, int grid2, hipStream_t s, hipEvent_t after0) {
   const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
   const TierIO t2 = {a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2};
   hipLaunchKernelGGL((lt_lane_kernel<MODE>), dim3(grid0), dim3(kLtWaves * kWave), 0, s, a, t0);
   if (after0) (void)hipEventRecord(after0, s);
-  hipLaunchKernelGGL((lt_big_kernel<MODE>), dim3((a.big_slots + kWave - 1) / kWave), dim3(kWave), 0, s, a, t2);
+  hipLaunchKernelGGL((lt_chain_kernel<MODE>), dim3(grid2), dim3(kChainWaves * kWave), 0, s, a, t2);
   if (MODE == kModeWidth || (MODE == kModeEmit && a.wbuf)) launch_kappa_reduce(a, s);
 }
 
@@ -1239,10 +1351,10 @@ void launch_ic_batch(const JobTable& t, int grid0, int grid1, int slots, unsigne
 }
 
 template <int MODE>
-void launch_lt_batch(const JobTable& t, int grid0, int slots, unsigned kappa_blocks, hipStream_t s, hipEvent_t after0) {
+void launch_lt_batch(const JobTable& t, int grid0, int grid2, unsigned kappa_blocks, hipStream_t s, hipEvent_t after0) {
   hipLaunchKernelGGL((lt_lane_batch_kernel<MODE>), dim3(grid0), dim3(kLtWaves * kWave), 0, s, t);
   if (after0) (void)hipEventRecord(after0, s);
-  hipLaunchKernelGGL((lt_big_batch_kernel<MODE>), dim3((slots + kWave - 1) / kWave), dim3(kWave), 0, s, t, slots);
+  hipLaunchKernelGGL((lt_chain_batch_kernel<MODE>), dim3(grid2), dim3(kChainWaves * kWave), 0, s, t);
   if (MODE == kModeWidth || MODE == kModeEmit)
     hipLaunchKernelGGL(kappa_reduce_batch_kernel, dim3(kappa_blocks, t.njobs), dim3(kSegThreads), 0, s, t,
                        MODE == kModeEmit ? 1 : 0);
@@ -1290,6 +1402,17 @@ int ic_blocks_per_cu(int mode, bool wc, int S) {
     case 3: return ic_occupancy<kModeEmit, true>(S);
     case 4: return ic_occupancy<kModeCover, false>(S);
     default: return ic_occupancy<kModeCover, true>(S);
+  }
+}
+
+int lt_chain_blocks_per_cu(int mode, bool batch) {
+  switch (mode + (batch ? 3 : 0)) {
+    case 0: return blocks_per_cu(lt_chain_kernel<kModeWidth>, kChainWaves * kWave);
+    case 1: return blocks_per_cu(lt_chain_kernel<kModeEmit>, kChainWaves * kWave);
+    case 2: return blocks_per_cu(lt_chain_kernel<kModeCover>, kChainWaves * kWave);
+    case 3: return blocks_per_cu(lt_chain_batch_kernel<kModeWidth>, kChainWaves * kWave);
+    case 4: return blocks_per_cu(lt_chain_batch_kernel<kModeEmit>, kChainWaves * kWave);
+    default: return blocks_per_cu(lt_chain_batch_kernel<kModeCover>, kChainWaves * kWave);
   }
 }
 
@@ -1355,9 +1478,9 @@ void launch_sample_batch(int model, int mode, bool wc, const JobTable& t, int gr
     }
   } else {
     switch (mode) {
-      case 0: launch_lt_batch<kModeWidth>(t, grid0, slots, kappa_blocks, s, after_tier0); break;
-      case 1: launch_lt_batch<kModeEmit>(t, grid0, slots, kappa_blocks, s, after_tier0); break;
-      default: launch_lt_batch<kModeCover>(t, grid0, slots, kappa_blocks, s, after_tier0); break;
+      case 0: launch_lt_batch<kModeWidth>(t, grid0, grid1, kappa_blocks, s, after_tier0); break;
+      case 1: launch_lt_batch<kModeEmit>(t, grid0, grid1, kappa_blocks, s, after_tier0); break;
+      default: launch_lt_batch<kModeCover>(t, grid0, grid1, kappa_blocks, s, after_tier0); break;
     }
   }
 }
@@ -1377,9 +1500,9 @@ void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int 
     }
   } else {
     switch (mode) {
-      case 0: launch_lt<kModeWidth>(a, grid0, s, after_tier0); break;
-      case 1: launch_lt<kModeEmit>(a, grid0, s, after_tier0); break;
-      default: launch_lt<kModeCover>(a, grid0, s, after_tier0); break;
+      case 0: launch_lt<kModeWidth>(a, grid0, grid1, s, after_tier0); break;
+      case 1: launch_lt<kModeEmit>(a, grid0, grid1, s, after_tier0); break;
+      default: launch_lt<kModeCover>(a, grid0, grid1, s, after_tier0); break;
     }
   }
 }

@@ -116,6 +116,42 @@ def test_rr_sets_cfg2_sampled(eng, cfg2, model):
     _check_sets(eng, cfg2, model, 2, 64, 123457, 20011)
 
 
+def _functional_graph(n, seed, ends):
+    """Each node has one in-edge from a random other node (a fraction `ends` has none): LT walks are
+    deterministic rho shapes (a tail into a cycle, about sqrt(n) long) or paths to a node without in-edges."""
+    rng = np.random.default_rng(seed)
+    u = rng.integers(0, n - 1, size=n)
+    v = np.arange(n)
+    u = u + (u >= v)
+    keep = rng.random(n) >= ends
+    return synth.from_edges(n, np.stack([u[keep], v[keep]], axis=1).tolist(), name=f"functional_n{n}_s{seed}")
+
+
+@pytest.mark.parametrize("which", ["functional", "dense"])
+def test_lt_long_chains_all_modes(eng, which):
+    """LT walks far longer than the first tier's 64-node chain (the long-chain tier finds where each walk
+    repeats with Brent's cycle search): stored sets, widths with exact kappa sums, and coverage."""
+    g = _functional_graph(300_000, 21, 0.0005) if which == "functional" else synth.chung_lu(300_000, 9_000_000, 2.1, 22)
+    dg = eng.upload(g)
+    count = 6000
+    st = _check_sets(eng, g, LT, 31, 64, 5, count, dg=dg)
+    so, nodes, ww = oracle.sample_sets(g, LT, 31, 64, 5, count)
+    sizes = np.diff(so)
+    _say(f"{which}: set sizes mean {sizes.mean():.1f} max {sizes.max()}, deferred {st.deferred}")
+    assert sizes.max() > 100 and st.deferred > 0
+    w, sz, wst = eng.sample_widths(dg, LT, 31, 64, 5, count, 9)
+    assert np.array_equal(w.cpu().numpy().astype(np.uint64), ww)
+    assert np.array_equal(sz.cpu().numpy(), sizes.astype(np.int32))
+    assert wst.kappa_sum == sum(oracle.kappa_fixed(int(x), g.m, 9) for x in ww)
+    seeds = np.unique(nodes[:: max(1, len(nodes) // 40)])[:30].astype(np.int32)
+    cst = eng.sample_cover(dg, LT, 31, 64, 5, count, seeds)
+    sid = np.repeat(np.arange(count), sizes)
+    hit = np.zeros(count, dtype=bool)
+    hit[sid[np.isin(nodes, seeds)]] = True
+    assert cst.covered == int(hit.sum())
+    eng.free(dg)
+
+
 # ------------------------------------------------------ widths / kappa --
 @pytest.mark.parametrize("model", [IC, LT])
 @pytest.mark.parametrize("k", [1, 50])
