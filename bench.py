@@ -21,6 +21,15 @@ uniform in [1, 50], eps from {0.1, 0.2, 0.5}, ell = 1), all graphs resident.
 A step runs the 64 queries one after the other (tim_run) and then as one
 batch (tim_run_batch); value is the batch's queries per second, beside the
 sequential rate, and the two must return identical results.
+
+--workload serve: a request loop (tim_server_*, 16 slots, 200 GB budget) over
+4 resident Chung-Lu graphs (n = 10^5, 10^6, 4*10^6, 10^7, average degree 16).
+Queries from a seeded stream (graph and model uniform, IC with p = 1/indeg or
+LT, k uniform in [1, 100], eps from {0.1, 0.2, 0.3}, ell = 1) arrive as a
+Poisson process at 1, 5, 20, 50 and 200 per second; each rate reports p50 and
+p99 latency (submission to result) and the queries per second completed.
+value is the rate sustained at 200 arrivals per second; the same queries run
+one by one (tim_run) give the plain rate, and must give the same results.
 """
 import argparse
 import json
@@ -80,7 +89,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--workload", choices=("timplus", "batch64"), default="timplus")
+    ap.add_argument("--workload", choices=("timplus", "batch64", "serve"), default="timplus")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -90,6 +99,8 @@ def main():
 
     if args.workload == "batch64":
         return batch_main(args)
+    if args.workload == "serve":
+        return serve_main(args)
 
     import torch
 
@@ -301,6 +312,90 @@ def batch_main(args):
         "rr_sets_per_s": round(sets / tb, 1),
         "slowest_alone_ms": {name: round(ms, 3) for ms, name in slow},
         "roofline": roofline,
+    }
+    eng.close()
+    print(json.dumps(line), flush=True)
+
+
+def serve_main(args):
+    import numpy as np
+    import torch
+
+    import paper_1404_0900_amd as tim
+    import synth
+
+    slots, budget = 16, 200 << 30
+    log("generating the 4 resident graphs of the serving workload")
+    graphs = synth.serve_graphs()
+    eng = tim.Engine(0, budget_bytes=budget)
+    dgs = [eng.upload(g) for g in graphs]
+    log(f"graphs resident: {[g.n for g in graphs]} nodes, {sum(g.m for g in graphs)} edges")
+    for q in synth.serve_queries(8, 100.0, 99):  # warm-up: buffers of the plain path
+        eng.run(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"])
+
+    def serve(qs):
+        with eng.serve(slots) as srv:
+            t0 = time.perf_counter()
+            tickets = []
+            for q in qs:
+                delay = q["arrival"] - (time.perf_counter() - t0)
+                if delay > 0:
+                    time.sleep(delay)
+                tickets.append((time.perf_counter() - t0,
+                                srv.submit(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"])))
+            res = [(t_sub,) + srv.wait(t) for t_sub, t in tickets]
+            info = srv.stop()
+        return res, info
+
+    serve(synth.serve_queries(16, 200.0, 98))  # warm-up: member contexts and their buffers
+    sweep, last = [], None
+    for idx, rate in enumerate((1.0, 5.0, 20.0, 50.0, 200.0)):
+        count = int(min(60, max(10, rate * 10)))
+        qs = synth.serve_queries(count, rate, 7 + idx)
+        res, info = serve(qs)
+        lat = np.array([r[4] for r in res])
+        first = qs[0]["arrival"]
+        done = max(r[0] + r[4] / 1e3 for r in res)
+        point = {"rate_per_s": rate, "queries": count, "completed_per_s": round(count / (done - first), 3),
+                 "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                 "rounds": int(info.rounds), "max_jobs": int(info.max_jobs)}
+        sweep.append(point)
+        last = (qs, res)
+        log(f"rate {rate:g}/s: {point}")
+
+    # the last point's queries one by one: the plain rate, and the same results
+    qs, res = last
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    identical = True
+    for q, r in zip(qs, res):
+        seeds, gains, rep = eng.run(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"])
+        identical = identical and np.array_equal(seeds, r[1]) and np.array_equal(gains, r[2]) and \
+            rep.select.theta == r[3].select.theta and rep.refine.kpt_plus == r[3].refine.kpt_plus
+    plain = time.perf_counter() - t0
+    log(f"plain: {len(qs)} queries one by one in {plain:.3f} s, identical={identical}")
+    top = sweep[-1]
+    line = {
+        "metric": "served TIM+ queries/s at 200 Poisson arrivals/s (1 GPU, continuous batching), p50/p99 latency",
+        "value": top["completed_per_s"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": len(sweep),
+        "warmup": 1,
+        "ms_per_step": round(1e3 * top["queries"] / top["completed_per_s"], 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 integer, f64 kappa",
+        "data": "synthetic (4 seeded directed Chung-Lu graphs, alpha=2.1; seeded Poisson query stream)",
+        "config": {"workload": "serve_chunglu_4graphs_deg16_poisson", "graphs_n": [g.n for g in graphs],
+                   "avg_degree": synth.SERVE_DEGREE, "models": ["IC p=1/indeg", "LT"], "k_range": [1, 100],
+                   "eps": [0.1, 0.2, 0.3], "ell": 1.0, "slots": slots, "budget_bytes": budget},
+        "p50_ms": top["p50_ms"],
+        "p99_ms": top["p99_ms"],
+        "sweep": sweep,
+        "plain": {"value": round(len(qs) / plain, 3), "unit": "queries/s", "queries": len(qs)},
+        "identical_outputs": identical,
     }
     eng.close()
     print(json.dumps(line), flush=True)

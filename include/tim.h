@@ -336,6 +336,36 @@ typedef struct {
  * variable TIM_BATCH_WINDOW_US, read per call). */
 tim_status tim_run_batch(tim_ctx *ctx, tim_query *queries, int count, int max_concurrent, tim_batch_info *info);
 
+/* ---- serving: queries that arrive over time ------------------------------ */
+
+typedef struct tim_server tim_server;
+
+/* Starts a request loop on ctx for its resident graphs (upload them first:
+ * the large-set slots are sized for the largest).  Up to `slots` queries run
+ * at once, each on a member context with an equal share of the context's
+ * budget (as in tim_run_batch); the RR-set requests of the queries running
+ * at any moment are batched into shared launches, so a query that arrives
+ * while others run joins them at the next round.  Further queries wait in
+ * a FIFO queue until a slot frees up.  Results are those of tim_run alone.
+ * While the server runs, ctx takes no other call but the server's; stop it
+ * before destroying ctx. */
+tim_status tim_server_start(tim_ctx *ctx, int slots, tim_server **out);
+
+/* Queues one query (arguments as tim_run; TIM_EINVAL if they are invalid).
+ * *q and its output arrays must stay valid until tim_server_wait returns for
+ * it or the server stops.  *ticket (host) receives its number.  Thread-safe. */
+tim_status tim_server_submit(tim_server *srv, tim_query *q, uint64_t *ticket);
+
+/* Blocks until the query of `ticket` is done and returns its status (also
+ * in q->status); *latency_ms (host, nullable) receives the time from its
+ * submission to its completion.  Thread-safe; may be called more than once. */
+tim_status tim_server_wait(tim_server *srv, uint64_t ticket, double *latency_ms);
+
+/* Runs every queued query to completion, stops the threads and frees the
+ * server (tickets become invalid).  info (host, nullable) receives the
+ * batching statistics of its lifetime. */
+tim_status tim_server_stop(tim_server *srv, tim_batch_info *info);
+
 #ifdef __cplusplus
 }
 #endif

@@ -29,7 +29,8 @@ EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_devi
             "tim_graph_upload",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
-            "tim_profile_read", "tim_run_batch")
+            "tim_profile_read", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
+            "tim_server_stop")
 
 U64, I64, U32, I32, DBL, P = (ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
                               ctypes.c_void_p)
@@ -136,6 +137,10 @@ def load_library():
         "tim_profile_read": (ctypes.c_int, [P, ctypes.POINTER(Profile)]),
         "tim_run_batch": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(BatchInfo)]),
+        "tim_server_start": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(P)]),
+        "tim_server_submit": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.POINTER(U64)]),
+        "tim_server_wait": (ctypes.c_int, [P, U64, ctypes.POINTER(DBL)]),
+        "tim_server_stop": (ctypes.c_int, [P, ctypes.POINTER(BatchInfo)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -319,6 +324,10 @@ class Engine:
                                 gains.ctypes.data, ctypes.byref(rep)))
         return seeds, gains, rep
 
+    def serve(self, slots: int) -> "Server":
+        """Starts a request loop with `slots` queries at a time (upload the graphs first)."""
+        return Server(self, slots)
+
     def run_batch(self, queries, max_concurrent: int = 0):
         """Runs queries [(graph, model, k, eps, ell, seed[, flags]), ...] as one batch.
 
@@ -338,6 +347,50 @@ class Engine:
         info = BatchInfo()
         _check(self.lib.tim_run_batch(self.ctx, arr, nq, max_concurrent, ctypes.byref(info)))
         return keep, info
+
+
+class Server:
+    """A request loop on an Engine (tim_server_*): submit() queues a query, wait() returns its result."""
+
+    def __init__(self, engine: "Engine", slots: int):
+        self.engine = engine
+        self.lib = engine.lib
+        h = P()
+        _check(self.lib.tim_server_start(engine.ctx, slots, ctypes.byref(h)))
+        self.handle = h.value
+        self._pending = {}
+
+    def submit(self, g: DeviceGraph, model: int, k: int, eps: float, ell: float, seed: int, flags: int = 0) -> int:
+        seeds = np.zeros(k, dtype=np.int32)
+        gains = np.zeros(k, dtype=np.uint64)
+        rep = Report()
+        q = Query(g.handle, model, k, eps, ell, seed, flags, seeds.ctypes.data, gains.ctypes.data,
+                  ctypes.addressof(rep), 0)
+        t = U64(0)
+        _check(self.lib.tim_server_submit(self.handle, ctypes.byref(q), ctypes.byref(t)))
+        self._pending[int(t.value)] = (q, seeds, gains, rep)
+        return int(t.value)
+
+    def wait(self, ticket: int):
+        """(seeds, gains, Report, latency in ms) of a submitted query."""
+        lat = DBL(0.0)
+        _check(self.lib.tim_server_wait(self.handle, ticket, ctypes.byref(lat)))
+        _, seeds, gains, rep = self._pending.pop(ticket)
+        return seeds, gains, rep, lat.value
+
+    def stop(self) -> BatchInfo:
+        info = BatchInfo()
+        if self.handle:
+            _check(self.lib.tim_server_stop(self.handle, ctypes.byref(info)))
+            self.handle = None
+            self._pending.clear()
+        return info
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.stop()
 
 
 def report_dict(rep: Report, k: int) -> dict:

@@ -110,6 +110,8 @@ struct tim_ctx {
   // (with their buffers) from one tim_run_batch call to the next
   Hub* batch = nullptr;
   std::vector<tim_ctx*> members;
+  bool serving = false;  // a server runs on this context
+  int64_t max_graph_n = 0;  // largest graph uploaded to this context
   hipEvent_t ready_ev = nullptr;
   bool prof_on = false;
   hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
@@ -1223,6 +1225,11 @@ void hub_scheduler(Hub* h) {
   }
 }
 
+void hub_enter(Hub* h) {
+  std::lock_guard<std::mutex> lk(h->mu);
+  h->alive += 1;
+}
+
 void hub_leave(Hub* h) {
   std::lock_guard<std::mutex> lk(h->mu);
   h->alive -= 1;
@@ -1295,7 +1302,7 @@ void hub_free_slots(Hub* h) {
 // free or already held by the hub and its members); the last-tier slots for
 // the largest graph come first (one per CU where a quarter of it allows),
 // and every query running at once gets an equal share of the rest.
-tim_status hub_prepare(Hub* h, tim_ctx* parent, const tim_query* qs, int nq, int workers) {
+tim_status hub_prepare(Hub* h, tim_ctx* parent, int64_t maxn, int workers) {
   uint64_t limit = 0;
   if (parent->budget) {
     limit = parent->budget > parent->held ? parent->budget - parent->held : 0;
@@ -1307,8 +1314,7 @@ tim_status hub_prepare(Hub* h, tim_ctx* parent, const tim_query* qs, int nq, int
     limit = (uint64_t)(0.85 * (double)(free_b + ours));
   }
   h->limit = limit;
-  int64_t maxn = 2;
-  for (int i = 0; i < nq; ++i) maxn = std::max<int64_t>(maxn, qs[i].graph->n);
+  maxn = std::max<int64_t>(maxn, 2);
   const uint64_t per = (uint64_t)maxn * 8;
   const int slots = (int)std::min<uint64_t>((uint64_t)std::max(h->num_cu, 64), limit / 4 / per);
   if (slots < 1) return fail(TIM_EBUDGET, "budget too small for the large-set pass of the batch");
@@ -1363,6 +1369,66 @@ void hub_destroy(tim_ctx* parent) {
   if (h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   parent->batch = nullptr;
+}
+
+// ---- serving: queries that arrive over time ----
+//
+// The same hub and member contexts as a batch.  Submitted queries wait in a
+// queue; each of `slots` worker threads takes the next one when it is free
+// and runs it on its member context.  The hub's rounds gather the sampling
+// requests of whichever queries are running at that moment (continuous
+// batching): a query that arrives while others are on the GPU joins the
+// next round its worker reaches.
+
+struct Ticket {
+  tim_query* q = nullptr;
+  std::chrono::steady_clock::time_point submitted, finished;
+  bool done = false;
+  std::string err;
+};
+
+}  // namespace
+
+struct tim_server {
+  tim_ctx* ctx = nullptr;
+  Hub* hub = nullptr;
+  int slots = 0;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::vector<Ticket*> queue;  // FIFO: queue[head ..]
+  size_t head = 0;
+  std::vector<Ticket*> tickets;  // by ticket number
+  bool stopping = false;
+  std::vector<std::thread> workers;
+  std::thread sched;
+};
+
+namespace {
+
+void server_worker(tim_server* sv, tim_ctx* c) {
+  (void)hipSetDevice(c->device);
+  for (;;) {
+    Ticket* t = nullptr;
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_work.wait(lk, [&] { return sv->stopping || sv->head < sv->queue.size(); });
+      if (sv->head == sv->queue.size()) break;  // stopping, nothing left
+      t = sv->queue[sv->head++];
+    }
+    hub_enter(sv->hub);
+    tim_query& q = *t->q;
+    q.status = run_impl(c, q.graph, q.model, q.k, q.eps, q.ell, q.seed, q.flags, q.seeds, q.gains, q.report);
+    const std::string err = q.status == TIM_OK ? std::string() : g_error;
+    c->stored.valid = false;
+    hub_leave(sv->hub);
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      t->err = err;
+      t->finished = std::chrono::steady_clock::now();
+      t->done = true;
+    }
+    sv->cv_done.notify_all();
+  }
 }
 
 }  // namespace
@@ -1481,6 +1547,7 @@ tim_status tim_graph_upload(tim_ctx* c, int64_t n, int64_t m, const int64_t* in_
   HIP_TRY(hipSetDevice(c->device));
   tim_graph* g = new tim_graph();
   g->ctx = c;
+  c->max_graph_n = std::max<int64_t>(c->max_graph_n, n);
   g->n = n;
   g->m = m;
   const size_t mpad = (size_t)((m + 3) / 4 * 4 + 4);
@@ -1646,6 +1713,7 @@ tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_conc
   if (!c || (count > 0 && !queries)) return fail(TIM_EINVAL, "null argument");
   if (count < 0 || max_concurrent < 0) return fail(TIM_EINVAL, "negative count");
   if (c->hub) return fail(TIM_EINVAL, "context is a batch member");
+  if (c->serving) return fail(TIM_EINVAL, "a server runs on this context");
   if (info) memset(info, 0, sizeof(*info));
   for (int i = 0; i < count; ++i) {
     tim_query& q = queries[i];
@@ -1665,7 +1733,9 @@ tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_conc
     }
   }
   Hub& hub = *c->batch;
-  TIM_TRY(hub_prepare(&hub, c, queries, count, workers));
+  int64_t maxn = 2;
+  for (int i = 0; i < count; ++i) maxn = std::max<int64_t>(maxn, queries[i].graph->n);
+  TIM_TRY(hub_prepare(&hub, c, maxn, workers));
   std::atomic<int> next{0};
   std::vector<std::string> errs((size_t)count);
   std::thread sched(hub_scheduler, &hub);
@@ -1691,6 +1761,103 @@ tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_conc
   }
   for (int i = 0; i < count; ++i)
     if (queries[i].status != TIM_OK) return fail(queries[i].status, "query %d: %s", i, errs[(size_t)i].c_str());
+  return TIM_OK;
+}
+
+tim_status tim_server_start(tim_ctx* c, int slots, tim_server** out) {
+  if (!c || !out || slots < 1) return fail(TIM_EINVAL, "null argument or slots < 1");
+  *out = nullptr;
+  if (c->hub) return fail(TIM_EINVAL, "context is a batch member");
+  if (c->serving) return fail(TIM_EINVAL, "a server already runs on this context");
+  if (c->max_graph_n < 2) return fail(TIM_EINVAL, "upload the graphs before starting a server");
+  HIP_TRY(hipSetDevice(c->device));
+  if (!c->batch) {
+    c->batch = new Hub();
+    const tim_status st = hub_setup(c->batch, c);
+    if (st != TIM_OK) {
+      hub_destroy(c);
+      return st;
+    }
+  }
+  TIM_TRY(hub_prepare(c->batch, c, c->max_graph_n, slots));
+  c->batch->alive = 0;  // queries in flight, counted as they start and finish
+  tim_server* sv = new tim_server();
+  sv->ctx = c;
+  sv->hub = c->batch;
+  sv->slots = slots;
+  c->serving = true;
+  sv->sched = std::thread(hub_scheduler, sv->hub);
+  for (int w = 0; w < slots; ++w) sv->workers.emplace_back(server_worker, sv, c->members[(size_t)w]);
+  *out = sv;
+  return TIM_OK;
+}
+
+tim_status tim_server_submit(tim_server* sv, tim_query* q, uint64_t* ticket) {
+  if (!sv || !q || !ticket) return fail(TIM_EINVAL, "null argument");
+  tim_ctx* c = sv->ctx;
+  TIM_TRY(check_run_args(c, q->graph, q->model, q->k, q->eps, q->ell, q->seeds));
+  if ((uint64_t)q->graph->n > sv->hub->big_stride)
+    return fail(TIM_EINVAL, "graph uploaded after the server started is larger than its slots");
+  Ticket* t = new Ticket();
+  t->q = q;
+  q->status = TIM_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    if (sv->stopping) {
+      delete t;
+      return fail(TIM_EINVAL, "server is stopping");
+    }
+    t->submitted = std::chrono::steady_clock::now();
+    *ticket = (uint64_t)sv->tickets.size();
+    sv->tickets.push_back(t);
+    sv->queue.push_back(t);
+  }
+  sv->cv_work.notify_one();
+  return TIM_OK;
+}
+
+tim_status tim_server_wait(tim_server* sv, uint64_t ticket, double* latency_ms) {
+  if (!sv) return fail(TIM_EINVAL, "null server");
+  Ticket* t = nullptr;
+  {
+    std::unique_lock<std::mutex> lk(sv->mu);
+    if (ticket >= sv->tickets.size()) return fail(TIM_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+    t = sv->tickets[(size_t)ticket];
+    sv->cv_done.wait(lk, [&] { return t->done; });
+  }
+  if (latency_ms) *latency_ms = std::chrono::duration<double, std::milli>(t->finished - t->submitted).count();
+  if (t->q->status != TIM_OK) return fail(t->q->status, "%s", t->err.c_str());
+  return TIM_OK;
+}
+
+tim_status tim_server_stop(tim_server* sv, tim_batch_info* info) {
+  if (!sv) return fail(TIM_EINVAL, "null server");
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->stopping = true;
+  }
+  sv->cv_work.notify_all();
+  for (std::thread& w : sv->workers) w.join();
+  Hub* h = sv->hub;
+  {
+    std::lock_guard<std::mutex> lk(h->mu);
+    h->stop = true;
+    h->cv_sched.notify_one();
+  }
+  sv->sched.join();
+  if (info) {
+    memset(info, 0, sizeof(*info));
+    info->rounds = h->rounds;
+    info->jobs = h->jobs;
+    info->launches = h->launches;
+    info->max_jobs = h->max_jobs;
+    info->workers = (uint64_t)sv->slots;
+    info->budget_bytes = h->limit;
+    info->member_budget_bytes = h->member_budget;
+  }
+  sv->ctx->serving = false;
+  for (Ticket* t : sv->tickets) delete t;
+  delete sv;
   return TIM_OK;
 }
 

@@ -166,6 +166,40 @@ def batch_graphs(queries, workers: int = 8) -> list:
         return list(ex.map(batch_graph, queries))
 
 
+# Serving workload: resident graphs and a seeded stream of queries arriving over time.
+SERVE_GRAPHS = ((100_000, 1601), (1_000_000, 1602), (4_000_000, 1603), (10_000_000, 1604))  # (n, seed)
+SERVE_DEGREE = 16
+
+
+def serve_graphs(scale: float = 1.0, workers: int = 4) -> list:
+    """The serving workload's resident graphs: directed Chung-Lu (alpha 2.1), average degree 16, with
+    n = 10^5, 10^6, 4*10^6 and 10^7 (times `scale`, for tests), generated by `workers` threads."""
+    from concurrent.futures import ThreadPoolExecutor
+    _load()
+    specs = [(max(1000, int(n * scale)), seed) for n, seed in SERVE_GRAPHS]
+    with ThreadPoolExecutor(max_workers=max(1, workers)) as ex:
+        return list(ex.map(lambda a: chung_lu(a[0], SERVE_DEGREE * a[0], 2.1, a[1], name=f"serve_n{a[0]}"), specs))
+
+
+def serve_queries(count: int, rate: float, seed: int, ngraphs: int = 4, k_max: int = 100,
+                  eps_choices=(0.1, 0.2, 0.3)) -> list:
+    """A seeded stream of `count` queries with Poisson arrivals at `rate` per second.
+
+    From numpy's default_rng(seed), per query in order: the gap to the previous arrival (exponential,
+    mean 1/rate; the first query arrives at its gap), the graph (uniform over ngraphs), the model (IC
+    with p = 1/indeg, or LT, uniform), k uniform in [1, k_max], eps from eps_choices; ell = 1 and the
+    algorithm seed is seed * 100000 + the query's index.
+    """
+    r = np.random.default_rng(seed)
+    out, t = [], 0.0
+    for i in range(count):
+        t += float(r.exponential(1.0 / rate))
+        out.append(dict(arrival=t, graph=int(r.integers(0, ngraphs)), model=int(r.integers(0, 2)),
+                        k=int(r.integers(1, k_max + 1)), eps=float(r.choice(np.asarray(eps_choices))),
+                        ell=1.0, seed=seed * 100_000 + i))
+    return out
+
+
 # Configurations of the synthetic workloads (graph part only).
 CONFIGS = {
     "cfg1": dict(n=15_000, m=60_000, alpha=2.1, seed=1),

@@ -48,3 +48,22 @@ def test_batch_graph_thresholds_and_csr():
             assert set(np.unique(thr).tolist()) == {429_496_728, 42_949_671, 4_294_966}
         else:
             assert thr is None
+
+
+def test_serve_queries_follow_the_recipe():
+    qs = synth.serve_queries(2000, 50.0, 7)
+    assert qs == synth.serve_queries(2000, 50.0, 7)
+    t = np.array([q["arrival"] for q in qs])
+    assert np.all(np.diff(t) > 0)
+    gaps = np.diff(np.concatenate([[0.0], t]))
+    assert abs(gaps.mean() - 1 / 50.0) < 0.003  # Poisson arrivals at 50 per second
+    assert {q["graph"] for q in qs} == {0, 1, 2, 3} and {q["model"] for q in qs} == {0, 1}
+    assert min(q["k"] for q in qs) >= 1 and max(q["k"] for q in qs) <= 100
+    assert {q["eps"] for q in qs} == {0.1, 0.2, 0.3}
+    assert len({q["seed"] for q in qs}) == len(qs)
+
+
+def test_serve_graph_sizes():
+    gs = synth.serve_graphs(scale=0.01)
+    assert [g.n for g in gs] == [1000, 10000, 40000, 100000]
+    assert all(g.m == 16 * g.n for g in gs)
