@@ -86,6 +86,8 @@ def _load():
         "orc_wc_threshold": (ctypes.c_uint32, [ctypes.c_int64]),
         "orc_lt_pick": (ctypes.c_int64, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64,
                                          ctypes.c_int64]),
+        "orc_lt_pick_cumulative": (ctypes.c_int64, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
+                                                    ctypes.c_int64, _P, ctypes.c_int64]),
         "orc_sample_sets": (ctypes.c_int64, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                                   ctypes.c_uint64, _P, _P, ctypes.c_int64, _P]),
         "orc_rr_single": (ctypes.c_int64, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, _P,
@@ -168,6 +170,12 @@ def wc_threshold(d) -> int:
 
 def lt_pick(seed, phase, set_id, v, d) -> int:
     return int(_load().orc_lt_pick(seed, phase, set_id, v, d))
+
+
+def lt_pick_cumulative(seed, phase, set_id, v, t) -> int:
+    """In-edge index the LT walk takes at v under cumulative thresholds t (uint32 over v's in-edges), or -1."""
+    t = np.ascontiguousarray(t, dtype=np.uint32)
+    return int(_load().orc_lt_pick_cumulative(seed, phase, set_id, v, t.ctypes.data, len(t)))
 
 
 # ---- RR sets ---------------------------------------------------------------

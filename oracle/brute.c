@@ -13,7 +13,9 @@
  * IC edge e is kept with probability (t(e) + 1) / 2^32, the probability that
  * a uniform 32-bit word is <= its uint32 threshold t(e); under the weighted
  * cascade t = floor(2^32/indeg) - 1.  LT: every node of in-degree d >= 1 keeps
- * exactly one in-edge, each with probability 1/d.
+ * at most one in-edge: without thresholds each with probability 1/d; with
+ * cumulative thresholds t_0 <= .. <= t_{d-1} edge j with probability
+ * (t_j - t_{j-1}) / 2^32 (t_{-1} = -1) and none with (2^32 - 1 - t_{d-1}) / 2^32.
  * Node sets are bit masks, so n <= 20.
  */
 #include <math.h>
@@ -27,6 +29,8 @@ typedef struct {
   int indeg[32];
   long double p[64];  /* IC keep probability */
   int first_in[33];   /* in-edges of v are [first_in[v], first_in[v+1]) in CSR order */
+  int lt_choices[32];  /* LT: outcomes at v (its in-edges, and the empty set if it has probability) */
+  long double lt_p[64 + 32]; /* LT: probability of outcome c of v at lt_p[first_in[v] + v + c] */
 } bgraph;
 
 static int load(bgraph *g, int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr) {
@@ -43,6 +47,23 @@ static int load(bgraph *g, int64_t n, int64_t m, const int64_t *off, const int32
       if (thr) t = thr[e];
       else t = (((uint64_t)1 << 32) / (uint64_t)g->indeg[v]) - 1;
       g->p[e] = ((long double)t + 1.0L) / 4294967296.0L;
+    }
+    /* LT outcomes of v: its in-edges in order, then the empty triggering set */
+    const int d = g->indeg[v];
+    long double *lp = g->lt_p + off[v] + v;
+    g->lt_choices[v] = d;
+    if (!thr) {
+      for (int j = 0; j < d; ++j) lp[j] = 1.0L / (long double)d;
+    } else if (d > 0) {
+      int64_t prev = -1;
+      for (int j = 0; j < d; ++j) {
+        lp[j] = (long double)((int64_t)thr[off[v] + j] - prev) / 4294967296.0L;
+        prev = (int64_t)thr[off[v] + j];
+      }
+      if (prev < 0xFFFFFFFFLL) {
+        lp[d] = (long double)(0xFFFFFFFFLL - prev) / 4294967296.0L;
+        g->lt_choices[v] = d + 1;
+      }
     }
   }
   g->first_in[n] = (int)m;
@@ -80,26 +101,27 @@ static int64_t for_each_world(const bgraph *g, int model, world_fn fn, void *ctx
     }
     return (int64_t)worlds;
   }
-  /* LT: a mixed-radix counter over the in-edge choice of each node */
+  /* LT: a mixed-radix counter over the outcome at each node (one of its
+   * in-edges, or none) */
   int choice[32];
   int64_t worlds = 1;
   for (int v = 0; v < g->n; ++v) {
     choice[v] = 0;
-    if (g->indeg[v] > 0) worlds *= g->indeg[v];
+    if (g->lt_choices[v] > 0) worlds *= g->lt_choices[v];
     if (worlds > ((int64_t)1 << 26)) return -1;
   }
   for (int64_t w = 0; w < worlds; ++w) {
     uint64_t live = 0;
     long double prob = 1.0L;
     for (int v = 0; v < g->n; ++v) {
-      if (g->indeg[v] == 0) continue;
-      live |= (uint64_t)1 << (g->first_in[v] + choice[v]);
-      prob /= (long double)g->indeg[v];
+      if (g->lt_choices[v] == 0) continue;
+      if (choice[v] < g->indeg[v]) live |= (uint64_t)1 << (g->first_in[v] + choice[v]);
+      prob *= g->lt_p[g->first_in[v] + v + choice[v]];
     }
-    fn(g, live, prob, ctx);
+    if (prob != 0.0L) fn(g, live, prob, ctx);
     for (int v = 0; v < g->n; ++v) {
-      if (g->indeg[v] == 0) continue;
-      if (++choice[v] < g->indeg[v]) break;
+      if (g->lt_choices[v] == 0) continue;
+      if (++choice[v] < g->lt_choices[v]) break;
       choice[v] = 0;
     }
   }

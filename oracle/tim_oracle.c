@@ -34,6 +34,13 @@
  *   R3 root = floor(X64 * n / 2^64), X64 = word1<<32 | word0 of the root draw.
  *   R4 LT pick at node v: j = floor(X64 * indeg(v) / 2^64), in-edge off[v]+j;
  *      the walk stops at a node of in-degree 0 or at an already visited node.
+ *   R9 LT with in-weights (Section 7.1: random weights normalized per node)
+ *      is given as per-edge uint32 cumulative thresholds t_0 <= .. <= t_{d-1}
+ *      over v's in-edges in CSR order: t_j = floor(C_j * 2^32) - 1 for the
+ *      cumulative weight C_j.  With x = word0 of the pick draw at v, the walk
+ *      takes the first in-edge j with x <= t_j, and stops at v if x > t_{d-1}
+ *      (the empty triggering set, of probability 1 - C_{d-1}).  Edge j has
+ *      probability (t_j - t_{j-1}) / 2^32 with t_{-1} = -1.
  *   R5 kappa in IEEE binary64 without contraction: q = 1 - w/m, r = q^k by
  *      binary exponentiation (r=1,b=q; per bit: if set r*=b; shift; if more
  *      bits b*=b), kappa = 1 - r.  kappa*2^53 is an integer; the round sum is
@@ -119,6 +126,17 @@ int64_t orc_lt_pick(uint64_t seed, uint32_t phase, uint64_t set, int64_t v, int6
   return (int64_t)(((u128)x64 * (u128)(uint64_t)d) >> 64);
 }
 
+/* LT pick with cumulative thresholds t[0..d) at node v (reading R9): the
+ * index of the in-edge taken, or -1 if the walk stops at v. */
+int64_t orc_lt_pick_cumulative(uint64_t seed, uint32_t phase, uint64_t set, int64_t v, const uint32_t *t,
+                               int64_t d) {
+  uint32_t x[4];
+  orc_draw(seed, phase, 2, (uint64_t)v, set, x);
+  for (int64_t j = 0; j < d; ++j)
+    if (x[0] <= t[j]) return j;
+  return -1;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Graph and per-set workspace.                                              */
 /* ------------------------------------------------------------------------- */
@@ -127,7 +145,8 @@ typedef struct {
   int64_t n, m;
   const int64_t *off;  /* in-CSR offsets, n+1 */
   const int32_t *src;  /* sources of in-edges, sorted by (dst, src) */
-  const uint32_t *thr; /* per-edge IC thresholds, or NULL for weighted cascade */
+  const uint32_t *thr; /* per-edge thresholds of the model: IC live thresholds (NULL: weighted
+                          cascade), LT cumulative thresholds (NULL: uniform 1/indeg) */
 } orc_graph;
 
 typedef struct {
@@ -201,7 +220,10 @@ static int64_t rr_set(const orc_graph *g, int model, uint64_t seed, uint32_t pha
       int64_t a = g->off[v], d = g->off[v + 1] - a;
       wsum += (uint64_t)d;
       if (d == 0) break;
-      int32_t u = g->src[a + orc_lt_pick(seed, phase, set, v, d)];
+      int64_t j = g->thr ? orc_lt_pick_cumulative(seed, phase, set, v, g->thr + a, d)
+                         : orc_lt_pick(seed, phase, set, v, d);
+      if (j < 0) break; /* the empty triggering set */
+      int32_t u = g->src[a + j];
       if (w->mark[u] == w->stamp) break;
       w->mark[u] = w->stamp;
       w->queue[len++] = u;

@@ -102,6 +102,37 @@ def random_thresholds(m: int, seed: int, choices=None) -> np.ndarray:
     return c[rng.integers(0, len(c), size=m)]
 
 
+def random_lt_thresholds(g: Graph, seed: int, total=None) -> np.ndarray:
+    """LT in-weights drawn at random and normalized per node, as uint32 cumulative thresholds.
+
+    Every in-edge of v gets an integer weight uniform in [1, 2^16]; with S_j the sum of the first j+1
+    weights of v's list (CSR order) and S the sum of all of them, t_j = floor(S_j * 2^32 / S) - 1
+    (exact integer arithmetic; the last is 2^32 - 1, so the weights sum to 1), clamped to >= 0.
+    `total` (a float in (0, 1], or None for 1) scales the cumulative weights so that they sum to
+    `total` instead: the walk then stops at v with probability about 1 - total.
+    """
+    rng = np.random.default_rng(seed)
+    w = rng.integers(1, 2**16 + 1, size=g.m, dtype=np.uint64)
+    cum = np.cumsum(w, dtype=np.uint64)
+    indeg = np.diff(g.off)
+    first = np.repeat(g.off[:-1], indeg)  # first edge of each edge's node
+    before = np.where(first > 0, cum[np.maximum(first - 1, 0)], 0).astype(np.uint64)
+    s_j = cum - before  # prefix within the node's list, <= 2^16 * indeg < 2^48
+    last = (g.off[1:] - 1)[indeg > 0]
+    s_tot = np.zeros(g.n, dtype=np.uint64)
+    s_tot[indeg > 0] = cum[last] - np.where(g.off[:-1][indeg > 0] > 0,
+                                            cum[np.maximum(g.off[:-1][indeg > 0] - 1, 0)], 0)
+    den = np.repeat(s_tot, indeg)
+    if total is not None:  # scale the numerator by total in 2^-16 steps
+        s_j = (s_j * np.uint64(int(round(total * 65536)))) >> np.uint64(16)
+    # floor(s_j * 2^32 / den) in two 16-bit steps (no product exceeds 2^64)
+    hi = (s_j << np.uint64(16)) // den
+    rem = (s_j << np.uint64(16)) % den
+    q = (hi << np.uint64(16)) + ((rem << np.uint64(16)) // den)
+    t = q.astype(np.int64) - 1
+    return np.clip(t, 0, 0xFFFFFFFF).astype(np.uint32)
+
+
 def random_small_graph(n: int, m: int, seed: int) -> Graph:
     """Uniform random simple digraph with exactly m edges (tiny sizes, for exhaustive tests)."""
     rng = np.random.default_rng(seed)

@@ -92,6 +92,62 @@ def test_lt_pick_uniform():
     assert chi2 < 25.0
 
 
+def _cumulative(weights):
+    """uint32 cumulative thresholds t_j = floor(C_j * 2^32) - 1 of exact rational weights."""
+    c, out = Fraction(0), []
+    for w in weights:
+        c += Fraction(w)
+        out.append(int(c * 2**32) - 1)
+    return np.array(out, dtype=np.uint32)
+
+
+def test_lt_pick_cumulative_follows_the_weights():
+    # weights 1/10, 1/5, 3/10, 1/5: the walk stops at v with probability 1/5
+    w = [Fraction(1, 10), Fraction(1, 5), Fraction(3, 10), Fraction(1, 5)]
+    t = _cumulative(w)
+    N = 60000
+    picks = np.array([oracle.lt_pick_cumulative(9, 64, s, 33, t) for s in range(N)])
+    counts = np.array([(picks == j).sum() for j in range(4)] + [(picks == -1).sum()])
+    p = np.array([float(x) for x in w] + [0.2])
+    chi2 = ((counts - N * p) ** 2 / (N * p)).sum()
+    assert chi2 < 30.0  # 4 degrees of freedom
+
+
+def test_lt_pick_cumulative_boundaries():
+    # the pick compares word 0 of the node's pick draw with each threshold, inclusively
+    for s in range(20):
+        x = oracle.draw(4, 64, 2, 12, s)[0]
+        if 2 <= x <= 0xFFFFFFFD:
+            assert oracle.lt_pick_cumulative(4, 64, s, 12, [x - 1, x, 0xFFFFFFFF]) == 1
+            assert oracle.lt_pick_cumulative(4, 64, s, 12, [x, x, x]) == 0
+            assert oracle.lt_pick_cumulative(4, 64, s, 12, [x - 2, x - 1]) == -1
+        assert oracle.lt_pick_cumulative(4, 64, s, 12, [0xFFFFFFFF]) == 0
+
+
+def test_lt_first_in_edge_when_it_holds_all_the_weight():
+    # thresholds all 2^32 - 1: every node takes its first in-edge, so the set is the chain of first in-edges
+    g = synth.chung_lu(300, 1500, 2.1, 5)
+    t = np.full(g.m, 0xFFFFFFFF, dtype=np.uint32)
+    for s in range(200):
+        root = oracle.root(6, 64, s, g.n)
+        chain, v = [root], root
+        while g.off[v + 1] > g.off[v] and int(g.src[g.off[v]]) not in chain:
+            v = int(g.src[g.off[v]])
+            chain.append(v)
+        nodes, w = oracle.rr_set(g, LT, 6, 64, s, thr=t)
+        assert list(nodes) == sorted(chain)
+        assert w == sum(int(g.off[u + 1] - g.off[u]) for u in chain)
+
+
+def test_lt_sets_are_single_roots_when_weights_vanish():
+    # cumulative thresholds 0: an in-edge is taken with probability 2^-32, so the walk stops at the root
+    g = synth.chung_lu(300, 1500, 2.1, 5)
+    t = np.zeros(g.m, dtype=np.uint32)
+    so, nodes, widths = oracle.sample_sets(g, LT, 6, 64, 0, 2000, thr=t)
+    assert np.all(np.diff(so) == 1)
+    assert np.array_equal(widths, np.diff(g.off)[nodes].astype(np.uint64))
+
+
 # ---------------------------------------------------- RR set = ancestors --
 def _ancestors(n, live_edges, root):
     """Nodes that reach `root` along live edges: fixed-point iteration."""
@@ -120,16 +176,22 @@ def _live_world(g, model, seed, phase, s, thr):
         for v in range(g.n):
             d = g.off[v + 1] - g.off[v]
             if d:
-                j = oracle.lt_pick(seed, phase, s, v, d)
-                live.append((int(g.src[g.off[v] + j]), v))
+                if thr is None:
+                    j = oracle.lt_pick(seed, phase, s, v, d)
+                else:
+                    j = oracle.lt_pick_cumulative(seed, phase, s, v, thr[g.off[v]:g.off[v + 1]])
+                if j >= 0:
+                    live.append((int(g.src[g.off[v] + j]), v))
     return live
 
 
-@pytest.mark.parametrize("model", [IC, LT])
+@pytest.mark.parametrize("model", [IC, LT, "LT-weighted"])
 @pytest.mark.parametrize("gseed", [1, 2, 3])
 def test_rr_set_is_reverse_reachable_set(model, gseed):
     g = synth.random_small_graph(9, 24, gseed)
     thr = synth.random_thresholds(g.m, gseed, choices=[0x3FFFFFFF, 0x7FFFFFFF, 0xBFFFFFFF]) if model == IC else None
+    if model == "LT-weighted":
+        model, thr = LT, synth.random_lt_thresholds(g, gseed, total=0.8)
     indeg = g.indeg()
     for s in range(60):
         nodes, w = oracle.rr_set(g, model, 77, 64, s, thr=thr)
@@ -202,6 +264,8 @@ def _tiny_cases():
         out.append((g, IC, synth.random_thresholds(g.m, gs, choices=[0x1FFFFFFF, 0x7FFFFFFF, 0xDFFFFFFF])))
         out.append((g, IC, None))
         out.append((g, LT, None))
+        out.append((g, LT, synth.random_lt_thresholds(g, gs)))                # normalized in-weights
+        out.append((g, LT, synth.random_lt_thresholds(g, gs + 1, total=0.7)))  # weights summing to 0.7
     return out
 
 
@@ -209,7 +273,7 @@ def _mask(nodes):
     return sum(1 << int(u) for u in nodes)
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(10))
 def test_lemma2_and_corollary1_rr_frequency_matches_exact_spread(case):
     g, model, thr = _tiny_cases()[case]
     spreads = oracle.brute_all_spreads(g, model, thr=thr)
@@ -233,7 +297,7 @@ def test_lemma2_and_corollary1_rr_frequency_matches_exact_spread(case):
         assert abs(hit - q) <= 5 * math.sqrt(q * (1 - q) / N) + 1e-12
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(10))
 def test_lemma4_ept_and_sampled_width(case):
     g, model, thr = _tiny_cases()[case]
     spreads = oracle.brute_all_spreads(g, model, thr=thr)
@@ -249,7 +313,7 @@ def test_lemma4_ept_and_sampled_width(case):
     assert abs(wv.mean() - st["ept"]) <= 5 * wv.std() / math.sqrt(N) + 1e-9
 
 
-@pytest.mark.parametrize("case", range(6))
+@pytest.mark.parametrize("case", range(10))
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_lemma5_kpt_equals_n_expected_kappa(case, k):
     g, model, thr = _tiny_cases()[case]
