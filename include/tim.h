@@ -60,9 +60,10 @@ typedef enum {
 
 typedef enum {
   TIM_MODEL_IC = 0, /* independent cascade (Section 2.1) */
-  TIM_MODEL_LT = 1  /* linear threshold with in-weights 1/indeg(v): a triggering
-                       model whose triggering set is one uniform in-neighbour
-                       (Section 4.2; Section 7.1) */
+  TIM_MODEL_LT = 1  /* linear threshold: a triggering model whose triggering set
+                       is one in-neighbour or none (Section 4.2; Section 7.1);
+                       in-weights 1/indeg(v) unless tim_graph_set_lt_weights
+                       gave the graph others */
 } tim_model;
 
 enum { TIM_PHASE_REFINE = 63, TIM_PHASE_SELECT = 64 };
@@ -215,6 +216,18 @@ tim_status tim_profile_read(const tim_ctx *ctx, tim_profile *out);
 tim_status tim_graph_upload(tim_ctx *ctx, int64_t n, int64_t m, const int64_t *in_off, const int32_t *in_src,
                             const uint32_t *ic_thr, tim_graph **out);
 void tim_graph_free(tim_graph *g);
+
+/* LT with in-weights (Section 7.1: a random weight per in-edge, normalized
+ * so that each node's weights sum to 1; weights summing below 1 leave the
+ * empty triggering set the rest).  lt_thr host uint32[m]: cumulative
+ * thresholds over each node's in-edges in CSR order, t_j = floor(C_j * 2^32)
+ * - 1 for the cumulative weight C_j, non-decreasing within a node (2^32 - 1
+ * at a node's last edge when its weights sum to 1).  The walk at v takes the
+ * first in-edge j with x <= t_j, x = word 0 of v's pick draw (kind 2), and
+ * stops at v if x > t_{d-1}.  in_off is the graph's host offsets (to check
+ * the order).  Later LT calls on g use these weights; NULL restores 1/indeg.
+ * TIM_EINVAL names the first decreasing pair. */
+tim_status tim_graph_set_lt_weights(tim_ctx *ctx, tim_graph *g, const uint32_t *lt_thr, const int64_t *in_off);
 
 /* ---- RR sets (Definitions 1-2; Section 3.1; Section 4.2) ---------------- */
 

@@ -26,7 +26,7 @@ OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, ECAPACITY = range(6)
 _STATUS = {1: "TIM_EINVAL", 2: "TIM_ENOMEM", 3: "TIM_EBUDGET", 4: "TIM_EDEVICE", 5: "TIM_ECAPACITY"}
 
 EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_device_bytes", "tim_set_resident_limit",
-            "tim_graph_upload",
+            "tim_graph_upload", "tim_graph_set_lt_weights",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
             "tim_profile_read", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
@@ -119,6 +119,7 @@ def load_library():
         "tim_set_resident_limit": (ctypes.c_int, [P, U64]),
         "tim_graph_upload": (ctypes.c_int, [P, I64, I64, P, P, P, ctypes.POINTER(P)]),
         "tim_graph_free": (None, [P]),
+        "tim_graph_set_lt_weights": (ctypes.c_int, [P, P, P, P]),
         "tim_sample_rr": (ctypes.c_int, [P, P, ctypes.c_int, U64, U32, U64, U64, P, P, U64, P,
                                          ctypes.POINTER(U64), ctypes.POINTER(BatchStats)]),
         "tim_sample_widths": (ctypes.c_int, [P, P, ctypes.c_int, U64, U32, U64, U64, ctypes.c_int, P, P,
@@ -233,6 +234,12 @@ class Engine:
         g = DeviceGraph(h.value, graph.n, graph.m, thr is None)
         self._graphs.append(g)
         return g
+
+    def set_lt_weights(self, g: DeviceGraph, graph, lt_thr):
+        """LT in-weights of g as uint32 cumulative thresholds per edge (None: back to 1/indeg)."""
+        off = np.ascontiguousarray(graph.off, dtype=np.int64)
+        t = None if lt_thr is None else np.ascontiguousarray(lt_thr, dtype=np.uint32)
+        _check(self.lib.tim_graph_set_lt_weights(self.ctx, g.handle, _np_ptr(t), off.ctypes.data))
 
     def free(self, g: DeviceGraph):
         self.lib.tim_graph_free(g.handle)

@@ -124,6 +124,7 @@ struct tim_graph {
   int64_t* off = nullptr;
   int32_t* src = nullptr;
   uint32_t* thr = nullptr;
+  uint32_t* lthr = nullptr;  // LT cumulative in-weight thresholds, or nullptr (1/indeg)
 };
 
 namespace {
@@ -342,6 +343,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   a.g.off = g->off;
   a.g.src = g->src;
   a.g.thr = g->thr;
+  a.g.lthr = g->lthr;
   a.g.n = g->n;
   a.g.m = g->m;
   a.seed = seed;
@@ -1575,7 +1577,38 @@ void tim_graph_free(tim_graph* g) {
   if (g->off) (void)hipFree(g->off);
   if (g->src) (void)hipFree(g->src);
   if (g->thr) (void)hipFree(g->thr);
+  if (g->lthr) (void)hipFree(g->lthr);
   delete g;
+}
+
+tim_status tim_graph_set_lt_weights(tim_ctx* c, tim_graph* g, const uint32_t* lt_thr, const int64_t* in_off) {
+  if (!c || !g || g->ctx != c) return fail(TIM_EINVAL, "graph does not belong to this context");
+  if (c->serving) return fail(TIM_EINVAL, "a server runs on this context");
+  HIP_TRY(hipSetDevice(c->device));
+  if (!lt_thr) {
+    if (g->lthr) {
+      HIP_TRY(hipStreamSynchronize(c->stream));
+      (void)hipFree(g->lthr);
+    }
+    g->lthr = nullptr;
+    return TIM_OK;
+  }
+  if (!in_off) return fail(TIM_EINVAL, "in_off is null");
+  if (in_off[0] != 0 || in_off[g->n] != g->m) return fail(TIM_EINVAL, "in_off does not match the graph");
+  for (int64_t v = 0; v < g->n; ++v)
+    for (int64_t e = in_off[v] + 1; e < in_off[v + 1]; ++e)
+      if (lt_thr[e] < lt_thr[e - 1])
+        return fail(TIM_EINVAL, "LT thresholds of node %lld decrease at edge %lld", (long long)v, (long long)e);
+  uint32_t* d = nullptr;
+  if (hipMalloc(&d, (size_t)g->m * 4) != hipSuccess) return fail(TIM_ENOMEM, "LT thresholds: hipMalloc failed");
+  if (hipMemcpyAsync(d, lt_thr, (size_t)g->m * 4, hipMemcpyHostToDevice, c->stream) != hipSuccess ||
+      hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipFree(d);
+    return fail(TIM_EDEVICE, "LT thresholds: copy failed");
+  }
+  if (g->lthr) (void)hipFree(g->lthr);
+  g->lthr = d;
+  return TIM_OK;
 }
 
 tim_status tim_sample_rr(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase, uint64_t first,

@@ -55,6 +55,7 @@ struct GraphView {
   const int64_t* off;   // n+1
   const int32_t* src;   // m rounded up to a multiple of 4, plus 4, zero padded
   const uint32_t* thr;  // same padding, or nullptr for the weighted cascade
+  const uint32_t* lthr; // LT cumulative in-weight thresholds (m), or nullptr for 1/indeg
   int64_t n, m;
 };
 

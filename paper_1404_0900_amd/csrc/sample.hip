@@ -133,6 +133,26 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
   return -1;
 }
 
+// The in-edge an LT walk takes at v (in-degree d >= 1, first in-edge ea), or
+// -1 if it stops there.  With 1/indeg weights: in-edge floor(X64 * d / 2^64).
+// With cumulative thresholds t (Section 7.1's normalized random weights): the
+// first in-edge j with word0 <= t_j, found by binary search over v's list; the
+// walk stops if word0 exceeds t_{d-1} (weights summing below 1).
+__device__ __forceinline__ int64_t lt_pick_edge(const GraphView& g, const Key& key, const SetStream& st, int32_t v,
+                                                int64_t ea, int64_t d) {
+  const uint4 x = draw(key, st, kKindPick, (uint64_t)v);
+  if (!g.lthr) return ea + (int64_t)scale64(x, (uint64_t)d);
+  const uint32_t* t = g.lthr + ea;
+  if (x.x > t[d - 1]) return -1;
+  int64_t lo = 0, hi = d - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (x.x <= t[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return ea + lo;
+}
+
 // One bit of a 64-bit membership signature: a clear bit proves absence.
 __device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
 
@@ -695,11 +715,11 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
         const int64_t ea = g.off[v];
         const int64_t d = g.off[v + 1] - ea;
         width += (unsigned long long)d;
-        if (d == 0) {
+        const int64_t e = d ? lt_pick_edge(g, key, st, v, ea, d) : -1;
+        if (e < 0) {
           done = true;
         } else {
-          const uint64_t j = scale64(draw(key, st, kKindPick, (uint64_t)v), (uint64_t)d);
-          const int32_t u = g.src[ea + (int64_t)j];
+          const int32_t u = g.src[e];
           const uint64_t bit = sig_bit(u);
           bool seen = false;
           if (sig & bit) {
@@ -943,8 +963,9 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
 
 // LT, chains longer than the first tier's LDS chain: one lane per chain and
 // no visited marks at all.  The walk's pick at a node is a fixed function of
-// (set, node), so the walk is x_{i+1} = f(x_i): it ends at a node without
-// in-edges, or it enters a cycle and the first repeated node closes the set.
+// (set, node), so the walk is x_{i+1} = f(x_i): it ends where f stops (no
+// in-edges or the empty triggering set), or it enters a cycle and the first
+// repeated node closes the set.
 // Brent's cycle detection (R. P. Brent, "An improved Monte Carlo
 // factorization algorithm", BIT 20, 1980) finds the cycle length lambda and
 // the tail length mu in O(1) memory; the set is x_0 .. x_{mu+lambda-1}, walked
@@ -963,15 +984,15 @@ enum ChainPhase : int {
   kIdle = 5
 };
 
-// f(v) and indeg(v): the in-neighbour the walk moves to from v, or -1 at a
-// node without in-edges.
+// f(v) and indeg(v): the in-neighbour the walk moves to from v, or -1 where
+// the walk stops (no in-edges, or the empty triggering set).
 __device__ __forceinline__ int32_t lt_next(const GraphView& g, const Key& key, const SetStream& st, int32_t v,
                                            int64_t& d) {
   const int64_t ea = g.off[v];
   d = g.off[v + 1] - ea;
   if (d == 0) return -1;
-  const uint64_t j = scale64(draw(key, st, kKindPick, (uint64_t)v), (uint64_t)d);
-  return g.src[ea + (int64_t)j];
+  const int64_t e = lt_pick_edge(g, key, st, v, ea, d);
+  return e < 0 ? -1 : g.src[e];
 }
 
 constexpr int kChainWaves = 4;  // wavefronts per block of the long-chain tier
