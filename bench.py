@@ -52,8 +52,8 @@ MODES = ("widths", "store", "cover")
 # WRITE_SIZE runs of this benchmark (scaled by a plain-copy calibration; see
 # profiles/ic_seg_kernel_chunglu_n1e6_m1e7.md).  Valid only for the kernel
 # sources they were taken on.
-TRAFFIC = {"kernel": "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)", "sources_sha256_16": "42455c3576ac12f2",
-           "fetch_bytes": 308359845, "write_bytes": 9106512}
+TRAFFIC = {"kernel": "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)", "sources_sha256_16": "115d5cc4e1222100",
+           "fetch_bytes": 308042083, "write_bytes": 9036248}
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/engine.hpp")
 
