@@ -88,6 +88,8 @@ def _load():
                                          ctypes.c_int64]),
         "orc_lt_pick_cumulative": (ctypes.c_int64, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                                     ctypes.c_int64, _P, ctypes.c_int64]),
+        "orc_forward_spread": (ctypes.c_int, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
+                                                   _P, ctypes.c_int, _P]),
         "orc_sample_sets": (ctypes.c_int64, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                                   ctypes.c_uint64, _P, _P, ctypes.c_int64, _P]),
         "orc_rr_single": (ctypes.c_int64, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, _P,
@@ -176,6 +178,22 @@ def lt_pick_cumulative(seed, phase, set_id, v, t) -> int:
     """In-edge index the LT walk takes at v under cumulative thresholds t (uint32 over v's in-edges), or -1."""
     t = np.ascontiguousarray(t, dtype=np.uint32)
     return int(_load().orc_lt_pick_cumulative(seed, phase, set_id, v, t.ctypes.data, len(t)))
+
+
+# ---- spread evaluation -----------------------------------------------------
+PHASE_EVAL = 65
+
+
+def forward_spread(g, model, seed, first, count, seeds, thr=None) -> np.ndarray:
+    """Spread of `seeds` in the live-edge worlds of runs [first, first+count) (uint64 per run)."""
+    off, src, t = _garr(g, thr)
+    s = np.ascontiguousarray(seeds, dtype=np.int32)
+    out = np.zeros(count, dtype=np.uint64)
+    rc = _load().orc_forward_spread(*_gargs(g, off, src, t), model, seed, first, count, s.ctypes.data, len(s),
+                                     out.ctypes.data)
+    if rc:
+        raise RuntimeError(f"orc_forward_spread failed ({rc})")
+    return out
 
 
 # ---- RR sets ---------------------------------------------------------------

@@ -41,6 +41,11 @@
  *      takes the first in-edge j with x <= t_j, and stops at v if x > t_{d-1}
  *      (the empty triggering set, of probability 1 - C_{d-1}).  Edge j has
  *      probability (t_j - t_{j-1}) / 2^32 with t_{-1} = -1.
+ *  R10 spread evaluation (the live-edge view of Section 2.2; Monte-Carlo runs
+ *      as in the paper's experiments, Section 7): run r uses the live-edge
+ *      world of phase 65 and set id r, with the coins and picks of R2, R4 and
+ *      R9.  Its spread is the number of nodes reachable from S along live
+ *      edges (S included); E[I(S)] is estimated by the mean over runs.
  *   R5 kappa in IEEE binary64 without contraction: q = 1 - w/m, r = q^k by
  *      binary exponentiation (r=1,b=q; per bit: if set r*=b; shift; if more
  *      bits b*=b), kappa = 1 - r.  kappa*2^53 is an integer; the round sum is
@@ -598,3 +603,74 @@ int64_t orc_rr_single(int64_t n, int64_t m, const int64_t *off, const int32_t *s
 }
 
 size_t orc_report_size(void) { return sizeof(orc_report); }
+
+/* ------------------------------------------------------------------------- */
+/* Spread evaluation by forward Monte-Carlo runs (reading R10).              */
+/* ------------------------------------------------------------------------- */
+
+enum { ORC_PHASE_EVAL = 65 };
+
+/* Is in-edge e of v (in-degree d, first in-edge a) live in world (seed, phase, run)? */
+static int edge_live_in_world(const orc_graph *g, int model, uint64_t seed, uint32_t phase, uint64_t run,
+                              int64_t v, int64_t a, int64_t d, int64_t e) {
+  if (model == 0) return edge_is_live(g, seed, phase, run, e, d);
+  int64_t j = g->thr ? orc_lt_pick_cumulative(seed, phase, run, v, g->thr + a, d) : orc_lt_pick(seed, phase, run, v, d);
+  return j >= 0 && a + j == e;
+}
+
+/*
+ * Runs [first, first+count): counts[i] = number of nodes reachable from the
+ * seed set in the world of run first+i.  Returns 0, or -1 on a bad seed and
+ * -2 on allocation failure.
+ */
+int orc_forward_spread(int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr, int model,
+                       uint64_t seed, uint64_t first, uint64_t count, const int32_t *seeds, int nseeds,
+                       uint64_t *counts) {
+  orc_graph g = {n, m, off, src, thr};
+  /* out-edges: for each source u, the in-edge ids e with src[e] == u */
+  int64_t *out_off = (int64_t *)calloc((size_t)n + 1, sizeof(int64_t));
+  int64_t *out_e = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+  int64_t *dst = (int64_t *)malloc(sizeof(int64_t) * (size_t)(m ? m : 1));
+  int64_t *fill = (int64_t *)malloc(sizeof(int64_t) * (size_t)n);
+  orc_ws *w = ws_new(n);
+  if (!out_off || !out_e || !dst || !fill || !w) {
+    free(out_off); free(out_e); free(dst); free(fill); ws_free(w);
+    return -2;
+  }
+  for (int64_t v = 0; v < n; ++v)
+    for (int64_t e = off[v]; e < off[v + 1]; ++e) {
+      out_off[src[e] + 1]++;
+      dst[e] = v;
+    }
+  for (int64_t u = 0; u < n; ++u) out_off[u + 1] += out_off[u];
+  for (int64_t u = 0; u < n; ++u) fill[u] = out_off[u];
+  for (int64_t e = 0; e < m; ++e) out_e[fill[src[e]]++] = e;
+  int rc = 0;
+  for (int i = 0; i < nseeds; ++i)
+    if (seeds[i] < 0 || seeds[i] >= n) rc = -1;
+  for (uint64_t r = 0; r < count && rc == 0; ++r) {
+    const uint64_t run = first + r;
+    ws_next_stamp(w);
+    int64_t len = 0;
+    for (int i = 0; i < nseeds; ++i) {
+      if (w->mark[seeds[i]] == w->stamp) continue;
+      w->mark[seeds[i]] = w->stamp;
+      w->queue[len++] = seeds[i];
+    }
+    for (int64_t head = 0; head < len; ++head) {
+      int64_t u = w->queue[head];
+      for (int64_t x = out_off[u]; x < out_off[u + 1]; ++x) {
+        int64_t e = out_e[x], v = dst[e];
+        if (w->mark[v] == w->stamp) continue;
+        int64_t a = off[v], d = off[v + 1] - a;
+        if (edge_live_in_world(&g, model, seed, ORC_PHASE_EVAL, run, v, a, d, e)) {
+          w->mark[v] = w->stamp;
+          w->queue[len++] = (int32_t)v;
+        }
+      }
+    }
+    counts[r] = (uint64_t)len;
+  }
+  free(out_off); free(out_e); free(dst); free(fill); ws_free(w);
+  return rc;
+}

@@ -672,3 +672,51 @@ def test_pipeline_is_composed_of_its_phases(model):
     seeds, gains = oracle.greedy(g.n, so, nodes, k)
     assert list(seeds) == list(r["seeds"]) and list(gains) == list(r["gains"])
     assert int(widths.sum()) == r["ns_width"] and len(nodes) == r["ns_nodes"]
+
+
+# ------------------------------------------------- forward spread (R10) --
+def _descendants(n, live_edges, seeds):
+    on = np.zeros(n, dtype=bool)
+    on[list(seeds)] = True
+    changed = True
+    while changed:
+        changed = False
+        for u, v in live_edges:
+            if on[u] and not on[v]:
+                on[v] = True
+                changed = True
+    return int(on.sum())
+
+
+@pytest.mark.parametrize("model", [IC, LT, "LT-weighted"])
+def test_forward_spread_is_reach_in_the_runs_world(model):
+    g = synth.random_small_graph(10, 30, 4)
+    thr = synth.random_thresholds(g.m, 4, choices=[0x3FFFFFFF, 0x9FFFFFFF]) if model == IC else None
+    if model == "LT-weighted":
+        model, thr = LT, synth.random_lt_thresholds(g, 4, total=0.9)
+    S = [1, 6]
+    got = oracle.forward_spread(g, model, 31, 5, 80, S, thr=thr)
+    for r in range(80):
+        want = _descendants(g.n, _live_world(g, model, 31, oracle.PHASE_EVAL, 5 + r, thr), S)
+        assert int(got[r]) == want, r
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_forward_spread_mean_matches_exact_spread(case):
+    g, model, thr = _tiny_cases()[case]
+    spreads = oracle.brute_all_spreads(g, model, thr=thr)
+    N = 40000
+    for S in [(0,), (2, 5), (1, 3, 6)]:
+        c = oracle.forward_spread(g, model, 500 + case, 0, N, list(S), thr=thr).astype(np.float64)
+        assert abs(c.mean() - spreads[_mask(S)]) <= 5 * c.std() / math.sqrt(N) + 1e-9
+
+
+def test_forward_spread_special_cases():
+    g = synth.chung_lu(400, 2000, 2.1, 9)
+    ones = np.full(g.m, 0xFFFFFFFF, dtype=np.uint32)  # p = 1: the spread is the set of descendants in G
+    el = synth.edge_list(g)
+    want = _descendants(g.n, [tuple(x) for x in el], [3, 77])
+    c = oracle.forward_spread(g, IC, 2, 0, 20, [3, 77, 3], thr=ones)  # a repeated seed counts once
+    assert np.all(c == want)
+    assert np.all(oracle.forward_spread(g, IC, 2, 0, 5, list(range(g.n))) == g.n)
+    assert np.all(oracle.forward_spread(g, LT, 2, 0, 5, []) == 0)
