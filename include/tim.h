@@ -300,6 +300,21 @@ tim_status tim_node_select(tim_ctx *ctx, const tim_graph *g, int model, uint64_t
 tim_status tim_run(tim_ctx *ctx, const tim_graph *g, int model, int k, double eps, double ell, uint64_t seed,
                    uint32_t flags, int32_t *seeds, uint64_t *gains, tim_report *rep);
 
+/* ---- spread evaluation --------------------------------------------------- */
+
+/* E[I(S)] by forward Monte-Carlo runs, as in the paper's experiments
+ * (Section 7) over the live-edge view of Section 2.2.  Run r (runs [first,
+ * first+runs)) is the live-edge world of phase 65 and set id r under the
+ * rules of the RR sets (IC coins of kind 1 against the thresholds; LT picks of
+ * kind 2, with the graph's in-weights if set); its spread is the number of
+ * nodes reachable from seeds[0..nseeds) (host int32, repeats allowed) along
+ * live edges.  d_counts (device uint32[runs], nullable) receives each run's
+ * spread, *total (host, nullable) their sum and *mean (host, nullable) the
+ * estimate total / runs.  The first call on a graph builds its out-edge lists
+ * (8(n+1) + 8m bytes, freed with the graph). */
+tim_status tim_spread_mc(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, uint64_t first, uint64_t runs,
+                         const int32_t *seeds, int nseeds, uint32_t *d_counts, double *mean, uint64_t *total);
+
 /* ---- batches of queries -------------------------------------------------- */
 
 /* One TIM / TIM+ query of a batch: tim_run's arguments and results. */

@@ -29,7 +29,7 @@ EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_devi
             "tim_graph_upload", "tim_graph_set_lt_weights",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
-            "tim_profile_read", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
+            "tim_profile_read", "tim_spread_mc", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
             "tim_server_stop")
 
 U64, I64, U32, I32, DBL, P = (ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
@@ -136,6 +136,8 @@ def load_library():
                                    ctypes.POINTER(Report)]),
         "tim_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "tim_profile_read": (ctypes.c_int, [P, ctypes.POINTER(Profile)]),
+        "tim_spread_mc": (ctypes.c_int, [P, P, ctypes.c_int, U64, U64, U64, P, ctypes.c_int, P,
+                                         ctypes.POINTER(DBL), ctypes.POINTER(U64)]),
         "tim_run_batch": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(BatchInfo)]),
         "tim_server_start": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(P)]),
@@ -330,6 +332,21 @@ class Engine:
         _check(self.lib.tim_run(self.ctx, g.handle, model, k, eps, ell, seed, flags, seeds.ctypes.data,
                                 gains.ctypes.data, ctypes.byref(rep)))
         return seeds, gains, rep
+
+    def spread(self, g: DeviceGraph, model: int, seed: int, seeds, runs: int, first: int = 0,
+               per_run: bool = False):
+        """E[I(S)] by forward Monte-Carlo runs: (mean, total[, spreads per run as a uint32 tensor])."""
+        torch = self._torch
+        s = np.ascontiguousarray(seeds, dtype=np.int32)
+        counts = torch.empty(max(runs, 1), dtype=torch.int32, device=torch.device("cuda", self.device)) \
+            if per_run else None
+        mean, total = DBL(0.0), U64(0)
+        self._sync_torch()
+        _check(self.lib.tim_spread_mc(self.ctx, g.handle, model, seed, first, runs, _np_ptr(s) if len(s) else None,
+                                      len(s), _dev_ptr(counts), ctypes.byref(mean), ctypes.byref(total)))
+        if per_run:
+            return mean.value, int(total.value), counts[:runs]
+        return mean.value, int(total.value)
 
     def serve(self, slots: int) -> "Server":
         """Starts a request loop with `slots` queries at a time (upload the graphs first)."""

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libtim.so")
-SOURCES = ["csrc/sample.hip", "csrc/coverage.hip", "csrc/api.cpp"]
+SOURCES = ["csrc/sample.hip", "csrc/coverage.hip", "csrc/spread.hip", "csrc/api.cpp"]
 
 
 def hipcc() -> str:

@@ -125,6 +125,10 @@ struct tim_graph {
   int32_t* src = nullptr;
   uint32_t* thr = nullptr;
   uint32_t* lthr = nullptr;  // LT cumulative in-weight thresholds, or nullptr (1/indeg)
+  // out-edge lists for the spread evaluator, built on first use
+  int64_t* out_off = nullptr;
+  int32_t* out_dst = nullptr;
+  uint32_t* out_eid = nullptr;
 };
 
 namespace {
@@ -1090,6 +1094,46 @@ tim_status run_impl(tim_ctx* c, const tim_graph* g, int model, int k, double eps
   return st;
 }
 
+// Out-edge lists of g (counting sort of its in-edges by source), kept with the
+// graph: 8(n+1) + 8m bytes.
+tim_status ensure_out_csr(tim_ctx* c, tim_graph* g) {
+  if (g->out_off) return TIM_OK;
+  const int64_t n = g->n, m = g->m;
+  int64_t* off = nullptr;
+  int32_t* dst = nullptr;
+  uint32_t* eid = nullptr;
+  if (hipMalloc(&off, (size_t)(n + 1) * 8) != hipSuccess || hipMalloc(&dst, (size_t)m * 4) != hipSuccess ||
+      hipMalloc(&eid, (size_t)m * 4) != hipSuccess) {
+    if (off) (void)hipFree(off);
+    if (dst) (void)hipFree(dst);
+    return fail(TIM_ENOMEM, "out-edge lists: hipMalloc failed");
+  }
+  tim_status st = ensure(c, c->cnt, (size_t)n * 4, "out-degree counts");
+  if (st == TIM_OK) st = ensure(c, c->fill, (size_t)n * 4, "out-list cursors");
+  if (st == TIM_OK) st = ensure(c, c->scan_tmp, tim::scan_temp_bytes((uint64_t)n + 1), "scan");
+  if (st != TIM_OK) {
+    (void)hipFree(off);
+    (void)hipFree(dst);
+    (void)hipFree(eid);
+    return st;
+  }
+  tim::launch_zero_counts(c->cnt.as<uint32_t>(), n, c->stream);
+  tim::launch_zero_counts(c->fill.as<uint32_t>(), n, c->stream);
+  tim::launch_out_csr_count(g->src, m, c->cnt.as<uint32_t>(), c->stream);
+  tim::launch_scan_u32_to_i64(c->cnt.as<uint32_t>(), off, (uint64_t)n, c->scan_tmp.p, c->stream);
+  tim::launch_out_csr_scatter(g->off, g->src, n, m, off, c->fill.as<uint32_t>(), dst, eid, c->stream);
+  if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+    (void)hipFree(off);
+    (void)hipFree(dst);
+    (void)hipFree(eid);
+    return fail(TIM_EDEVICE, "building the out-edge lists failed");
+  }
+  g->out_off = off;
+  g->out_dst = dst;
+  g->out_eid = eid;
+  return TIM_OK;
+}
+
 tim_status check_run_args(const tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell,
                           const int32_t* seeds) {
   TIM_TRY(check_phase_args(c, g, model, k));
@@ -1578,6 +1622,9 @@ void tim_graph_free(tim_graph* g) {
   if (g->src) (void)hipFree(g->src);
   if (g->thr) (void)hipFree(g->thr);
   if (g->lthr) (void)hipFree(g->lthr);
+  if (g->out_off) (void)hipFree(g->out_off);
+  if (g->out_dst) (void)hipFree(g->out_dst);
+  if (g->out_eid) (void)hipFree(g->out_eid);
   delete g;
 }
 
@@ -1733,6 +1780,54 @@ tim_status tim_node_select(tim_ctx* c, const tim_graph* g, int model, uint64_t s
   if (!seeds) return fail(TIM_EINVAL, "seeds is null");
   HIP_TRY(hipSetDevice(c->device));
   return node_select_impl(c, g, model, seed, k, theta, theta * 16, seeds, gains, out, nullptr);
+}
+
+tim_status tim_spread_mc(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint64_t first, uint64_t runs,
+                         const int32_t* seeds, int nseeds, uint32_t* d_counts, double* mean, uint64_t* total) {
+  TIM_TRY(check_phase_args(c, g, model, 1));
+  if (c->serving) return fail(TIM_EINVAL, "a server runs on this context");
+  if (nseeds < 0 || (nseeds > 0 && !seeds)) return fail(TIM_EINVAL, "bad seed list");
+  for (int i = 0; i < nseeds; ++i)
+    if (seeds[i] < 0 || seeds[i] >= g->n) return fail(TIM_EINVAL, "seed %d outside [0, n)", seeds[i]);
+  HIP_TRY(hipSetDevice(c->device));
+  tim_graph* gm = const_cast<tim_graph*>(g);  // the out-edge lists are a cache of the graph
+  TIM_TRY(ensure_out_csr(c, gm));
+  TIM_TRY(ensure_big(c, g->n));
+  TIM_TRY(ensure(c, c->rr_nodes, (size_t)std::max(nseeds, 1) * 4, "seed list"));
+  if (nseeds)
+    HIP_TRY(hipMemcpyAsync(c->rr_nodes.p, seeds, (size_t)nseeds * 4, hipMemcpyHostToDevice, c->stream));
+  tim::SpreadArgs a;
+  memset(&a, 0, sizeof(a));
+  a.g.off = g->off;
+  a.g.src = g->src;
+  a.g.thr = model == TIM_MODEL_IC ? g->thr : nullptr;
+  a.g.lthr = model == TIM_MODEL_LT ? g->lthr : nullptr;
+  a.g.n = g->n;
+  a.g.m = g->m;
+  a.out_off = gm->out_off;
+  a.out_dst = gm->out_dst;
+  a.out_eid = gm->out_eid;
+  a.seed = seed;
+  a.first = first;
+  a.runs = runs;
+  a.seeds = c->rr_nodes.as<int32_t>();
+  a.nseeds = nseeds;
+  a.counts = d_counts;
+  a.ctr = c->ctr;
+  a.stamp = c->big_stamp.as<uint32_t>();
+  a.queue = c->big_queue.as<int32_t>();
+  a.epoch = c->big_epoch.as<uint32_t>();
+  a.stride = (uint64_t)c->big_n;
+  a.slots = c->big_slots;
+  tim::launch_clear_counters(c->ctr, c->stream);
+  if (runs) tim::launch_spread(model, a, c->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(c->ctr_host, c->ctr, 2 * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  const uint64_t sum = c->ctr_host[1];
+  if (total) *total = sum;
+  if (mean) *mean = runs ? (double)sum / (double)runs : 0.0;
+  return TIM_OK;
 }
 
 tim_status tim_run(tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell, uint64_t seed,

@@ -122,6 +122,29 @@ void launch_clear_counters_batch(const JobTable& t, hipStream_t s);
 void launch_sample_batch(int model, int mode, bool wc, const JobTable& t, int grid0, int grid1, int slots,
                          uint64_t max_count, hipStream_t s, hipEvent_t after_tier0);
 
+// ---- spread.hip ----
+// Forward Monte-Carlo runs [first, first+runs) of phase 65 from a seed set.
+struct SpreadArgs {
+  GraphView g;                // in-CSR (coins, thresholds, LT picks)
+  const int64_t* out_off;     // n+1
+  const int32_t* out_dst;     // m: head of each out-edge
+  const uint32_t* out_eid;    // m: its in-CSR edge id
+  uint64_t seed, first, runs;
+  const int32_t* seeds;       // nseeds node ids (repeats allowed)
+  int nseeds;
+  uint32_t* counts;           // per run, nullable
+  unsigned long long* ctr;    // [0] run cursor, [1] sum of the runs' spreads (cleared by the caller)
+  uint32_t* stamp;            // per slot: n stamps and an n-entry queue, stride entries apart
+  int32_t* queue;
+  uint32_t* epoch;
+  uint64_t stride;
+  int slots;
+};
+void launch_out_csr_count(const int32_t* src, int64_t m, uint32_t* cnt, hipStream_t s);
+void launch_out_csr_scatter(const int64_t* in_off, const int32_t* src, int64_t n, int64_t m, const int64_t* out_off,
+                            uint32_t* fill, int32_t* out_dst, uint32_t* out_eid, hipStream_t s);
+void launch_spread(int model, const SpreadArgs& a, hipStream_t s);
+
 // ---- coverage.hip ----
 // out[0..len] = exclusive prefix sums of in[0..len), out[len] = total.
 size_t scan_temp_bytes(uint64_t len);

@@ -28,6 +28,7 @@
 #include <stdlib.h>
 
 #include "engine.hpp"
+#include "pick.hpp"
 #include "rng.hpp"
 
 namespace tim {
@@ -102,17 +103,6 @@ __device__ __forceinline__ bool in_seed(const uint32_t* bits, int32_t u) {
   return (bits[(uint32_t)u >> 5] >> ((uint32_t)u & 31u)) & 1u;
 }
 
-// Edge e of an in-list of length d decided by word x: live iff x <= t(e).
-template <bool WC>
-__device__ __forceinline__ bool edge_live(uint32_t x, uint32_t t, int64_t d) {
-  if (WC) {
-    // t = floor(2^32/d) - 1, and x <= t  <=>  (x + 1) * d <= 2^32
-    return (uint64_t)((uint64_t)x + 1ull) * (uint64_t)d <= (1ull << 32);
-  } else {
-    return x <= t;
-  }
-}
-
 // Open addressing in LDS over 2^HLOG slots, key u+1 (0 = empty).
 // Returns 1: inserted, 0: already present, -1: table full.
 template <int HLOG>
@@ -131,26 +121,6 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
     pos = (pos + 1u) & (H - 1u);
   }
   return -1;
-}
-
-// The in-edge an LT walk takes at v (in-degree d >= 1, first in-edge ea), or
-// -1 if it stops there.  With 1/indeg weights: in-edge floor(X64 * d / 2^64).
-// With cumulative thresholds t (Section 7.1's normalized random weights): the
-// first in-edge j with word0 <= t_j, found by binary search over v's list; the
-// walk stops if word0 exceeds t_{d-1} (weights summing below 1).
-__device__ __forceinline__ int64_t lt_pick_edge(const GraphView& g, const Key& key, const SetStream& st, int32_t v,
-                                                int64_t ea, int64_t d) {
-  const uint4 x = draw(key, st, kKindPick, (uint64_t)v);
-  if (!g.lthr) return ea + (int64_t)scale64(x, (uint64_t)d);
-  const uint32_t* t = g.lthr + ea;
-  if (x.x > t[d - 1]) return -1;
-  int64_t lo = 0, hi = d - 1;
-  while (lo < hi) {
-    const int64_t mid = (lo + hi) >> 1;
-    if (x.x <= t[mid]) hi = mid;
-    else lo = mid + 1;
-  }
-  return ea + lo;
 }
 
 // One bit of a 64-bit membership signature: a clear bit proves absence.
