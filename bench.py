@@ -30,6 +30,11 @@ Poisson process at 1, 5, 20, 50 and 200 per second; each rate reports p50 and
 p99 latency (submission to result) and the queries per second completed.
 value is the rate sustained at 200 arrivals per second; the same queries run
 one by one (tim_run) give the plain rate, and must give the same results.
+
+--workload sweep: quality and time of TIM and TIM+ on the 1M-node graph
+(IC with p = 1/indeg, and LT), a k sweep (eps = 0.2) and an eps sweep
+(k = 50): TIM+ and TIM seconds, theta, KPT*, KPT+ and their ratio, and the
+expected spread of the seeds by 10^4 forward Monte-Carlo runs (tim_spread_mc).
 """
 import argparse
 import json
@@ -89,7 +94,8 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
-    ap.add_argument("--workload", choices=("timplus", "batch64", "serve"), default="timplus")
+    ap.add_argument("--workload", choices=("timplus", "batch64", "serve", "sweep"), default="timplus")
+    ap.add_argument("--mc-runs", type=int, default=10_000, help="forward Monte-Carlo runs per seed set (sweep)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -101,6 +107,8 @@ def main():
         return batch_main(args)
     if args.workload == "serve":
         return serve_main(args)
+    if args.workload == "sweep":
+        return sweep_main(args)
 
     import torch
 
@@ -412,6 +420,61 @@ def serve_main(args):
         "identical_outputs": identical,
     }
     eng.close()
+    print(json.dumps(line), flush=True)
+
+
+def sweep_main(args):
+    import math
+
+    import paper_1404_0900_amd as tim
+    import synth
+
+    log("generating the 1M-node / 10M-edge Chung-Lu graph")
+    g = synth.config_graph("cfg2")
+    eng = tim.Engine(0)
+    dg = eng.upload(g)
+    for model in (tim.IC, tim.LT):  # warm-up
+        eng.run(dg, model, 10, 0.5, ELL, SEED)
+        eng.spread(dg, model, SEED, [0], 10)
+    points = [("k", k, 0.2) for k in (1, 10, 20, 30, 40, 50)] + [("eps", 50, e) for e in (0.1, 0.2, 0.3, 0.5)]
+    rows = []
+    for model in (tim.IC, tim.LT):
+        for sweep, k, eps in points:
+            t0 = time.perf_counter()
+            seeds, gains, rep = eng.run(dg, model, k, eps, ELL, SEED)
+            t_plus = time.perf_counter() - t0
+            plain = eps >= 0.2  # TIM at eps = 0.1 needs billions of sets here (theta = lambda / KPT*)
+            if plain:
+                t0 = time.perf_counter()
+                seeds_p, _, rep_p = eng.run(dg, model, k, eps, ELL, SEED, tim.FLAG_PLAIN)
+                t_plain = time.perf_counter() - t0
+            t0 = time.perf_counter()
+            spread, _ = eng.spread(dg, model, SEED + 1, seeds, args.mc_runs)
+            spread_p = eng.spread(dg, model, SEED + 1, seeds_p, args.mc_runs)[0] if plain else None
+            t_mc = time.perf_counter() - t0
+            row = {"model": "IC" if model == tim.IC else "LT", "sweep": sweep, "k": k, "eps": eps,
+                   "tim_plus_s": round(t_plus, 5), "tim_s": round(t_plain, 5) if plain else None,
+                   "theta_plus": int(rep.select.theta),
+                   "theta_tim": int(rep_p.select.theta) if plain else int(math.ceil(rep.lambda_ / rep.kpt.kpt_star)),
+                   "kpt_star": round(rep.kpt.kpt_star, 3), "kpt_plus": round(rep.refine.kpt_plus, 3),
+                   "kpt_ratio": round(rep.refine.kpt_plus / rep.kpt.kpt_star, 3),
+                   "spread_plus": round(spread, 2), "spread_tim": round(spread_p, 2) if plain else None,
+                   "mc_runs": args.mc_runs, "mc_s": round(t_mc, 3)}
+            rows.append(row)
+            log(f"{row}")
+    eng.close()
+    line = {
+        "metric": "TIM/TIM+ quality and time sweeps (1 GPU, 1M-node Chung-Lu): seconds, theta, KPT+/KPT*, E[I(S)]",
+        "value": round(sum(r["tim_plus_s"] for r in rows), 5),
+        "unit": "s (sum of TIM+ runs over the sweep)",
+        "n_gpus": 1, "steps": len(rows), "warmup": 1,
+        "ms_per_step": round(1e3 * sum(r["tim_plus_s"] for r in rows) / len(rows), 3),
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u32/u64 integer, f64 kappa", "data": "synthetic (seeded directed Chung-Lu, alpha=2.1)",
+        "config": {"workload": "sweep_chunglu_n1e6_m1e7", "n": g.n, "m": g.m, "ell": ELL, "seed": SEED,
+                   "mc_runs": args.mc_runs},
+        "rows": rows,
+    }
     print(json.dumps(line), flush=True)
 
 

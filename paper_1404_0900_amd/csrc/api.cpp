@@ -154,6 +154,7 @@ tim_status ensure(tim_ctx* c, DevBuf& b, size_t bytes, const char* what) {
   b.bytes = 0;
   if (hipMalloc(&b.p, want) != hipSuccess) {
     b.p = nullptr;
+    (void)hipGetLastError();  // the failed allocation is reported here, not by the next launch check
     return fail(TIM_ENOMEM, "hipMalloc of %zu bytes for %s failed", want, what);
   }
   b.bytes = want;
@@ -688,20 +689,35 @@ tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t
   if (count <= c->resident_limit && resident_bytes(c, n, model, count, expect_nodes, k) <= room) {
     // the sets stay in the node pool as the samplers left them (no compaction)
     Totals t;
-    TIM_TRY(emit_sets(c, g, model, seed, phase, 0, count, expect_nodes, nullptr, &t));
-    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
-    st->ms_sample = elapsed_ms(c);
+    tim_status s0 = emit_sets(c, g, model, seed, phase, 0, count, expect_nodes, nullptr, &t);
+    if (s0 == TIM_OK) {
+      // the estimate was ahead of the sets: their actual size decides whether the index fits too
+      expect_nodes = std::max(expect_nodes, t.nodes);
+      uint64_t room2 = 0;  // counts the buffers the context already holds as usable
+      TIM_TRY(collection_room(c, &room2));
+      if (resident_bytes(c, n, model, count, t.nodes, k) <= room2) {
+        HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+        st->ms_sample = elapsed_ms(c);
+        HIP_TRY(hipEventRecord(c->ev[0], c->stream));
+        s0 = greedy(c, n, count, nullptr, c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
+                    c->pool.as<int32_t>(), t.nodes, k, seeds, gains);
+        if (s0 == TIM_OK) {
+          HIP_TRY(hipEventRecord(c->ev[1], c->stream));
+          st->ms_greedy = elapsed_ms(c);
+          st->nodes = t.nodes;
+          st->width = t.width;
+          st->resident = count;
+          st->store_bytes = c->pool.bytes + c->set_start.bytes + c->set_len.bytes +
+                            (k > 1 ? c->inv_sets.bytes + c->inv_off.bytes : 0);
+          return TIM_OK;
+        }
+      } else {
+        s0 = TIM_EBUDGET;
+      }
+    }
+    // out of device memory on the way: the chunked plan below regenerates instead
+    if (s0 != TIM_ENOMEM && s0 != TIM_EBUDGET) return s0;
     HIP_TRY(hipEventRecord(c->ev[0], c->stream));
-    TIM_TRY(greedy(c, n, count, nullptr, c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
-                   c->pool.as<int32_t>(), t.nodes, k, seeds, gains));
-    HIP_TRY(hipEventRecord(c->ev[1], c->stream));
-    st->ms_greedy = elapsed_ms(c);
-    st->nodes = t.nodes;
-    st->width = t.width;
-    st->resident = count;
-    st->store_bytes = c->pool.bytes + c->set_start.bytes + c->set_len.bytes +
-                      (k > 1 ? c->inv_sets.bytes + c->inv_off.bytes : 0);
-    return TIM_OK;
   }
 
   // ---- plan: a chunk size for the regenerated part, then the resident prefix
