@@ -17,9 +17,10 @@ enum SampleMode : int {
 // Device counters of one sampling launch (zeroed before it).  Sets flow
 // through up to three tiers: tier 0 takes the launch's range of set ids and
 // hands sets that outgrow its on-chip structures to list 1; tier 1 (IC only)
-// takes list 1 and hands the rest to list 2; the last tier (device-memory
-// visited stamps) finishes list 2 (IC) or list 1 (LT).  Each tier has its own
-// block of accumulators at kCtrAcc + kAccStride * tier.
+// takes list 1 and hands the rest to list 2; the last tier finishes list 2
+// (IC: device-memory visited stamps) or list 1 (LT: the stamp-free chain
+// tier).  Each tier has its own block of accumulators at kCtrAcc +
+// kAccStride * tier.
 enum Counter : int {
   kCtrNext0 = 0,       // tier-0 cursor over the range
   kCtrList1 = 1,       // length of list 1

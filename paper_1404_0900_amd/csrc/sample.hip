@@ -16,9 +16,10 @@
 // capacity; the last tier is a 256-thread block per set with visited stamps
 // and a queue of n entries in device memory.
 //
-// LT (one live in-edge per node): each lane walks one set's chain, kept in LDS
-// with a 64-bit membership signature in a register; longer chains go to the
-// last tier (one lane per set, stamps in device memory).
+// LT (at most one live in-edge per node): each lane walks one set's chain,
+// kept in LDS with a 64-bit membership signature in a register; longer chains
+// go to the last tier, one lane per chain without visited marks (Brent's
+// cycle search over the walk, which is a fixed function of the set's keys).
 //
 // Every launch also reduces what the phase needs: the widths (Equation (1)),
 // the set sizes, the number of sets meeting a seed set (Algorithm 3, line 10)
