@@ -101,6 +101,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--workload", choices=("timplus", "batch64", "serve", "sweep"), default="timplus")
     ap.add_argument("--mc-runs", type=int, default=10_000, help="forward Monte-Carlo runs per seed set (sweep)")
+    ap.add_argument("--rates", type=str, default="1,5,20,50,200", help="arrival rates per second (serve)")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -376,7 +377,7 @@ def serve_main(args):
 
     serve(synth.serve_queries(16, 200.0, 98))  # warm-up: member contexts and their buffers
     sweep, last = [], None
-    for idx, rate in enumerate((1.0, 5.0, 20.0, 50.0, 200.0)):
+    for idx, rate in enumerate(float(r) for r in args.rates.split(",")):
         count = int(min(60, max(10, rate * 10)))
         qs = synth.serve_queries(count, rate, 7 + idx)
         res, info = serve(qs)
