@@ -76,12 +76,13 @@ def sources_sha():
     return h.hexdigest()[:16]
 
 
-def kernel_name(model, mode):
+def kernel_name(model, mode, lanes=None):
     """Tier-0 sampler kernel of (model, mode) as rocprofv3 lists it (template arguments: mode, WC, lanes per set,
     queue length, log2 of the hash size, group limit, groups per lane)."""
     if model == 1:
         return f"lt_lane_kernel<{mode}> ({MODES[mode]})"
-    lanes = int(os.environ.get("TIM_IC_SEG_LANES", "8"))
+    if lanes is None:
+        lanes = int(os.environ.get("TIM_IC_SEG_LANES", "8"))
     lanes = lanes if lanes in (4, 8, 16, 32, 64) else 8
     q = {4: 64, 8: 128, 16: 128, 32: 256, 64: 512}[lanes]
     hlog = {4: 0, 8: 0, 16: 8, 32: 9, 64: 10}[lanes]
@@ -126,6 +127,8 @@ def main():
     eng = tim.Engine(0)
     dg = eng.upload(g)
     log(f"graph resident: n={g.n} m={g.m}")
+    tune = eng.autotune(dg, tim.IC, 1 << 20)  # the sampler shapes for this graph, before timing
+    log(f"autotune: {tune.seg_lanes} lanes per set, slice cap {tune.slice_cap}")
 
     def step():
         out = []
@@ -162,11 +165,14 @@ def main():
     eng.profile(False)
 
     # dominant sampler kernel: the one with the most GPU time in the timed steps
+    def name_of(model, mode):
+        return kernel_name(model, mode, tune.seg_lanes)
+
     def traffic_of(model, mode):
-        if kernel_name(model, mode) == TRAFFIC["kernel"] and sources_sha() == TRAFFIC["sources_sha256_16"]:
+        if name_of(model, mode) == TRAFFIC["kernel"] and sources_sha() == TRAFFIC["sources_sha256_16"]:
             return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
         return None
-    roofline = dominant_roofline(prof, kernel_name, traffic_of)
+    roofline = dominant_roofline(prof, name_of, traffic_of)
     sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
 
     line = {
@@ -191,6 +197,9 @@ def main():
         "sampler_gpu_ms_per_step": round(sampler_ms / args.steps, 3),
         "index_greedy_gpu_ms_per_step": round((prof.index_ms + prof.greedy_ms) / args.steps, 3),
         "roofline": roofline,
+        "autotune": {"seg_lanes": int(tune.seg_lanes), "slice_cap": int(tune.slice_cap),
+                     "ms_width_4_8_16_32_64": [round(x, 3) for x in tune.ms_width],
+                     "ms_emit_512_1024_2048_4096": [round(x, 3) for x in tune.ms_emit]},
     }
 
     # the same TIM+ runs under LT (one uniform in-edge per node), outside the timed steps

@@ -172,6 +172,29 @@ uint64_t tim_ctx_device_bytes(const tim_ctx *ctx);
  * it. */
 tim_status tim_set_resident_limit(tim_ctx *ctx, uint64_t max_sets);
 
+/* ---- tuning -------------------------------------------------------------- */
+
+/* What tim_autotune measured and chose. */
+typedef struct {
+  int32_t seg_lanes;   /* lanes per IC set in the first sampler tier: 4, 8, 16, 32 or 64 (with it come
+                          the sizes a set may reach before a later tier takes it: a 64/128/128/256/512-
+                          node queue and 256/512/512/1024/2048 four-edge groups) */
+  uint32_t slice_cap;  /* largest node-pool slice a wavefront reserves when storing sets */
+  double ms_width[5];  /* IC: one width-mode launch of `sets` sets with 4, 8, 16, 32, 64 lanes (0 for LT) */
+  double ms_emit[4];   /* one stored-set launch with slice caps 512, 1024, 2048, 4096 */
+} tim_tune_result;
+
+/* Times the context's sampler shapes on graph g and keeps the fastest for
+ * the context's later calls: first the IC first-tier lanes per set (the
+ * wave-per-set thresholds; width mode, as the KptEstimation rounds run),
+ * then the node-pool slice size (stored sets, as RefineKPT and
+ * NodeSelection run).  Each candidate runs `sets` sets (phase 66, a fixed
+ * seed; the sets are dropped) once untimed and three times timed; the best
+ * wall time wins if it beats the current shape by 3% or more (else the
+ * current one stays).  Results of every call do not depend on these shapes.
+ * Requires 4096 <= sets <= 2^26.  out (host) may be NULL. */
+tim_status tim_autotune(tim_ctx *ctx, const tim_graph *g, int model, uint64_t sets, tim_tune_result *out);
+
 /* ---- profile ------------------------------------------------------------ */
 
 /* Work and GPU time of one sampler kernel (one model, one mode), summed over

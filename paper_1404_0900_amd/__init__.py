@@ -29,7 +29,7 @@ EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_devi
             "tim_graph_upload", "tim_graph_set_lt_weights",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
-            "tim_profile_read", "tim_spread_mc", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
+            "tim_profile_read", "tim_autotune", "tim_spread_mc", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
             "tim_server_stop")
 
 U64, I64, U32, I32, DBL, P = (ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
@@ -75,6 +75,10 @@ class Report(ctypes.Structure):
                 ("select", SelectResult), ("s_prime", I32 * 128),
                 ("ms_kpt", DBL), ("ms_refine", DBL), ("ms_select_sample", DBL), ("ms_select_index", DBL),
                 ("ms_select_greedy", DBL), ("ms_total", DBL), ("sets_total", U64), ("width_total", U64)]
+
+
+class TuneResult(ctypes.Structure):
+    _fields_ = [("seg_lanes", I32), ("slice_cap", U32), ("ms_width", DBL * 5), ("ms_emit", DBL * 4)]
 
 
 class KernelProfile(ctypes.Structure):
@@ -136,6 +140,7 @@ def load_library():
                                    ctypes.POINTER(Report)]),
         "tim_profile_enable": (ctypes.c_int, [P, ctypes.c_int]),
         "tim_profile_read": (ctypes.c_int, [P, ctypes.POINTER(Profile)]),
+        "tim_autotune": (ctypes.c_int, [P, P, ctypes.c_int, U64, ctypes.POINTER(TuneResult)]),
         "tim_spread_mc": (ctypes.c_int, [P, P, ctypes.c_int, U64, U64, U64, P, ctypes.c_int, P,
                                          ctypes.POINTER(DBL), ctypes.POINTER(U64)]),
         "tim_run_batch": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.c_int, ctypes.c_int,
@@ -332,6 +337,12 @@ class Engine:
         _check(self.lib.tim_run(self.ctx, g.handle, model, k, eps, ell, seed, flags, seeds.ctypes.data,
                                 gains.ctypes.data, ctypes.byref(rep)))
         return seeds, gains, rep
+
+    def autotune(self, g: DeviceGraph, model: int, sets: int = 1 << 20) -> TuneResult:
+        """Times the sampler shapes on g and keeps the fastest for this engine (results do not change)."""
+        out = TuneResult()
+        _check(self.lib.tim_autotune(self.ctx, g.handle, model, sets, ctypes.byref(out)))
+        return out
 
     def spread(self, g: DeviceGraph, model: int, seed: int, seeds, runs: int, first: int = 0,
                per_run: bool = False):

@@ -79,6 +79,7 @@ struct tim_ctx {
   int num_cu = 0;
   int seg_lanes = 8;
   uint32_t slice_cap = tim::kPoolChunk;  // largest node-pool slice of a wavefront
+  uint32_t slice_cap_set = tim::kPoolChunk;  // its value outside the chunked plan (tim_autotune may change it)
   uint32_t emit_wave_sets = 0;           // emit launches: at least this many sets per tier-0 wavefront
   uint32_t slice = tim::kPoolChunk;      // slice of the current emit launches
   uint64_t resident_limit = ~0ull;       // most sets a greedy keeps resident
@@ -726,7 +727,7 @@ tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t
   struct SliceScope {
     tim_ctx* c;
     ~SliceScope() {
-      c->slice_cap = tim::kPoolChunk;
+      c->slice_cap = c->slice_cap_set;
       c->emit_wave_sets = 0;
     }
   } scope{c};
@@ -1148,6 +1149,12 @@ tim_status ensure_out_csr(tim_ctx* c, tim_graph* g) {
   g->out_dst = dst;
   g->out_eid = eid;
   return TIM_OK;
+}
+
+void set_seg_lanes(tim_ctx* c, int lanes) {
+  c->seg_lanes = lanes;
+  for (int mode = 0; mode < 3; ++mode)
+    for (int wc = 0; wc < 2; ++wc) c->grid_ic[mode][wc] = tim::ic_blocks_per_cu(mode, wc != 0, lanes);
 }
 
 tim_status check_run_args(const tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell,
@@ -1796,6 +1803,92 @@ tim_status tim_node_select(tim_ctx* c, const tim_graph* g, int model, uint64_t s
   if (!seeds) return fail(TIM_EINVAL, "seeds is null");
   HIP_TRY(hipSetDevice(c->device));
   return node_select_impl(c, g, model, seed, k, theta, theta * 16, seeds, gains, out, nullptr);
+}
+
+tim_status tim_autotune(tim_ctx* c, const tim_graph* g, int model, uint64_t sets, tim_tune_result* out) {
+  TIM_TRY(check_phase_args(c, g, model, 1));
+  if (c->hub || c->serving) return fail(TIM_EINVAL, "context is a batch member or runs a server");
+  if (sets < 4096 || sets > kMaxLaunchSets) return fail(TIM_EINVAL, "sets must lie in [4096, 2^26]");
+  HIP_TRY(hipSetDevice(c->device));
+  tim_tune_result r;
+  memset(&r, 0, sizeof(r));
+  c->stored.valid = false;
+  const uint64_t seed = 0x74756e65ull;  // the tuning sets are timed and dropped
+  const uint32_t phase = 66;
+  // best of three timed launches after one untimed; a failing launch leaves its status in st
+  tim_status st = TIM_OK;
+  auto best_ms = [&](auto&& launch) -> double {
+    double best = 1e300;
+    for (int trial = 0; trial < 4; ++trial) {
+      const auto t0 = std::chrono::steady_clock::now();
+      st = launch();
+      if (st != TIM_OK) return -1.0;
+      const double ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+      if (trial > 0) best = std::min(best, ms);
+    }
+    return best;
+  };
+  // a candidate replaces the current shape only if it is at least 3% faster (timing noise)
+  const double kGain = 0.97;
+  uint64_t nodes = 0;
+  if (model == TIM_MODEL_IC) {
+    static const int lanes[5] = {4, 8, 16, 32, 64};
+    const int cur_lanes = c->seg_lanes;
+    int best_lanes = cur_lanes;
+    double best = 1e300, cur = 1e300;
+    for (int i = 0; i < 5; ++i) {
+      set_seg_lanes(c, lanes[i]);
+      Totals t;
+      const double ms = best_ms([&] {
+        t = Totals();
+        return sample_counts(c, g, model, tim::kModeWidth, seed, phase, 0, sets, 1, nullptr, nullptr, &t);
+      });
+      if (ms < 0) {
+        set_seg_lanes(c, best_lanes);
+        return st;
+      }
+      r.ms_width[i] = ms;
+      nodes = t.nodes;
+      if (lanes[i] == cur_lanes) cur = ms;
+      if (ms < best) {
+        best = ms;
+        best_lanes = lanes[i];
+      }
+    }
+    set_seg_lanes(c, best < kGain * cur ? best_lanes : cur_lanes);
+  } else {
+    Totals t;
+    TIM_TRY(sample_counts(c, g, model, tim::kModeWidth, seed, phase, 0, sets, 1, nullptr, nullptr, &t));
+    nodes = t.nodes;
+  }
+  static const uint32_t slices[4] = {512, 1024, 2048, 4096};
+  const uint32_t cur_slice = c->slice_cap_set;
+  uint32_t best_slice = cur_slice;
+  double best = 1e300, cur = 1e300;
+  for (int i = 0; i < 4; ++i) {
+    c->slice_cap = slices[i];
+    const double ms = best_ms([&] {
+      Totals t;
+      return emit_sets(c, g, model, seed, phase, 0, sets, nodes + nodes / 4 + 4096, nullptr, &t);
+    });
+    if (ms < 0) {
+      c->slice_cap = c->slice_cap_set;
+      return st;
+    }
+    r.ms_emit[i] = ms;
+    if (slices[i] == cur_slice) cur = ms;
+    if (ms < best) {
+      best = ms;
+      best_slice = slices[i];
+    }
+  }
+  if (!(best < kGain * cur)) best_slice = cur_slice;
+  c->slice_cap = c->slice_cap_set = best_slice;
+  c->stored.valid = false;
+  r.seg_lanes = c->seg_lanes;
+  r.slice_cap = best_slice;
+  if (out) *out = r;
+  return TIM_OK;
 }
 
 tim_status tim_spread_mc(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint64_t first, uint64_t runs,
