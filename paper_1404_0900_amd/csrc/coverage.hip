@@ -578,11 +578,13 @@ void launch_argmax_step(const GreedyArgs& a, int j, hipStream_t s) {
 
 void launch_cover_step(const GreedyArgs& a, int j, hipStream_t s) {
   if (!a.nsets) return;
+  // the chosen node's list holds at most nsets sets: no more blocks than its tiles
+  const dim3 grid((unsigned)std::min<uint64_t>(1024, (a.nsets + kTileSets - 1) / kTileSets));
   if (a.set_off)
-    hipLaunchKernelGGL(cover_kernel<CsrSets>, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
+    hipLaunchKernelGGL(cover_kernel<CsrSets>, grid, dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
                        csr_of(a), a.covered, a.selected, a.cnt);
   else
-    hipLaunchKernelGGL(cover_kernel<PoolSets>, dim3(1024), dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
+    hipLaunchKernelGGL(cover_kernel<PoolSets>, grid, dim3(kThreads), 0, s, a.best + j, a.inv_off, a.inv_sets,
                        pool_of(a), a.covered, a.selected, a.cnt);
 }
 
