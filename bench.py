@@ -55,10 +55,15 @@ SEG_GROUPS = 1  # 4-edge groups per lane and step of the IC segment kernels (kSe
 MODES = ("widths", "store", "cover")
 # HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs of this benchmark (scaled by a plain-copy calibration; see
-# profiles/ic_seg_kernel_chunglu_n1e6_m1e7.md).  Valid only for the kernel
-# sources they were taken on.
-TRAFFIC = {"kernel": "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)", "sources_sha256_16": "73a8dd975e6de236",
-           "fetch_bytes": 308087866, "write_bytes": 9104165}
+# profiles/ic_seg_kernel_chunglu_n1e6_m1e7.md), for the first-tier shapes the
+# autotuner picks on this graph.  Valid only for the kernel sources they were
+# taken on.
+TRAFFIC = {
+    "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)": {
+        "sources_sha256_16": "73a8dd975e6de236", "fetch_bytes": 308087866, "write_bytes": 9104165},
+    "ic_seg_kernel<0, true, 16, 128, 8, 512, 1> (widths)": {
+        "sources_sha256_16": "73a8dd975e6de236", "fetch_bytes": 307665301, "write_bytes": 6640322},
+}
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/pick.hpp", "paper_1404_0900_amd/csrc/engine.hpp")
 
@@ -103,6 +108,8 @@ def main():
     ap.add_argument("--workload", choices=("timplus", "batch64", "serve", "sweep"), default="timplus")
     ap.add_argument("--mc-runs", type=int, default=10_000, help="forward Monte-Carlo runs per seed set (sweep)")
     ap.add_argument("--rates", type=str, default="1,5,20,50,200", help="arrival rates per second (serve)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the context's sampler shapes (TIM_IC_SEG_LANES) instead of timing them first")
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -127,8 +134,14 @@ def main():
     eng = tim.Engine(0)
     dg = eng.upload(g)
     log(f"graph resident: n={g.n} m={g.m}")
-    tune = eng.autotune(dg, tim.IC, 1 << 20)  # the sampler shapes for this graph, before timing
-    log(f"autotune: {tune.seg_lanes} lanes per set, slice cap {tune.slice_cap}")
+    if args.no_autotune:
+        tune = tim.TuneResult()
+        tune.seg_lanes = int(os.environ.get("TIM_IC_SEG_LANES", "8"))
+        tune.slice_cap = 0
+    else:
+        # the sampler shapes for this graph, before timing, on launches about the size of its large rounds
+        tune = eng.autotune(dg, tim.IC, 1 << 22)
+    log(f"sampler shape: {tune.seg_lanes} lanes per set, slice cap {tune.slice_cap}")
 
     def step():
         out = []
@@ -169,11 +182,13 @@ def main():
         return kernel_name(model, mode, tune.seg_lanes)
 
     def traffic_of(model, mode):
-        if name_of(model, mode) == TRAFFIC["kernel"] and sources_sha() == TRAFFIC["sources_sha256_16"]:
-            return TRAFFIC["fetch_bytes"] + TRAFFIC["write_bytes"]
+        t = TRAFFIC.get(name_of(model, mode))
+        if t and sources_sha() == t["sources_sha256_16"]:
+            return t["fetch_bytes"] + t["write_bytes"]
         return None
     roofline = dominant_roofline(prof, name_of, traffic_of)
     sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
+    by_phase = sampler_by_mode(prof, 0)
 
     line = {
         "metric": "RR sets/s (IC, 1 GPU, TIM+ on 1M-node Chung-Lu, k in {1,10,50})",
@@ -196,10 +211,13 @@ def main():
         "sets_per_step": sets // args.steps,
         "sampler_gpu_ms_per_step": round(sampler_ms / args.steps, 3),
         "index_greedy_gpu_ms_per_step": round((prof.index_ms + prof.greedy_ms) / args.steps, 3),
+        "sampler_by_phase": by_phase,
         "roofline": roofline,
-        "autotune": {"seg_lanes": int(tune.seg_lanes), "slice_cap": int(tune.slice_cap),
-                     "ms_width_4_8_16_32_64": [round(x, 3) for x in tune.ms_width],
-                     "ms_emit_512_1024_2048_4096": [round(x, 3) for x in tune.ms_emit]},
+        "autotune": None if args.no_autotune else {
+            "seg_lanes": int(tune.seg_lanes), "slice_cap": int(tune.slice_cap),
+            "ms_width_4_8_16_32_64": [round(x, 3) for x in tune.ms_width],
+            "ms_stored_4_8_16_32_64": [round(x, 3) for x in tune.ms_lanes_emit],
+            "ms_emit_512_1024_2048_4096": [round(x, 3) for x in tune.ms_emit]},
     }
 
     # the same TIM+ runs under LT (one uniform in-edge per node), outside the timed steps
@@ -239,6 +257,23 @@ def main():
         }
     eng.close()
     print(json.dumps(line), flush=True)
+
+
+def sampler_by_mode(prof, model):
+    """RR sets/s of one model's sampler per kind of launch: the width-only KptEstimation rounds, the stored
+    sets (the last round kept as R' and NodeSelection's theta sets) and RefineKPT's coverage sets.  Sets and
+    GPU time cover every tier of the launches (the HIP events bracket them); edges/s is the first tier's,
+    over the sets it finished."""
+    out = {}
+    for mode, name in ((0, "kpt_widths"), (1, "stored_sets"), (2, "refine_coverage")):
+        kp = prof.sampler[model][mode]
+        if not kp.launches:
+            continue
+        ms = kp.kernel_ms + kp.large_ms
+        out[name] = {"launches": int(kp.launches), "sets": int(kp.sets + kp.deferred), "gpu_ms": round(ms, 3),
+                     "sets_per_s": round((kp.sets + kp.deferred) / (ms * 1e-3), 1),
+                     "tier0_edges_per_s": round(kp.edges / (kp.kernel_ms * 1e-3), 1)}
+    return out
 
 
 def dominant_roofline(prof, name_of, traffic_of=lambda model, mode: None):

@@ -182,13 +182,15 @@ typedef struct {
   uint32_t slice_cap;  /* largest node-pool slice a wavefront reserves when storing sets */
   double ms_width[5];  /* IC: one width-mode launch of `sets` sets with 4, 8, 16, 32, 64 lanes (0 for LT) */
   double ms_emit[4];   /* one stored-set launch with slice caps 512, 1024, 2048, 4096 */
+  double ms_lanes_emit[5]; /* IC: one stored-set launch of `sets` sets with 4, 8, 16, 32, 64 lanes (0 for LT) */
 } tim_tune_result;
 
 /* Times the context's sampler shapes on graph g and keeps the fastest for
  * the context's later calls: first the IC first-tier lanes per set (the
- * wave-per-set thresholds; width mode, as the KptEstimation rounds run),
- * then the node-pool slice size (stored sets, as RefineKPT and
- * NodeSelection run).  Each candidate runs `sets` sets (phase 66, a fixed
+ * wave-per-set thresholds), by the sum of one width-mode launch (as the
+ * KptEstimation rounds run) and one stored-set launch (as the last round
+ * kept for RefineKPT and NodeSelection run), then the node-pool slice size
+ * (stored sets).  Each candidate runs `sets` sets (phase 66, a fixed
  * seed; the sets are dropped) once untimed and three times timed; the best
  * wall time wins if it beats the current shape by 3% or more (else the
  * current one stays).  Results of every call do not depend on these shapes.

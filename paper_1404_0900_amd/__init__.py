@@ -78,7 +78,7 @@ class Report(ctypes.Structure):
 
 
 class TuneResult(ctypes.Structure):
-    _fields_ = [("seg_lanes", I32), ("slice_cap", U32), ("ms_width", DBL * 5), ("ms_emit", DBL * 4)]
+    _fields_ = [("seg_lanes", I32), ("slice_cap", U32), ("ms_width", DBL * 5), ("ms_emit", DBL * 4), ("ms_lanes_emit", DBL * 5)]
 
 
 class KernelProfile(ctypes.Structure):

@@ -1836,19 +1836,26 @@ tim_status tim_autotune(tim_ctx* c, const tim_graph* g, int model, uint64_t sets
     const int cur_lanes = c->seg_lanes;
     int best_lanes = cur_lanes;
     double best = 1e300, cur = 1e300;
+    // a TIM+ run samples width-only rounds and stored sets: each shape is timed on one launch of each
     for (int i = 0; i < 5; ++i) {
       set_seg_lanes(c, lanes[i]);
       Totals t;
-      const double ms = best_ms([&] {
+      const double ms_w = best_ms([&] {
         t = Totals();
         return sample_counts(c, g, model, tim::kModeWidth, seed, phase, 0, sets, 1, nullptr, nullptr, &t);
       });
-      if (ms < 0) {
+      nodes = t.nodes;
+      const double ms_e = ms_w < 0 ? -1.0 : best_ms([&] {
+        Totals te;
+        return emit_sets(c, g, model, seed, phase, 0, sets, nodes + nodes / 4 + 4096, nullptr, &te);
+      });
+      if (ms_w < 0 || ms_e < 0) {
         set_seg_lanes(c, best_lanes);
         return st;
       }
-      r.ms_width[i] = ms;
-      nodes = t.nodes;
+      r.ms_width[i] = ms_w;
+      r.ms_lanes_emit[i] = ms_e;
+      const double ms = ms_w + ms_e;
       if (lanes[i] == cur_lanes) cur = ms;
       if (ms < best) {
         best = ms;

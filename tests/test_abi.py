@@ -44,7 +44,8 @@ int main(void) {
          sizeof(tim_batch_stats), sizeof(tim_refine_result), sizeof(tim_select_result), offsetof(tim_report, s_prime),
          offsetof(tim_report, ms_kpt), offsetof(tim_report, sets_total), sizeof(tim_query),
          offsetof(tim_query, status), sizeof(tim_batch_info), offsetof(tim_batch_info, ms_wall));
-  printf("%zu %zu\n", sizeof(tim_tune_result), offsetof(tim_tune_result, ms_emit));
+  printf("%zu %zu %zu\n", sizeof(tim_tune_result), offsetof(tim_tune_result, ms_emit),
+         offsetof(tim_tune_result, ms_lanes_emit));
   return 0;
 }
 '''
@@ -58,7 +59,7 @@ int main(void) {
             ctypes.sizeof(tim.RefineResult), ctypes.sizeof(tim.SelectResult), tim.Report.s_prime.offset,
             tim.Report.ms_kpt.offset, tim.Report.sets_total.offset, ctypes.sizeof(tim.Query), tim.Query.status.offset,
             ctypes.sizeof(tim.BatchInfo), tim.BatchInfo.ms_wall.offset, ctypes.sizeof(tim.TuneResult),
-            tim.TuneResult.ms_emit.offset]
+            tim.TuneResult.ms_emit.offset, tim.TuneResult.ms_lanes_emit.offset]
     assert got == want
 
 

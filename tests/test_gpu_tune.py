@@ -20,12 +20,13 @@ def test_autotune_keeps_results(model):
         assert r.seg_lanes in (4, 8, 16, 32, 64) and r.slice_cap in (512, 1024, 2048, 4096)
         assert all(x > 0 for x in r.ms_emit)
         if model == IC:
-            assert all(x > 0 for x in r.ms_width)
-            # the chosen shape is the current one or one at least 3% faster than it
-            times = dict(zip((4, 8, 16, 32, 64), r.ms_width))
+            assert all(x > 0 for x in r.ms_width) and all(x > 0 for x in r.ms_lanes_emit)
+            # the chosen shape is the current one or one at least 3% faster than it on a width launch plus a
+            # stored-set launch
+            times = {lanes: w + e for lanes, w, e in zip((4, 8, 16, 32, 64), r.ms_width, r.ms_lanes_emit)}
             assert r.seg_lanes == 8 or times[r.seg_lanes] < 0.97 * times[8]
         else:
-            assert all(x == 0 for x in r.ms_width) and r.seg_lanes == 8
+            assert all(x == 0 for x in r.ms_width) and all(x == 0 for x in r.ms_lanes_emit) and r.seg_lanes == 8
         seeds, gains, rep = e.run(dg, model, 30, 0.5, 1.0, 3)
         want = oracle.tim_run(g, model, 30, 0.5, 1.0, 3)
         assert np.array_equal(seeds, want["seeds"]) and np.array_equal(gains, want["gains"])
