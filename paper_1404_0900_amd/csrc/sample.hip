@@ -323,6 +323,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   __shared__ int32_t s_q[NSEG][Q];
   __shared__ uint32_t s_h[kHash ? NSEG : 1][H];
   __shared__ uint32_t s_tail[kHash ? NSEG : 1];
+  __shared__ unsigned long long s_sig[kHash ? 1 : NSEG];  // signature of each set's queued nodes (hash-free)
   const int lane = threadIdx.x % kWave;
   const int sl = threadIdx.x % S;       // lane within the segment
   const int seg = threadIdx.x / S;      // segment within the block
@@ -353,7 +354,6 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   unsigned long long rel = 0;
   SetStream st = make_set_stream(a.phase, a.first);
   int head = 0, tail_r = 0;                  // queue cursor; queue length (hash-free variant)
-  uint64_t ssig = 0;                         // signature of the queued nodes (hash-free variant)
   uint32_t G = 0, done_items = 0, gsum = 0;  // groups of the current batch / done / of the set so far
   // lane state: this lane's node of the current batch
   uint32_t ea = 0, d = 0, ng = 0, incl = 0;
@@ -379,7 +379,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
           }
         }
         tail_r = 1;
-        ssig = sig_bit(root);
+        if (!kHash && is_leader) s_sig[seg] = sig_bit(root);
         has = true;
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
         bad = false;
@@ -550,32 +550,24 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
           }
         }
       } else if (seg_bits<S>(__ballot(any_live), sw) != 0ull) {
-        // A live source whose signature bit is clear in the set's signature
-        // and used by no other live source of this step is new: those are
-        // appended at once.  The rest are looked up in the queue one at a time.
-        uint64_t bits[4 * R], once = 0ull, twice = 0ull;
-#pragma unroll
-        for (int w = 0; w < 4 * R; ++w) {
-          bits[w] = live[w] ? sig_bit(sv[w]) : 0ull;
-          twice |= once & bits[w];
-          once |= bits[w];
-        }
-#pragma unroll
-        for (int o = 1; o < S; o <<= 1) {
-          const uint64_t o2 = __shfl_xor(once, o, S), t2 = __shfl_xor(twice, o, S);
-          twice |= t2 | (once & o2);
-          once |= o2;
-        }
+        // Every live source sets its signature bit in the set's LDS signature
+        // with an atomic OR.  One that finds the bit clear is new (every queued
+        // node's bit is set, and of several sources sharing a bit in this step
+        // only the first sees it clear): those are appended at once.  The rest
+        // are looked up in the queue one at a time, after the appends.
         bool fast[4 * R];
         uint32_t nfast = 0;
 #pragma unroll
         for (int w = 0; w < 4 * R; ++w) {
-          fast[w] = live[w] && ((ssig | twice) & bits[w]) == 0ull;
+          fast[w] = false;
+          if (live[w]) {
+            const unsigned long long b = sig_bit(sv[w]);
+            fast[w] = (atomicOr(&s_sig[seg], b) & b) == 0ull;
+          }
           nfast += fast[w] ? 1u : 0u;
         }
         const uint32_t fincl = seg_incl_scan<S>(nfast, sl);
         const uint32_t ftot = __shfl(fincl, S - 1, S);
-        ssig |= once;
         if (tail_r + (int)ftot > Q) {
           lbad = true;
         } else {
