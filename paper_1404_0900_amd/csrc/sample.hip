@@ -50,15 +50,53 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// Inclusive prefix sum within segments of W lanes.
+// x from the lane O below in the same 16-lane DPP row (0 where that leaves the row).
+template <int O>
+__device__ __forceinline__ uint32_t dpp_row_shr(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x110 + O, 0xF, 0xF, true);
+}
+
+// Inclusive prefix sum within segments of W lanes.  Segments of up to 16
+// lanes lie inside one DPP row, so their steps are row shifts (no LDS
+// crossbar); lanes closer than the shift to their segment's start add nothing.
+// The shifted value is taken in every lane before the select: a DPP move
+// under a narrowed exec mask would read 0 from the disabled lanes below.
 template <int W>
 __device__ __forceinline__ uint32_t seg_incl_scan(uint32_t x, int sl) {
+  if constexpr (W <= 16) {
+    uint32_t y;
+    if constexpr (W > 1) { y = dpp_row_shr<1>(x); x += sl >= 1 ? y : 0u; }
+    if constexpr (W > 2) { y = dpp_row_shr<2>(x); x += sl >= 2 ? y : 0u; }
+    if constexpr (W > 4) { y = dpp_row_shr<4>(x); x += sl >= 4 ? y : 0u; }
+    if constexpr (W > 8) { y = dpp_row_shr<8>(x); x += sl >= 8 ? y : 0u; }
+    return x;
+  } else {
 #pragma unroll
-  for (int o = 1; o < W; o <<= 1) {
-    const uint32_t y = __shfl_up(x, o, W);
-    if (sl >= o) x += y;
+    for (int o = 1; o < W; o <<= 1) {
+      const uint32_t y = __shfl_up(x, o, W);
+      if (sl >= o) x += y;
+    }
+    return x;
   }
-  return x;
+}
+
+// Sum over segments of W lanes, in every lane of the segment.  Up to 16
+// lanes: a butterfly of DPP moves (swap neighbours, swap pairs in a quad,
+// then mirror the 8-lane and 16-lane halves), each step adding two disjoint
+// partial sums.
+template <int W>
+__device__ __forceinline__ uint32_t seg_sum_u32(uint32_t x) {
+  if constexpr (W <= 16) {
+    if constexpr (W > 1) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0xB1, 0xF, 0xF, false);  // [1,0,3,2]
+    if constexpr (W > 2) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x4E, 0xF, 0xF, false);  // [2,3,0,1]
+    if constexpr (W > 4) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x141, 0xF, 0xF, false);  // half mirror
+    if constexpr (W > 8) x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x140, 0xF, 0xF, false);  // mirror
+    return x;
+  } else {
+#pragma unroll
+    for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
+    return x;
+  }
 }
 
 template <int W>
@@ -399,10 +437,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
     if (has && (done_items >= G || hit || bad)) {
       const int tail = kHash ? (int)s_tail[seg] : tail_r;
       if (bad || tail > Q || hit || head >= tail) {
-        uint32_t w = wlane;
-#pragma unroll
-        for (int o = S / 2; o > 0; o >>= 1) w += __shfl_xor(w, o, S);
-        fin_width = w;
+        fin_width = seg_sum_u32<S>(wlane);
         has = false;
         if (bad || tail > Q) {
           defer_now = true;
