@@ -70,6 +70,16 @@ __device__ __forceinline__ uint32_t seg_incl_scan(uint32_t x, int sl) {
     if constexpr (W > 4) { y = dpp_row_shr<4>(x); x += sl >= 4 ? y : 0u; }
     if constexpr (W > 8) { y = dpp_row_shr<8>(x); x += sl >= 8 ? y : 0u; }
     return x;
+  } else if constexpr (W == 64) {
+    // whole wavefront (every lane active): scan each 16-lane row, then add
+    // row 0's total to rows 1 and 3 and rows 0-1's total to rows 2 and 3
+    x += dpp_row_shr<1>(x);
+    x += dpp_row_shr<2>(x);
+    x += dpp_row_shr<4>(x);
+    x += dpp_row_shr<8>(x);
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);  // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);  // row_bcast:31
+    return x;
   } else {
 #pragma unroll
     for (int o = 1; o < W; o <<= 1) {
@@ -97,6 +107,16 @@ __device__ __forceinline__ uint32_t seg_sum_u32(uint32_t x) {
     for (int o = W / 2; o > 0; o >>= 1) x += __shfl_xor(x, o, W);
     return x;
   }
+}
+
+// A segment's total in every lane of it, given the inclusive scan `incl` of
+// the values `x`: a DPP sum up to 16 lanes, the last lane read out for the
+// whole wavefront, else a shuffle from the segment's last lane.
+template <int W>
+__device__ __forceinline__ uint32_t seg_last(uint32_t incl, uint32_t x) {
+  if constexpr (W <= 16) return seg_sum_u32<W>(x);
+  else if constexpr (W == 64) return (uint32_t)__builtin_amdgcn_readlane((int)incl, kWave - 1);
+  else return __shfl(incl, W - 1, W);
 }
 
 template <int W>
@@ -472,7 +492,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
         wlane += d;
         head += nb;
         incl = seg_incl_scan<S>(ng, sl);
-        G = __shfl(incl, S - 1, S);
+        G = seg_last<S>(incl, ng);
         done_items = 0;
         gsum += G;
         if (gsum > (uint32_t)GMAX) {  // too wide for this tier: hand it on
@@ -503,7 +523,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
       const uint64_t fm = __ballot(mine != 0u);
       if (fm) {
         const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
-        const uint32_t tot = __shfl(winc, kWave - 1);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)winc, kWave - 1);
         // tier 0 reserves slices; the deferral tier (large sets, few) exactly what it stores
         const unsigned long long slice = io.acc == 0 ? (unsigned long long)a.pool_chunk : 0ull;
         const unsigned long long my_base = pool_place(a, slice, mine, winc, tot, pool_next, pool_end, lane);
@@ -602,7 +622,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
           nfast += fast[w] ? 1u : 0u;
         }
         const uint32_t fincl = seg_incl_scan<S>(nfast, sl);
-        const uint32_t ftot = __shfl(fincl, S - 1, S);
+        const uint32_t ftot = seg_last<S>(fincl, nfast);
         if (tail_r + (int)ftot > Q) {
           lbad = true;
         } else {
@@ -762,7 +782,7 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
     if (MODE == kModeEmit) {
       const uint32_t mine = fin ? (uint32_t)len : 0u;
       const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
-      const uint32_t tot = __shfl(winc, kWave - 1);
+      const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)winc, kWave - 1);
       if (tot) {
         const unsigned long long base =
             pool_place(a, (unsigned long long)a.pool_chunk, mine, winc, tot, pool_next, pool_end, lane);
