@@ -184,6 +184,9 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
 
 // One bit of a 64-bit membership signature: a clear bit proves absence.
 __device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
+// A 128-bit signature in two words: word index (0 or 1) and bit of node u.
+__device__ __forceinline__ uint32_t sig2_word(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> 31; }
+__device__ __forceinline__ uint64_t sig2_bit(int32_t u) { return 1ull << ((((uint32_t)u * 0x9E3779B1u) >> 25) & 63u); }
 
 struct Acc {
   u128 kappa = 0;
@@ -381,7 +384,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   __shared__ int32_t s_q[NSEG][Q];
   __shared__ uint32_t s_h[kHash ? NSEG : 1][H];
   __shared__ uint32_t s_tail[kHash ? NSEG : 1];
-  __shared__ unsigned long long s_sig[kHash ? 1 : NSEG];  // signature of each set's queued nodes (hash-free)
+  __shared__ unsigned long long s_sig[kHash ? 1 : NSEG][2];  // 128-bit signature of each set's queued nodes
   const int lane = threadIdx.x % kWave;
   const int sl = threadIdx.x % S;       // lane within the segment
   const int seg = threadIdx.x / S;      // segment within the block
@@ -437,7 +440,11 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
           }
         }
         tail_r = 1;
-        if (!kHash && is_leader) s_sig[seg] = sig_bit(root);
+        if (!kHash && is_leader) {
+          const uint32_t wd = sig2_word(root);
+          s_sig[seg][wd] = sig2_bit(root);
+          s_sig[seg][wd ^ 1u] = 0ull;
+        }
         has = true;
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
         bad = false;
@@ -616,8 +623,8 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
         for (int w = 0; w < 4 * R; ++w) {
           fast[w] = false;
           if (live[w]) {
-            const unsigned long long b = sig_bit(sv[w]);
-            fast[w] = (atomicOr(&s_sig[seg], b) & b) == 0ull;
+            const unsigned long long b = sig2_bit(sv[w]);
+            fast[w] = (atomicOr(&s_sig[seg][sig2_word(sv[w])], b) & b) == 0ull;
           }
           nfast += fast[w] ? 1u : 0u;
         }
