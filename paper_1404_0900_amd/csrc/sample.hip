@@ -184,9 +184,10 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
 
 // One bit of a 64-bit membership signature: a clear bit proves absence.
 __device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
-// A 128-bit signature in two words: word index (0 or 1) and bit of node u.
-__device__ __forceinline__ uint32_t sig2_word(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> 31; }
-__device__ __forceinline__ uint64_t sig2_bit(int32_t u) { return 1ull << ((((uint32_t)u * 0x9E3779B1u) >> 25) & 63u); }
+// A set signature of kSigWords 64-bit words: word index and bit of node u.
+constexpr int kSigWords = 4;
+__device__ __forceinline__ uint32_t sig2_word(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> 30; }
+__device__ __forceinline__ uint64_t sig2_bit(int32_t u) { return 1ull << ((((uint32_t)u * 0x9E3779B1u) >> 24) & 63u); }
 
 struct Acc {
   u128 kappa = 0;
@@ -384,7 +385,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   __shared__ int32_t s_q[NSEG][Q];
   __shared__ uint32_t s_h[kHash ? NSEG : 1][H];
   __shared__ uint32_t s_tail[kHash ? NSEG : 1];
-  __shared__ unsigned long long s_sig[kHash ? 1 : NSEG][2];  // 128-bit signature of each set's queued nodes
+  __shared__ unsigned long long s_sig[kHash ? 1 : NSEG][kSigWords];  // signature of each set's queued nodes
   const int lane = threadIdx.x % kWave;
   const int sl = threadIdx.x % S;       // lane within the segment
   const int seg = threadIdx.x / S;      // segment within the block
@@ -442,8 +443,8 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
         tail_r = 1;
         if (!kHash && is_leader) {
           const uint32_t wd = sig2_word(root);
-          s_sig[seg][wd] = sig2_bit(root);
-          s_sig[seg][wd ^ 1u] = 0ull;
+#pragma unroll
+          for (int i = 0; i < kSigWords; ++i) s_sig[seg][i] = (uint32_t)i == wd ? sig2_bit(root) : 0ull;
         }
         has = true;
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
