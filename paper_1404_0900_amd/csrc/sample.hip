@@ -185,9 +185,13 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
 // One bit of a 64-bit membership signature: a clear bit proves absence.
 __device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
 // A set signature of kSigWords 64-bit words: word index and bit of node u.
-constexpr int kSigWords = 4;
-__device__ __forceinline__ uint32_t sig2_word(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> 30; }
-__device__ __forceinline__ uint64_t sig2_bit(int32_t u) { return 1ull << ((((uint32_t)u * 0x9E3779B1u) >> 24) & 63u); }
+// The top bits of the hash pick the word, the 6 bits below them the bit.
+constexpr int kSigWordBits = 3;
+constexpr int kSigWords = 1 << kSigWordBits;
+__device__ __forceinline__ uint32_t sig2_word(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> (32 - kSigWordBits); }
+__device__ __forceinline__ uint64_t sig2_bit(int32_t u) {
+  return 1ull << ((((uint32_t)u * 0x9E3779B1u) >> (26 - kSigWordBits)) & 63u);
+}
 
 struct Acc {
   u128 kappa = 0;
@@ -385,7 +389,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   __shared__ int32_t s_q[NSEG][Q];
   __shared__ uint32_t s_h[kHash ? NSEG : 1][H];
   __shared__ uint32_t s_tail[kHash ? NSEG : 1];
-  __shared__ unsigned long long s_sig[kHash ? 1 : NSEG][kSigWords];  // signature of each set's queued nodes
+  __shared__ __align__(16) unsigned long long s_sig[kHash ? 1 : NSEG][kSigWords];  // signature of each set's queued nodes
   const int lane = threadIdx.x % kWave;
   const int sl = threadIdx.x % S;       // lane within the segment
   const int seg = threadIdx.x / S;      // segment within the block
