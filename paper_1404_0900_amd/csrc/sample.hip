@@ -41,6 +41,7 @@ constexpr int kLtWaves = 2;        // wavefronts per block, LT lane-level pass
 constexpr int kChain = 64;         // LT chain length held in LDS
 constexpr int kBigThreads = 512;   // IC last-tier block size
 constexpr int kSegGroups = 1;      // 4-edge groups a lane decides per step (IC tiers 0 and 1)
+constexpr uint64_t kKappaBlocks = 1024;  // largest grid of the kappa pass (four per CU)
 
 typedef unsigned __int128 u128;
 
@@ -184,9 +185,29 @@ __device__ __forceinline__ int lds_insert(uint32_t* h, uint32_t u) {
 
 // One bit of a 64-bit membership signature: a clear bit proves absence.
 __device__ __forceinline__ uint64_t sig_bit(int32_t u) { return 1ull << (((uint32_t)u * 0x9E3779B1u) >> 26); }
+
+// A 256-bit membership signature in four registers (a clear bit proves
+// absence); the word is chosen by selects, so the array never leaves registers.
+struct Sig256 {
+  uint64_t w0 = 0, w1 = 0, w2 = 0, w3 = 0;
+  __device__ __forceinline__ static uint32_t hash(int32_t u) { return (uint32_t)u * 0x9E3779B1u; }
+  __device__ __forceinline__ bool maybe(int32_t u) const {
+    const uint32_t h = hash(u), wd = h >> 30;
+    const uint64_t w = wd == 0u ? w0 : wd == 1u ? w1 : wd == 2u ? w2 : w3;
+    return (w >> ((h >> 24) & 63u)) & 1ull;
+  }
+  __device__ __forceinline__ void add(int32_t u) {
+    const uint32_t h = hash(u), wd = h >> 30;
+    const uint64_t b = 1ull << ((h >> 24) & 63u);
+    w0 |= wd == 0u ? b : 0ull;
+    w1 |= wd == 1u ? b : 0ull;
+    w2 |= wd == 2u ? b : 0ull;
+    w3 |= wd == 3u ? b : 0ull;
+  }
+};
 // A set signature of kSigWords 64-bit words: word index and bit of node u.
 // The top bits of the hash pick the word, the 6 bits below them the bit.
-constexpr int kSigWordBits = 3;
+constexpr int kSigWordBits = 4;
 constexpr int kSigWords = 1 << kSigWordBits;
 __device__ __forceinline__ uint32_t sig2_word(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> (32 - kSigWordBits); }
 __device__ __forceinline__ uint64_t sig2_bit(int32_t u) {
@@ -246,6 +267,58 @@ __device__ __forceinline__ void wave_flush(const SampleArgs& a, const Acc& acc, 
   }
 }
 
+// A block's accumulators in LDS.  Every wavefront adds its sums here when
+// it is done; the last one of the block adds the total to the counters, so
+// a launch makes one set of device atomics per block instead of one per
+// wavefront (atomics on one address serialize).  Wavefronts that leave
+// early count themselves done too.  Batched launches flush per wavefront:
+// the wavefronts of a block may be working for different jobs.
+struct BlockAcc {
+  unsigned long long v[6];  // kappa high word, kappa low word's two halves, width, nodes, covered
+  unsigned int done;
+};
+
+__device__ __forceinline__ void block_acc_init(BlockAcc& b) {
+  if (threadIdx.x < 6) b.v[threadIdx.x] = 0ull;
+  if (threadIdx.x == 0) b.done = 0u;
+  __syncthreads();
+}
+
+__device__ __forceinline__ void block_acc_flush(const SampleArgs& a, BlockAcc& b, const Acc& acc, int tier,
+                                                int lane) {
+  const unsigned long long lo = (unsigned long long)acc.kappa, hi = (unsigned long long)(acc.kappa >> 64);
+  unsigned long long s[6];
+  s[0] = seg_sum<kWave>(hi);
+  s[1] = seg_sum<kWave>(lo >> 32);
+  s[2] = seg_sum<kWave>(lo & 0xFFFFFFFFull);
+  s[3] = seg_sum<kWave>(acc.width);
+  s[4] = seg_sum<kWave>(acc.nodes);
+  s[5] = seg_sum<kWave>(acc.covered);
+  if (lane == 0) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i)
+      if (s[i]) __hip_atomic_fetch_add(&b.v[i], s[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    const unsigned int nw = blockDim.x / kWave;
+    if (__hip_atomic_fetch_add(&b.done, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP) == nw - 1u) {
+      unsigned long long t[6];
+#pragma unroll
+      for (int i = 0; i < 6; ++i) t[i] = __hip_atomic_load(&b.v[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      unsigned long long* c = a.ctr + kCtrAcc + kAccStride * tier;
+      // per-wavefront limbs are below 2^39, so 64-bit block sums of them are exact
+      add_u128(c + kAccKappaLo, ((u128)t[0] << 64) + ((u128)t[1] << 32) + (u128)t[2]);
+      if (t[3]) atomicAdd(c + kAccWidth, t[3]);
+      if (t[4]) atomicAdd(c + kAccNodes, t[4]);
+      if (t[5]) atomicAdd(c + kAccCovered, t[5]);
+    }
+  }
+}
+
+// Flush through the block when it has a BlockAcc, else per wavefront.
+__device__ __forceinline__ void flush_acc(const SampleArgs& a, BlockAcc* b, const Acc& acc, int tier, int lane) {
+  if (b) block_acc_flush(a, *b, acc, tier, lane);
+  else wave_flush(a, acc, tier, lane);
+}
+
 __device__ __forceinline__ void block_flush(const SampleArgs& a, const Acc& acc, int tier) {
   unsigned long long* c = a.ctr + kCtrAcc + kAccStride * tier;
   add_u128(c + kAccKappaLo, acc.kappa);
@@ -264,12 +337,13 @@ struct Reservoir {
   unsigned long long cur = 0, end = 0, chunk = 1;
 };
 
-// Items per refill: about 8 refills per wavefront over the launch, at least
-// one item per requester, at most 64 per requester.
+// Items per refill: about 4 refills per wavefront over the launch (each is a
+// device atomic on the one work cursor, and those serialize), at least one
+// item per requester, at most 64 per requester.
 __device__ __forceinline__ unsigned long long chunk_for(unsigned long long total, int waves_per_block,
                                                         int per_wave) {
   const unsigned long long waves = (unsigned long long)gridDim.x * (unsigned long long)waves_per_block;
-  unsigned long long c = total / (waves * 8ull);
+  unsigned long long c = total / (waves * 4ull);
   c = c < (unsigned long long)per_wave ? (unsigned long long)per_wave : c;
   return c > 64ull * per_wave ? 64ull * per_wave : c;
 }
@@ -382,7 +456,8 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
 // beyond the first ones the list needs leave at once instead of each taking
 // a turn at the list's cursor.
 template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
-__device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io, bool first_only) {
+__device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io, bool first_only,
+                                           BlockAcc* blk = nullptr) {
   constexpr bool kHash = HLOG > 0;
   constexpr int H = kHash ? (1 << HLOG) : 4;
   constexpr int NSEG = kSegThreads / S;
@@ -407,7 +482,10 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   const unsigned long long total = io.in_list ? list_len(a, io.in_len_ctr) : a.count;
   if (first_only && io.in_list) {
     const unsigned long long wave = (unsigned long long)blockIdx.x * (kSegThreads / kWave) + threadIdx.x / kWave;
-    if (wave * (unsigned long long)(kWave / S) >= total) return;
+    if (wave * (unsigned long long)(kWave / S) >= total) {
+      flush_acc(a, blk, Acc(), io.acc, lane);
+      return;
+    }
   }
   Acc acc;
   Reservoir res;
@@ -445,10 +523,9 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
           }
         }
         tail_r = 1;
-        if (!kHash && is_leader) {
+        if (!kHash) {  // the segment's lanes clear the words (the root is the same in all of them)
           const uint32_t wd = sig2_word(root);
-#pragma unroll
-          for (int i = 0; i < kSigWords; ++i) s_sig[seg][i] = (uint32_t)i == wd ? sig2_bit(root) : 0ull;
+          for (int i = sl; i < kSigWords; i += S) s_sig[seg][i] = (uint32_t)i == wd ? sig2_bit(root) : 0ull;
         }
         has = true;
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
@@ -677,33 +754,62 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
     hit = hit || seg_bits<S>(hm, sw) != 0ull;
     bad = bad || seg_bits<S>(bm, sw) != 0ull;
   }
-  wave_flush(a, acc, io.acc, lane);
+  flush_acc(a, blk, acc, io.acc, lane);
 }
 
 template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
 __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
-  ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, io, true);
+  __shared__ BlockAcc blk;
+  block_acc_init(blk);
+  ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, io, true, &blk);
 }
 
 // Exact sum of kappa(R) * 2^53 over the widths a width-mode launch wrote
 // (Equation (8)); optionally copies the widths out as uint64.
-__global__ __launch_bounds__(kSegThreads) void kappa_reduce_kernel(SampleArgs a) {
-  Acc acc;
+// The block's exact sum goes to the counters with one pair of atomics (the
+// wavefronts' sums meet in LDS first): atomics on one address from every
+// wavefront of a large launch would serialize.
+__device__ __forceinline__ void kappa_pass(const SampleArgs& a) {
+  __shared__ unsigned long long s_part[kSegThreads / kWave][3];
+  u128 kap = 0;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count; i += stride) {
     const uint32_t w = a.wbuf[i];
-    acc.kappa += kappa_fixed(w, a.g.m, a.k);
+    kap += kappa_fixed(w, a.g.m, a.k);
     if (a.widths) a.widths[i] = w;
   }
-  wave_flush(a, acc, 0, threadIdx.x % kWave);
+  // 32-bit limbs and the high word summed as 64-bit values: exact for 256 lanes
+  const unsigned long long lo = (unsigned long long)kap, hi = (unsigned long long)(kap >> 64);
+  const unsigned long long s_hi = seg_sum<kWave>(hi);
+  const unsigned long long s_l0 = seg_sum<kWave>(lo & 0xFFFFFFFFull);
+  const unsigned long long s_l1 = seg_sum<kWave>(lo >> 32);
+  const int wv = threadIdx.x / kWave;
+  if (threadIdx.x % kWave == 0) {
+    s_part[wv][0] = s_hi;
+    s_part[wv][1] = s_l1;
+    s_part[wv][2] = s_l0;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long h = 0, l1 = 0, l0 = 0;
+    for (int w = 0; w < kSegThreads / kWave; ++w) {
+      h += s_part[w][0];
+      l1 += s_part[w][1];
+      l0 += s_part[w][2];
+    }
+    const u128 v = ((u128)h << 64) + ((u128)l1 << 32) + (u128)l0;
+    if (v) add_u128(a.ctr + kCtrAcc + kAccKappaLo, v);
+  }
 }
+
+__global__ __launch_bounds__(kSegThreads) void kappa_reduce_kernel(SampleArgs a) { kappa_pass(a); }
 
 // ------------------------------------------------------------------------
 // LT, tier 0: one chain per lane.
 // ------------------------------------------------------------------------
 
 template <int MODE>
-__device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& io) {
+__device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& io, BlockAcc* blk = nullptr) {
   __shared__ int32_t s_chain[kLtWaves][kChain][kWave];
   const int wv = threadIdx.x / kWave;
   const int lane = threadIdx.x % kWave;
@@ -720,7 +826,7 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
   unsigned long long rel = 0, width = 0;
   int32_t v = 0;
   int len = 0;
-  uint64_t sig = 0;
+  Sig256 sig;
   SetStream st = make_set_stream(a.phase, a.first);
   for (;;) {
     {
@@ -732,7 +838,8 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
         chain[0][lane] = v;
         len = 1;
         width = 0;
-        sig = sig_bit(v);
+        sig = Sig256();
+        sig.add(v);
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, v);
         active = true;
       }
@@ -750,9 +857,8 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
           done = true;
         } else {
           const int32_t u = g.src[e];
-          const uint64_t bit = sig_bit(u);
           bool seen = false;
-          if (sig & bit) {
+          if (sig.maybe(u)) {
             for (int i = 0; i < len; ++i) {
               if (chain[i][lane] == u) {
                 seen = true;
@@ -768,7 +874,7 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
           } else {
             chain[len][lane] = u;
             ++len;
-            sig |= bit;
+            sig.add(u);
             v = u;
             if (MODE == kModeCover && in_seed(a.seed_bits, u)) {
               hit = true;
@@ -824,9 +930,11 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
       }
     }
   }
-  wave_flush(a, acc, io.acc, lane);
+  flush_acc(a, blk, acc, io.acc, lane);
 }
 
+// (Per-wavefront flushes: the chains fill exactly 32 KB of LDS per block, and
+// any more would cost a block per CU.)
 template <int MODE>
 __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_kernel(SampleArgs a, TierIO io) {
   lt_lane_run<MODE>(a, io);
@@ -1028,7 +1136,8 @@ __device__ __forceinline__ int32_t lt_next(const GraphView& g, const Key& key, c
 constexpr int kChainWaves = 4;  // wavefronts per block of the long-chain tier
 
 template <int MODE>
-__device__ __forceinline__ void lt_chain_run(const SampleArgs& a, const TierIO& io, bool first_only) {
+__device__ __forceinline__ void lt_chain_run(const SampleArgs& a, const TierIO& io, bool first_only,
+                                             BlockAcc* blk = nullptr) {
   const int lane = threadIdx.x % kWave;
   const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
   const GraphView g = a.g;
@@ -1036,7 +1145,10 @@ __device__ __forceinline__ void lt_chain_run(const SampleArgs& a, const TierIO& 
   const unsigned long long total = list_len(a, io.in_len_ctr);
   if (first_only) {  // a chain per lane to start with: later wavefronts are not needed
     const unsigned long long wave = (unsigned long long)blockIdx.x * kChainWaves + threadIdx.x / kWave;
-    if (wave * (unsigned long long)kWave >= total) return;
+    if (wave * (unsigned long long)kWave >= total) {
+      flush_acc(a, blk, Acc(), io.acc, lane);
+      return;
+    }
   }
   Acc acc;
   Reservoir res;
@@ -1161,12 +1273,14 @@ __device__ __forceinline__ void lt_chain_run(const SampleArgs& a, const TierIO& 
       }
     }
   }
-  wave_flush(a, acc, io.acc, lane);
+  flush_acc(a, blk, acc, io.acc, lane);
 }
 
 template <int MODE>
 __global__ __launch_bounds__(kChainWaves* kWave) void lt_chain_kernel(SampleArgs a, TierIO io) {
-  lt_chain_run<MODE>(a, io, true);
+  __shared__ BlockAcc blk;
+  block_acc_init(blk);
+  lt_chain_run<MODE>(a, io, true, &blk);
 }
 
 __global__ void clear_counters_kernel(unsigned long long* ctr) {
@@ -1291,15 +1405,8 @@ __global__ __launch_bounds__(kChainWaves* kWave) void lt_chain_batch_kernel(JobT
 // that asked for them (wbuf set).
 __global__ __launch_bounds__(kSegThreads) void kappa_reduce_batch_kernel(JobTable t, int emit) {
   const SampleArgs& a = t.jobs[blockIdx.y];
-  if (emit && !a.wbuf) return;
-  Acc acc;
-  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
-  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < a.count; i += stride) {
-    const uint32_t w = a.wbuf[i];
-    acc.kappa += kappa_fixed(w, a.g.m, a.k);
-    if (a.widths) a.widths[i] = w;
-  }
-  wave_flush(a, acc, 0, threadIdx.x % kWave);
+  if (emit && !a.wbuf) return;  // the whole block: the job stores no widths
+  kappa_pass(a);
 }
 
 __global__ void clear_counters_batch_kernel(JobTable t) {
@@ -1349,7 +1456,7 @@ struct Tier1Kernel {
 
 void launch_kappa_reduce(const SampleArgs& a, hipStream_t s) {
   uint64_t blocks = (a.count + kSegThreads - 1) / kSegThreads;
-  blocks = blocks < 1 ? 1 : (blocks > 4096 ? 4096 : blocks);
+  blocks = blocks < 1 ? 1 : (blocks > kKappaBlocks ? kKappaBlocks : blocks);
   hipLaunchKernelGGL(kappa_reduce_kernel, dim3((unsigned)blocks), dim3(kSegThreads), 0, s, a);
 }
 
@@ -1517,7 +1624,7 @@ void launch_clear_counters_batch(const JobTable& t, hipStream_t s) {
 void launch_sample_batch(int model, int mode, bool wc, const JobTable& t, int grid0, int grid1, int slots,
                          uint64_t max_count, hipStream_t s, hipEvent_t after_tier0) {
   uint64_t kb = (max_count + kSegThreads - 1) / kSegThreads;
-  const unsigned kappa_blocks = (unsigned)(kb < 1 ? 1 : (kb > 4096 ? 4096 : kb));
+  const unsigned kappa_blocks = (unsigned)(kb < 1 ? 1 : (kb > kKappaBlocks ? kKappaBlocks : kb));
   if (model == 0) {
     switch (mode * 2 + (wc ? 1 : 0)) {
       case 0: launch_ic_batch<kModeWidth, false>(t, grid0, grid1, slots, kappa_blocks, s, after_tier0); break;
