@@ -60,9 +60,9 @@ MODES = ("widths", "store", "cover")
 # taken on.
 TRAFFIC = {
     "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)": {
-        "sources_sha256_16": "73a8dd975e6de236", "fetch_bytes": 308087866, "write_bytes": 9104165},
+        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 307987023, "write_bytes": 9238990},
     "ic_seg_kernel<0, true, 16, 128, 8, 512, 1> (widths)": {
-        "sources_sha256_16": "73a8dd975e6de236", "fetch_bytes": 307665301, "write_bytes": 6640322},
+        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 307753732, "write_bytes": 7206336},
 }
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/pick.hpp", "paper_1404_0900_amd/csrc/engine.hpp")
