@@ -173,6 +173,8 @@ constexpr int kAggLog = 12;
 constexpr int kAgg = 1 << kAggLog;
 constexpr int kAggProbes = 32;
 constexpr int kTileSets = 128;      // sets per tile (set-tiled kernels)
+constexpr int kHistTileSets = 256;  // sets per tile of the counts pass (at most kThreads)
+static_assert(kTileSets <= kThreads && kHistTileSets <= kThreads, "a tile's sets are carried one per thread");
 constexpr int kTileEntries = 2048;  // entries per tile (flat histogram)
 
 __device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert) {
@@ -204,6 +206,7 @@ __device__ __forceinline__ void agg_clear(uint32_t* a, uint32_t* b) {
 // carries set t (len 0 if it takes no part); afterwards s_pre[t] is the first
 // tile position of set t, s_pre[kTileSets] the tile total, and s_start[t] its
 // first entry in the collection.
+template <int TS = kTileSets>
 __device__ __forceinline__ void tile_prefix(uint32_t len, int64_t start, int64_t* s_start, int64_t* s_pre,
                                             uint32_t* s_wtot) {
   const int lane = threadIdx.x % 64, wv = threadIdx.x / 64;
@@ -217,7 +220,7 @@ __device__ __forceinline__ void tile_prefix(uint32_t len, int64_t start, int64_t
   __syncthreads();
   uint32_t carry = 0;
   for (int w = 0; w < wv; ++w) carry += s_wtot[w];
-  if (threadIdx.x < kTileSets) {
+  if (threadIdx.x < TS) {
     s_start[threadIdx.x] = start;
     s_pre[threadIdx.x + 1] = carry + incl;
   }
@@ -237,9 +240,10 @@ __device__ __forceinline__ int tile_set_of(const int64_t* s_pre, int ns, int64_t
   return lo;
 }
 
+template <int TS = kTileSets>
 struct TileShared {
-  int64_t start[kTileSets];
-  int64_t pre[kTileSets + 1];
+  int64_t start[TS];
+  int64_t pre[TS + 1];
   uint32_t wtot[kThreads / 64];
   uint32_t key[kAgg], cnt[kAgg];
 };
@@ -252,16 +256,16 @@ constexpr int64_t kAggMin = 1;
 
 // Adds (sign +1) or subtracts the memberships of the tile's listed sets (prefix
 // from tile_prefix) to cnt, skipping node `skip`.
-template <bool kAdd>
-__device__ __forceinline__ void tile_apply(const int32_t* nodes, TileShared& t, int64_t skip, uint32_t* cnt) {
-  const int64_t tot = t.pre[kTileSets];
+template <bool kAdd, int TS = kTileSets>
+__device__ __forceinline__ void tile_apply(const int32_t* nodes, TileShared<TS>& t, int64_t skip, uint32_t* cnt) {
+  const int64_t tot = t.pre[TS];
   const bool agg = tot >= kAggMin;
   if (agg) {
     agg_clear(t.key, t.cnt);
     __syncthreads();
   }
   for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
-    const int j = tile_set_of(t.pre, kTileSets, e);
+    const int j = tile_set_of(t.pre, TS, e);
     const int32_t u = nodes[t.start[j] + (e - t.pre[j])];
     if (u == skip) continue;
     const int slot = agg ? agg_slot(t.key, (uint32_t)u, true) : -1;
@@ -302,19 +306,22 @@ __global__ __launch_bounds__(kThreads) void hist_flat_kernel(const int32_t* node
 }
 
 // cnt[u] += number of sets containing u, in tiles of sets.
+// (Larger tiles than the other passes: the LDS table's clear and scan are
+// spread over twice the entries, and more hub repeats meet in it.)
 template <class V>
 __global__ __launch_bounds__(kThreads) void hist_sets_kernel(V sets, uint64_t nsets, uint32_t* cnt) {
-  __shared__ TileShared t;
-  for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
-    const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
+  constexpr int TS = kHistTileSets;
+  __shared__ TileShared<TS> t;
+  for (uint64_t s0 = (uint64_t)blockIdx.x * TS; s0 < nsets; s0 += (uint64_t)gridDim.x * TS) {
+    const int ns = (int)min((uint64_t)TS, nsets - s0);
     uint32_t len = 0;
     int64_t start = 0;
     if (threadIdx.x < ns) {
       start = sets.start(s0 + threadIdx.x);
       len = sets.len(s0 + threadIdx.x);
     }
-    tile_prefix(len, start, t.start, t.pre, t.wtot);
-    tile_apply<true>(sets.nodes, t, -1, cnt);
+    tile_prefix<TS>(len, start, t.start, t.pre, t.wtot);
+    tile_apply<true, TS>(sets.nodes, t, -1, cnt);
   }
 }
 
@@ -322,7 +329,7 @@ __global__ __launch_bounds__(kThreads) void hist_sets_kernel(V sets, uint64_t ns
 template <class V>
 __global__ __launch_bounds__(kThreads) void scatter_kernel(V sets, uint64_t nsets, const int64_t* inv_off,
                                                            uint32_t* fill, uint32_t* inv_sets) {
-  __shared__ TileShared t;
+  __shared__ TileShared<> t;
   __shared__ uint32_t s_base[kAgg];
   for (uint64_t s0 = (uint64_t)blockIdx.x * kTileSets; s0 < nsets; s0 += (uint64_t)gridDim.x * kTileSets) {
     const int ns = (int)min((uint64_t)kTileSets, nsets - s0);
@@ -413,7 +420,7 @@ template <class V>
 __global__ __launch_bounds__(kThreads) void cover_kernel(const unsigned long long* best, const int64_t* inv_off,
                                                          const uint32_t* inv_sets, V sets, uint8_t* covered,
                                                          uint8_t* selected, uint32_t* cnt) {
-  __shared__ TileShared t;
+  __shared__ TileShared<> t;
   if (*best == 0ull) return;  // no unselected node (cannot happen for k <= n)
   const int64_t v = node_of_key(*best);
   if (blockIdx.x == 0 && threadIdx.x == 0) selected[v] = 1u;
@@ -444,7 +451,7 @@ __global__ void select_kernel(const unsigned long long* best, uint8_t* selected)
 // them and take them out of the counts of their members.
 __global__ __launch_bounds__(kThreads) void scan_cover_kernel(const unsigned long long* best, PoolSets sets,
                                                               uint64_t nsets, uint8_t* covered, uint32_t* cnt) {
-  __shared__ TileShared t;
+  __shared__ TileShared<> t;
   __shared__ uint32_t s_hit[kTileSets];
   if (*best == 0ull) return;
   const int64_t v = node_of_key(*best);
@@ -531,7 +538,7 @@ void launch_counts(const GreedyArgs& a, hipStream_t s) {
       hipLaunchKernelGGL(hist_flat_kernel, dim3(tile_grid(a.total, kTileEntries)), dim3(kThreads), 0, s, a.nodes,
                          a.total, a.cnt);
   } else {
-    hipLaunchKernelGGL(hist_sets_kernel<PoolSets>, dim3(tile_grid(a.nsets, kTileSets)), dim3(kThreads), 0, s,
+    hipLaunchKernelGGL(hist_sets_kernel<PoolSets>, dim3(tile_grid(a.nsets, kHistTileSets)), dim3(kThreads), 0, s,
                        pool_of(a), a.nsets, a.cnt);
   }
 }
@@ -591,7 +598,7 @@ void launch_cover_step(const GreedyArgs& a, int j, hipStream_t s) {
 void launch_pool_hist(const int32_t* pool, const uint64_t* set_start, const uint32_t* set_len, uint64_t nsets,
                       uint32_t* cnt, hipStream_t s) {
   if (!nsets) return;
-  hipLaunchKernelGGL(hist_sets_kernel<PoolSets>, dim3(tile_grid(nsets, kTileSets)), dim3(kThreads), 0, s,
+  hipLaunchKernelGGL(hist_sets_kernel<PoolSets>, dim3(tile_grid(nsets, kHistTileSets)), dim3(kThreads), 0, s,
                      PoolSets{set_start, set_len, pool}, nsets, cnt);
 }
 
