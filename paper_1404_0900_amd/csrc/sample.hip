@@ -3,8 +3,9 @@
 // IC (reverse BFS over in-edges), tier 0: a wavefront is split into segments
 // of S lanes and every segment builds its own RR set, so one wavefront keeps
 // 64/S sets in flight and their memory latencies overlap.  A set's nodes live
-// in an LDS queue (which is also its output list) and an LDS open-addressing
-// hash marks visited nodes.  Each iteration of the loop, every segment either
+// in an LDS queue (which is also its output list); visited nodes are found
+// through an LDS membership signature (segments of up to 8 lanes) or an LDS
+// open-addressing hash (wider ones).  Each iteration of the loop, every segment either
 // loads its next batch of up to S queued nodes (two CSR offsets per lane, a
 // segmented prefix sum of their 4-edge groups) or processes S groups of the
 // current batch: a lane loads 4 consecutive sources with one 16-byte load,
@@ -13,11 +14,11 @@
 // that outgrow the segment's LDS structures are deferred: a set is a pure
 // function of its keys, so restarting it in another tier gives the same set.
 // Tier 1 is the same kernel with one set per wavefront and 8x the LDS
-// capacity; the last tier is a 256-thread block per set with visited stamps
+// capacity; the last tier is a 512-thread block per set with visited stamps
 // and a queue of n entries in device memory.
 //
 // LT (at most one live in-edge per node): each lane walks one set's chain,
-// kept in LDS with a 64-bit membership signature in a register; longer chains
+// kept in LDS with a 256-bit membership signature in registers; longer chains
 // go to the last tier, one lane per chain without visited marks (Brent's
 // cycle search over the walk, which is a fixed function of the set's keys).
 //
@@ -447,9 +448,11 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
 // ------------------------------------------------------------------------
 // IC, tiers 0 and 1: S lanes per set.  Edge positions fit 32 bits (m < 2^32).
 // HLOG > 0: visited nodes are marked in an LDS hash of 2^HLOG slots and live
-// edges are inserted concurrently.  HLOG == 0: no hash; the segment takes its
-// live edges one at a time and looks each source up in its own queue (all S
-// lanes scan Q/S entries), which leaves the LDS to more sets in flight.
+// edges are inserted concurrently.  HLOG == 0: no hash, which leaves the LDS
+// to more sets in flight; a 1024-bit LDS signature per set proves most
+// sources new (an atomic OR settles sources sharing a bit), and the rest are
+// looked up one at a time in the set's own queue (each of the S lanes scans
+// Q/S entries).
 // Width mode writes w(R) per set; kappa is summed by kappa_reduce_kernel.
 // ------------------------------------------------------------------------
 // first_only: a launch of its own over one deferred list, whose wavefronts
