@@ -53,16 +53,20 @@ EPS, ELL, SEED = 0.2, 1.0, 2
 HBM_PEAK_GBS = 8000.0
 SEG_GROUPS = 1  # 4-edge groups per lane and step of the IC segment kernels (kSegGroups)
 MODES = ("widths", "store", "cover")
-# HBM bytes per launch of the dominant kernel from rocprofv3 FETCH_SIZE and
+# HBM bytes per launch of the first-tier IC kernels that can be the dominant
+# one (stored sets; widths of the large rounds), from rocprofv3 FETCH_SIZE and
 # WRITE_SIZE runs of this benchmark (scaled by a plain-copy calibration; see
-# profiles/ic_seg_kernel_chunglu_n1e6_m1e7.md), for the first-tier shapes the
-# autotuner picks on this graph.  Valid only for the kernel sources they were
-# taken on.
+# profiles/ic_seg_kernel_chunglu_n1e6_m1e7.md), for the shapes the autotuner
+# picks on this graph.  Valid only for the kernel sources they were taken on.
 TRAFFIC = {
+    "ic_seg_kernel<1, true, 8, 128, 0, 512, 1> (store)": {
+        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 2246133522, "write_bytes": 375326933},
+    "ic_seg_kernel<1, true, 16, 128, 8, 512, 1> (store)": {
+        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 2216938642, "write_bytes": 295785643},
     "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)": {
-        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 307987023, "write_bytes": 9238990},
+        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 1600544600, "write_bytes": 47842834},
     "ic_seg_kernel<0, true, 16, 128, 8, 512, 1> (widths)": {
-        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 307753732, "write_bytes": 7206336},
+        "sources_sha256_16": "26bf307ef7731b59", "fetch_bytes": 1596524605, "write_bytes": 36360370},
 }
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/pick.hpp", "paper_1404_0900_amd/csrc/engine.hpp")
@@ -188,6 +192,7 @@ def main():
         return None
     roofline = dominant_roofline(prof, name_of, traffic_of)
     sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
+    sampler_ms += sum(prof.ic_wide[b].kernel_ms + prof.ic_wide[b].large_ms for b in (0, 1, 2))
     by_phase = sampler_by_mode(prof, 0)
 
     line = {
@@ -262,17 +267,22 @@ def main():
 def sampler_by_mode(prof, model):
     """RR sets/s of one model's sampler per kind of launch: the width-only KptEstimation rounds, the stored
     sets (the last round kept as R' and NodeSelection's theta sets) and RefineKPT's coverage sets.  Sets and
-    GPU time cover every tier of the launches (the HIP events bracket them); edges/s is the first tier's,
-    over the sets it finished."""
+    GPU time cover every tier of the launches (the HIP events bracket them), including IC launches of few sets
+    that run the 64-lane first tier; edges/s is the first tier's, over the sets it finished."""
     out = {}
     for mode, name in ((0, "kpt_widths"), (1, "stored_sets"), (2, "refine_coverage")):
-        kp = prof.sampler[model][mode]
-        if not kp.launches:
+        parts = [prof.sampler[model][mode]] + ([prof.ic_wide[mode]] if model == 0 else [])
+        launches = sum(int(p.launches) for p in parts)
+        if not launches:
             continue
-        ms = kp.kernel_ms + kp.large_ms
-        out[name] = {"launches": int(kp.launches), "sets": int(kp.sets + kp.deferred), "gpu_ms": round(ms, 3),
-                     "sets_per_s": round((kp.sets + kp.deferred) / (ms * 1e-3), 1),
-                     "tier0_edges_per_s": round(kp.edges / (kp.kernel_ms * 1e-3), 1)}
+        sets = sum(int(p.sets + p.deferred) for p in parts)
+        ms = sum(p.kernel_ms + p.large_ms for p in parts)
+        out[name] = {"launches": launches, "sets": sets, "gpu_ms": round(ms, 3),
+                     "sets_per_s": round(sets / (ms * 1e-3), 1),
+                     "tier0_edges_per_s": round(sum(p.edges for p in parts) / (sum(p.kernel_ms for p in parts) * 1e-3), 1)}
+        wide = prof.ic_wide[mode] if model == 0 else None
+        if wide is not None and wide.launches:
+            out[name]["wide_launches"] = int(wide.launches)
     return out
 
 

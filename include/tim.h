@@ -220,6 +220,8 @@ typedef struct {
   tim_kernel_profile sampler[2][3]; /* [model][0: widths, 1: stored sets, 2: coverage] */
   uint64_t index_calls;             /* inverted-index builds + greedy runs */
   double index_ms, greedy_ms;
+  tim_kernel_profile ic_wide[3];    /* IC launches of fewer than 262144 sets (widths, coverage), which run
+                                       the 64-lane first tier; sampler[0][] holds the others */
 } tim_profile;
 
 /* Turns per-launch timing on (on != 0) or off, and clears the counters. */

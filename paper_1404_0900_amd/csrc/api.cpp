@@ -94,6 +94,7 @@ struct tim_ctx {
   } stored;
   int grid_ic[3][2] = {};
   int grid_ic64[3][2] = {};
+  int grid_ic_wide[3][2] = {};  // first tier with 64 lanes per set (launches of few sets)
   int grid_lt[3] = {};
   int grid_lt_chain[3] = {};
   unsigned long long* ctr = nullptr;       // device counters of the current launch
@@ -282,11 +283,27 @@ void hub_submit(Hub* h, Pending* p) {
   h->cv_done.wait(lk, [&] { return p->done; });
 }
 
+// IC width and coverage launches of fewer sets than this (the early
+// KptEstimation rounds) cannot fill the chip with 8-lane segments: they last
+// as long as their largest set takes to cross its BFS levels, so they run the
+// 64-lane shape instead.  Stored sets keep the context's shape, which the
+// node-pool slice bound assumes.
+constexpr uint64_t kWideLaunchSets = 262144;
+
+// Lanes per set of the IC first tier for a launch of `count` sets.
+int launch_lanes(const tim_ctx* c, int model, int mode, uint64_t count) {
+  if (model == TIM_MODEL_IC && mode != tim::kModeEmit && count < kWideLaunchSets) return 64;
+  return c->seg_lanes;
+}
+
 // Blocks of the tier-0 sampler over `count` sets (and its wavefronts).
 uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t count, uint64_t* waves) {
-  const int per_cu = model == TIM_MODEL_IC ? c->grid_ic[mode][wc ? 1 : 0] : c->grid_lt[mode];
+  const int lanes = launch_lanes(c, model, mode, count);
+  const int per_cu = model != TIM_MODEL_IC ? c->grid_lt[mode]
+                     : lanes == c->seg_lanes ? c->grid_ic[mode][wc ? 1 : 0]
+                                             : c->grid_ic_wide[mode][wc ? 1 : 0];
   const uint64_t waves_per_block = model == TIM_MODEL_IC ? 4 : 2;
-  uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)c->seg_lanes) : 128;
+  uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)lanes) : 128;
   if (mode == tim::kModeEmit && c->emit_wave_sets)
     sets_per_block = std::max<uint64_t>(sets_per_block, waves_per_block * c->emit_wave_sets);
   uint64_t grid = (uint64_t)per_cu * (uint64_t)c->num_cu;
@@ -404,7 +421,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
         (uint64_t)c->num_cu;
     tim::launch_clear_counters(c->ctr, c->stream);
     if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
-    tim::launch_sample(model, mode, a, c->seg_lanes, (int)grid0, (int)grid1, c->stream,
+    tim::launch_sample(model, mode, a, launch_lanes(c, model, mode, count), (int)grid0, (int)grid1, c->stream,
                        c->prof_on ? c->pev[1] : nullptr);
     if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[2], c->stream));
     HIP_TRY(hipGetLastError());
@@ -427,7 +444,11 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
     float ms_main = 0.f, ms_big = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms_main, c->pev[0], c->pev[1]));
     HIP_TRY(hipEventElapsedTime(&ms_big, c->pev[1], c->pev[2]));
-    tim_kernel_profile& p = c->prof.sampler[model][mode];
+    // launches in the 64-lane shape are kept apart, so that the sampler[][]
+    // entries describe one kernel each
+    tim_kernel_profile& p = (model == TIM_MODEL_IC && launch_lanes(c, model, mode, count) != c->seg_lanes)
+                                ? c->prof.ic_wide[mode]
+                                : c->prof.sampler[model][mode];
     const unsigned long long* acc0 = h + tim::kCtrAcc;
     const uint64_t sets = count - h[tim::kCtrList1];
     const uint64_t nodes = acc0[tim::kAccNodes], edges = acc0[tim::kAccWidth];
@@ -1539,6 +1560,7 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
     for (int wc = 0; wc < 2; ++wc) {
       c->grid_ic[mode][wc] = tim::ic_blocks_per_cu(mode, wc != 0, c->seg_lanes);
       c->grid_ic64[mode][wc] = tim::ic_tier1_blocks_per_cu(mode, wc != 0);
+      c->grid_ic_wide[mode][wc] = tim::ic_blocks_per_cu(mode, wc != 0, 64);
     }
     c->grid_lt[mode] = tim::lt_lane_blocks_per_cu(mode);
     c->grid_lt_chain[mode] = tim::lt_chain_blocks_per_cu(mode, false);

@@ -46,6 +46,7 @@ int main(void) {
          offsetof(tim_query, status), sizeof(tim_batch_info), offsetof(tim_batch_info, ms_wall));
   printf("%zu %zu %zu\n", sizeof(tim_tune_result), offsetof(tim_tune_result, ms_emit),
          offsetof(tim_tune_result, ms_lanes_emit));
+  printf("%zu %zu %zu\n", sizeof(tim_profile), offsetof(tim_profile, greedy_ms), offsetof(tim_profile, ic_wide));
   return 0;
 }
 '''
@@ -59,7 +60,8 @@ int main(void) {
             ctypes.sizeof(tim.RefineResult), ctypes.sizeof(tim.SelectResult), tim.Report.s_prime.offset,
             tim.Report.ms_kpt.offset, tim.Report.sets_total.offset, ctypes.sizeof(tim.Query), tim.Query.status.offset,
             ctypes.sizeof(tim.BatchInfo), tim.BatchInfo.ms_wall.offset, ctypes.sizeof(tim.TuneResult),
-            tim.TuneResult.ms_emit.offset, tim.TuneResult.ms_lanes_emit.offset]
+            tim.TuneResult.ms_emit.offset, tim.TuneResult.ms_lanes_emit.offset,
+            ctypes.sizeof(tim.Profile), tim.Profile.greedy_ms.offset, tim.Profile.ic_wide.offset]
     assert got == want
 
 

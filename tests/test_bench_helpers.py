@@ -23,10 +23,13 @@ def _prof():
     s[0][0] = _kp(10, 8.0, 1000, 9000, 70000, 424000, 2.0, 10)
     s[0][1] = _kp(4, 12.0, 500, 5000, 40000, 30_000_000_000, 1.0, 5)
     s[1][0] = _kp(3, 1.0, 100, 300, 900, 6000)
-    return SimpleNamespace(sampler=s, index_ms=0.0, greedy_ms=0.0, index_calls=0)
+    wide = [_kp() for _ in range(3)]
+    wide[0] = _kp(5, 2.0, 400, 1000, 8000, 48000, 0.5, 0)
+    return SimpleNamespace(sampler=s, ic_wide=wide, index_ms=0.0, greedy_ms=0.0, index_calls=0)
 
 
 def test_dominant_roofline_takes_the_longest_kernel():
+    # the 64-lane launches of few sets (ic_wide) are another kernel: never the roofline's
     r = bench.dominant_roofline(_prof(), lambda model, mode: f"k{model}{mode}", lambda model, mode: 123)
     assert r["kernel"] == "k01" and r["launches"] == 4
     assert r["achieved"] == pytest.approx(30e9 / 12e-3 / 1e9, rel=1e-6)
@@ -38,17 +41,20 @@ def test_dominant_roofline_takes_the_longest_kernel():
 def test_sampler_by_mode_counts_every_tier():
     out = bench.sampler_by_mode(_prof(), 0)
     assert set(out) == {"kpt_widths", "stored_sets"}  # no coverage launches in this profile
-    w = out["kpt_widths"]
-    assert w["sets"] == 1010 and w["gpu_ms"] == pytest.approx(10.0)
-    assert w["sets_per_s"] == pytest.approx(1010 / 10e-3)
-    assert w["tier0_edges_per_s"] == pytest.approx(70000 / 8e-3)
+    w = out["kpt_widths"]  # the 8-lane launches and the 64-lane ones of few sets together
+    assert w["sets"] == 1010 + 400 and w["gpu_ms"] == pytest.approx(12.5) and w["launches"] == 15
+    assert w["sets_per_s"] == pytest.approx(1410 / 12.5e-3)
+    assert w["tier0_edges_per_s"] == pytest.approx(78000 / 10e-3)
+    assert w["wide_launches"] == 5 and "wide_launches" not in out["stored_sets"]
 
 
 def test_kernel_names_follow_the_shape_table():
     assert bench.kernel_name(0, 0, 8) == "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)"
     assert bench.kernel_name(0, 1, 16) == "ic_seg_kernel<1, true, 16, 128, 8, 512, 1> (store)"
     assert bench.kernel_name(1, 2) == "lt_lane_kernel<2> (cover)"
-    assert all(name.startswith("ic_seg_kernel<0, true,") for name in bench.TRAFFIC)
+    # traffic is kept for weighted-cascade first-tier kernels, under the names kernel_name gives them
+    names = {bench.kernel_name(0, mode, lanes) for mode in (0, 1) for lanes in (8, 16)}
+    assert set(bench.TRAFFIC) == names
 
 
 def test_traffic_key_ignores_comments_but_not_code(tmp_path, monkeypatch):
