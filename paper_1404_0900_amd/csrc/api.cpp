@@ -95,6 +95,7 @@ struct tim_ctx {
   int grid_ic[3][2] = {};
   int grid_ic64[3][2] = {};
   int grid_ic_wide[3][2] = {};  // first tier with 64 lanes per set (launches of few sets)
+  bool wide_small = true;       // launches of few sets take the 64-lane shape (off while tim_autotune times shapes)
   int grid_lt[3] = {};
   int grid_lt_chain[3] = {};
   unsigned long long* ctr = nullptr;       // device counters of the current launch
@@ -292,7 +293,7 @@ constexpr uint64_t kWideLaunchSets = 262144;
 
 // Lanes per set of the IC first tier for a launch of `count` sets.
 int launch_lanes(const tim_ctx* c, int model, int mode, uint64_t count) {
-  if (model == TIM_MODEL_IC && mode != tim::kModeEmit && count < kWideLaunchSets) return 64;
+  if (c->wide_small && model == TIM_MODEL_IC && mode != tim::kModeEmit && count < kWideLaunchSets) return 64;
   return c->seg_lanes;
 }
 
@@ -1854,6 +1855,12 @@ tim_status tim_autotune(tim_ctx* c, const tim_graph* g, int model, uint64_t sets
   const double kGain = 0.97;
   uint64_t nodes = 0;
   if (model == TIM_MODEL_IC) {
+    // every trial runs the shape it times, whatever the size of the trial launch
+    struct WideScope {
+      tim_ctx* c;
+      ~WideScope() { c->wide_small = true; }
+    } wide_scope{c};
+    c->wide_small = false;
     static const int lanes[5] = {4, 8, 16, 32, 64};
     const int cur_lanes = c->seg_lanes;
     int best_lanes = cur_lanes;
