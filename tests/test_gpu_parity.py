@@ -483,6 +483,37 @@ def test_max_coverage_large_tiles_overflow_lds_tables(eng):
         assert np.array_equal(seeds, ws) and np.array_equal(gains, wg), k
 
 
+_LARGE = {}
+
+
+@pytest.mark.parametrize("lanes", ["4", "8", "16", "32", "64"])
+def test_large_width_and_cover_launches_every_shape(cfg1, lanes, monkeypatch):
+    # width and coverage launches of 262144 sets or more run the context's first-tier shape (smaller
+    # ones take the 64-lane shape): every shape's widths, sizes, exact kappa sum and coverage count
+    import paper_1404_0900_amd as tim
+    monkeypatch.setenv("TIM_IC_SEG_LANES", lanes)
+    count, seed, phase, k = 300_000, 4, 11, 5
+    seeds = np.array([1559, 11944, 8686, 2086], dtype=np.int32)
+    if not _LARGE:
+        so, nodes, ww = oracle.sample_sets(cfg1, IC, seed, phase, 0, count)
+        sid = np.repeat(np.arange(count), np.diff(so))
+        hit = np.zeros(count, dtype=bool)
+        hit[sid[np.isin(nodes, seeds)]] = True
+        _LARGE.update(so=so, ww=ww, covered=int(hit.sum()),
+                      kappa=oracle.round_sum(cfg1, IC, seed, phase, 0, count, k)["sum"])
+    want = _LARGE
+    _say(f"large launches: {lanes} lanes per set")
+    with tim.Engine(0) as e:
+        dg = e.upload(cfg1)
+        w, sz, st = e.sample_widths(dg, IC, seed, phase, 0, count, k)
+        assert np.array_equal(w.cpu().numpy().astype(np.uint64), want["ww"])
+        assert np.array_equal(sz.cpu().numpy(), np.diff(want["so"]).astype(np.int32))
+        assert st.kappa_sum == want["kappa"]
+        assert st.width_sum == int(want["ww"].sum()) and st.node_sum == int(want["so"][-1])
+        cst = e.sample_cover(dg, IC, seed, phase, 0, count, seeds)
+        assert cst.covered == want["covered"]
+
+
 @pytest.mark.parametrize("lanes", ["4", "16", "32", "64"])
 def test_segment_width_does_not_change_results(cfg1, cfg2, lanes, monkeypatch):
     # the IC tier-0 kernel's lanes per set is a launch-shape choice only
