@@ -193,6 +193,7 @@ def main():
     roofline = dominant_roofline(prof, name_of, traffic_of)
     sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
     sampler_ms += sum(prof.ic_wide[b].kernel_ms + prof.ic_wide[b].large_ms for b in (0, 1, 2))
+    sampler_ms += sum(prof.grouped[a].kernel_ms + prof.grouped[a].large_ms for a in (0, 1))
     by_phase = sampler_by_mode(prof, 0)
 
     line = {
@@ -268,10 +269,13 @@ def sampler_by_mode(prof, model):
     """RR sets/s of one model's sampler per kind of launch: the width-only KptEstimation rounds, the stored
     sets (the last round kept as R' and NodeSelection's theta sets) and RefineKPT's coverage sets.  Sets and
     GPU time cover every tier of the launches (the HIP events bracket them), including IC launches of few sets
-    that run the 64-lane first tier; edges/s is the first tier's, over the sets it finished."""
+    that run the 64-lane first tier and the multi-job launches of the early rounds (whose sets include those of
+    rounds past the stopping one); edges/s is the first tier's, over the sets it finished."""
     out = {}
     for mode, name in ((0, "kpt_widths"), (1, "stored_sets"), (2, "refine_coverage")):
         parts = [prof.sampler[model][mode]] + ([prof.ic_wide[mode]] if model == 0 else [])
+        if mode == 0:
+            parts.append(prof.grouped[model])
         launches = sum(int(p.launches) for p in parts)
         if not launches:
             continue
@@ -283,6 +287,8 @@ def sampler_by_mode(prof, model):
         wide = prof.ic_wide[mode] if model == 0 else None
         if wide is not None and wide.launches:
             out[name]["wide_launches"] = int(wide.launches)
+        if mode == 0 and prof.grouped[model].launches:
+            out[name]["grouped_launches"] = int(prof.grouped[model].launches)
     return out
 
 

@@ -222,6 +222,9 @@ typedef struct {
   double index_ms, greedy_ms;
   tim_kernel_profile ic_wide[3];    /* IC launches of fewer than 262144 sets (widths, coverage), which run
                                        the 64-lane first tier; sampler[0][] holds the others */
+  tim_kernel_profile grouped[2];    /* [model] multi-job launches that run several early KptEstimation rounds
+                                       at once, one job per round; sets counts every set they sampled,
+                                       those of rounds past the stopping one included */
 } tim_profile;
 
 /* Turns per-launch timing on (on != 0) or off, and clears the counters. */

@@ -88,7 +88,7 @@ class KernelProfile(ctypes.Structure):
 
 class Profile(ctypes.Structure):
     _fields_ = [("sampler", (KernelProfile * 3) * 2), ("index_calls", U64), ("index_ms", DBL), ("greedy_ms", DBL),
-                ("ic_wide", KernelProfile * 3)]
+                ("ic_wide", KernelProfile * 3), ("grouped", KernelProfile * 2)]
 
 
 class Query(ctypes.Structure):

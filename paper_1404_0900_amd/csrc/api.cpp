@@ -98,6 +98,10 @@ struct tim_ctx {
   bool wide_small = true;       // launches of few sets take the 64-lane shape (off while tim_autotune times shapes)
   int grid_lt[3] = {};
   int grid_lt_chain[3] = {};
+  int grid_rounds[2][2] = {};     // multi-job launches of KptEstimation rounds: tier 0 per [model][wc]
+  int grid_batch1[2] = {};        // their IC tier 1, per wc
+  int grid_batch_chain = 0;       // their LT long-chain tier
+  DevBuf jobs;                    // job table and per-job counters of a multi-job launch
   unsigned long long* ctr = nullptr;       // device counters of the current launch
   unsigned long long* ctr_host = nullptr;  // pinned mirror
   DevBuf list1, list2, wbuf, pool, set_start, set_len;
@@ -932,10 +936,126 @@ float elapsed_ms(tim_ctx* c) {
   return ms;
 }
 
+// Early KptEstimation rounds whose sets together number at most this many run
+// as the jobs of one multi-job launch (kpt_estimate_impl).
+constexpr uint64_t kGroupSets = 1ull << 19;
+
+// Width-mode sets of rounds i0..i1 of KptEstimation, one job per round
+// (phase i, sets [0, c_i)), in one multi-job launch; t[r] receives the totals
+// of round i0 + r.  A launch of few sets lasts about as long as its largest
+// set takes to cross its BFS levels or chain, so the early rounds, launched
+// one by one, each pay that latency; launched together they pay it once.
+// Every set is a function of its own keys, so each round's totals are those
+// of a launch of that round alone.
+tim_status sample_rounds(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double ell, int i0, int i1,
+                         Totals* t) {
+  const int J = i1 - i0 + 1;
+  if (J < 1 || J > tim::kMaxBatchJobs) return fail(TIM_EINVAL, "%d rounds in one launch", J);
+  std::vector<uint64_t> base((size_t)J), cnt((size_t)J);
+  uint64_t total = 0, maxc = 0;
+  for (int r = 0; r < J; ++r) {
+    cnt[(size_t)r] = round_size(g->n, ell, i0 + r);
+    base[(size_t)r] = total;
+    total += cnt[(size_t)r];
+    maxc = std::max(maxc, cnt[(size_t)r]);
+  }
+  if (model == TIM_MODEL_IC) TIM_TRY(ensure_big(c, g->n));
+  TIM_TRY(ensure(c, c->list1, total * 8, "deferred-set list"));
+  if (model == TIM_MODEL_IC) TIM_TRY(ensure(c, c->list2, total * 8, "deferred-set list"));
+  TIM_TRY(ensure(c, c->wbuf, total * 4, "width buffer"));
+  const size_t table = ((size_t)J * sizeof(SampleArgs) + 255) & ~(size_t)255;
+  const size_t ctr_words = (size_t)J * tim::kCtrCount;
+  TIM_TRY(ensure(c, c->jobs, table + ctr_words * sizeof(unsigned long long), "job table"));
+  unsigned long long* d_ctr = reinterpret_cast<unsigned long long*>(static_cast<char*>(c->jobs.p) + table);
+  std::vector<SampleArgs> jobs((size_t)J);
+  for (int r = 0; r < J; ++r) {
+    SampleArgs& a = jobs[(size_t)r];
+    memset(&a, 0, sizeof(a));
+    a.g.off = g->off;
+    a.g.src = g->src;
+    a.g.thr = g->thr;
+    a.g.lthr = g->lthr;
+    a.g.n = g->n;
+    a.g.m = g->m;
+    a.seed = seed;
+    a.phase = (uint32_t)(i0 + r);
+    a.first = 0;
+    a.count = cnt[(size_t)r];
+    a.k = k;
+    a.ctr = d_ctr + (size_t)r * tim::kCtrCount;
+    a.wbuf = c->wbuf.as<uint32_t>() + base[(size_t)r];
+    a.seed_bits = c->seed_bits.as<uint32_t>();
+    a.list1 = c->list1.as<uint64_t>() + base[(size_t)r];
+    a.list2 = model == TIM_MODEL_IC ? c->list2.as<uint64_t>() + base[(size_t)r] : nullptr;
+    a.big_stamp = c->big_stamp.as<uint32_t>();
+    a.big_queue = c->big_queue.as<int32_t>();
+    a.big_epoch = c->big_epoch.as<uint32_t>();
+    a.big_slots = c->big_slots;
+    a.big_stride = (uint64_t)c->big_n;
+  }
+  const bool wc = g->thr == nullptr;
+  const tim::JobTable tab{c->jobs.as<SampleArgs>(), J};
+  HIP_TRY(hipMemcpyAsync(c->jobs.p, jobs.data(), (size_t)J * sizeof(SampleArgs), hipMemcpyHostToDevice, c->stream));
+  tim::launch_clear_counters_batch(tab, c->stream);
+  const uint64_t per_block = model == TIM_MODEL_IC ? 32 : 128;  // sets a tier-0 block holds at once
+  const uint64_t full = (uint64_t)c->grid_rounds[model][wc ? 1 : 0] * (uint64_t)c->num_cu;
+  const uint64_t grid0 = std::max<uint64_t>(1, std::min(full, (total + per_block - 1) / per_block));
+  const uint64_t grid1 =
+      (uint64_t)(model == TIM_MODEL_IC ? c->grid_batch1[wc ? 1 : 0] : c->grid_batch_chain) * (uint64_t)c->num_cu;
+  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
+  tim::launch_sample_batch(model, tim::kModeWidth, wc, tab, (int)grid0, (int)grid1, c->big_slots, maxc, c->stream,
+                           c->prof_on ? c->pev[1] : nullptr);
+  if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[2], c->stream));
+  HIP_TRY(hipGetLastError());
+  std::vector<unsigned long long> h(ctr_words);
+  HIP_TRY(hipMemcpyAsync(h.data(), d_ctr, ctr_words * sizeof(unsigned long long), hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  uint64_t sets = 0, nodes = 0, edges = 0, deferred = 0;
+  for (int r = 0; r < J; ++r) {
+    const unsigned long long* hr = h.data() + (size_t)r * tim::kCtrCount;
+    if (hr[tim::kCtrList1] > cnt[(size_t)r] || hr[tim::kCtrList2] > cnt[(size_t)r])
+      return fail(TIM_EDEVICE, "deferred-set list overflow");
+    Totals& tr = t[r];
+    tr = Totals();
+    tr.count = cnt[(size_t)r];
+    tr.deferred = hr[tim::kCtrList1];
+    for (int tier = 0; tier < 3; ++tier) {
+      const unsigned long long* acc = hr + tim::kCtrAcc + tim::kAccStride * tier;
+      tr.kappa += ((u128)acc[tim::kAccKappaHi] << 64) | (u128)acc[tim::kAccKappaLo];
+      tr.width += acc[tim::kAccWidth];
+      tr.nodes += acc[tim::kAccNodes];
+      tr.covered += acc[tim::kAccCovered];
+    }
+    sets += cnt[(size_t)r] - hr[tim::kCtrList1];
+    nodes += hr[tim::kCtrAcc + tim::kAccNodes];
+    edges += hr[tim::kCtrAcc + tim::kAccWidth];
+    deferred += hr[tim::kCtrList1];
+  }
+  if (c->prof_on) {
+    float ms_main = 0.f, ms_big = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms_main, c->pev[0], c->pev[1]));
+    HIP_TRY(hipEventElapsedTime(&ms_big, c->pev[1], c->pev[2]));
+    tim_kernel_profile& p = c->prof.grouped[model];
+    p.launches += 1;
+    p.kernel_ms += ms_main;
+    p.sets += sets;
+    p.nodes += nodes;
+    p.edges += edges;
+    p.bytes += model == TIM_MODEL_IC ? 16 * nodes + (g->thr ? 8 : 4) * edges : 20 * nodes;
+    p.large_launches += 1;
+    p.large_ms += ms_big;
+    p.deferred += deferred;
+  }
+  return TIM_OK;
+}
+
 // Algorithm 2.  With keep_last, a round that the previous one predicts to be
 // the last (its mean kappa already above 0.8 * 2^-i) is stored in the node
 // pool while its widths are summed, so that RefineKPT can take its sets
-// without generating them again.
+// without generating them again.  Outside batches, the early rounds run
+// together (sample_rounds) and are then taken in order exactly as if run one
+// by one: the first that stops ends the estimation, the rest are dropped, and
+// a round predicted to be the last is run again on its own to be stored.
 tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double ell,
                              bool keep_last, tim_kpt_result* out, uint64_t* sets, uint64_t* width) {
   memset(out, 0, sizeof(*out));
@@ -946,12 +1066,72 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
   out->kpt_star = 1.0;
   u128 prev_sum = 0;
   uint64_t prev_c = 0, prev_nodes = 0;
-  for (int i = 1; i <= imax; ++i) {
+  // predicted last: S_{i-1} * 2^i > 0.8 * c_{i-1} * 2^53, evaluated as 5 * S * 2^i > 4 * c * 2^53
+  auto predict = [&](int i, uint64_t ci) {
+    return keep_last && prev_c > 0 && ci <= kMaxLaunchSets && ((prev_sum * 5) << i) > (((u128)prev_c * 4) << 53);
+  };
+  // records round i; true when it stops the estimation
+  auto finish = [&](int i, uint64_t ci, const Totals& t, bool stored) {
+    out->round_c[i] = ci;
+    out->round_sum_lo[i] = (uint64_t)t.kappa;
+    out->round_sum_hi[i] = (uint64_t)(t.kappa >> 64);
+    out->round_width[i] = t.width;
+    out->round_nodes[i] = t.nodes;
+    if (sets) *sets += ci;
+    if (width) *width += t.width;
+    prev_sum = t.kappa;
+    prev_c = ci;
+    prev_nodes = t.nodes;
+    // sum/c_i > 2^-i with sum = S * 2^-53 exactly: S * 2^i > c_i * 2^53
+    if ((t.kappa << i) <= ((u128)ci << 53)) return false;
+    const double sum = std::ldexp((double)t.kappa, -53);
+    out->kpt_star = (sum * (double)g->n) / (2.0 * (double)ci);
+    out->i_last = i;
+    out->c_last = ci;
+    if (stored) {
+      c->stored.valid = true;
+      c->stored.graph = g;
+      c->stored.model = model;
+      c->stored.seed = seed;
+      c->stored.phase = (uint32_t)i;
+      c->stored.count = ci;
+      c->stored.nodes = t.nodes;
+      c->stored.width = t.width;
+    }
+    return true;
+  };
+  for (int i = 1; i <= imax;) {
     const uint64_t ci = round_size(g->n, ell, i);
     Totals t;
-    // predicted last: S_{i-1} * 2^i > 0.8 * c_{i-1} * 2^53, evaluated as 5 * S * 2^i > 4 * c * 2^53
-    const bool predicted = keep_last && prev_c > 0 && ci <= kMaxLaunchSets &&
-                           ((prev_sum * 5) << i) > (((u128)prev_c * 4) << 53);
+    const bool predicted = predict(i, ci);
+    if (!c->hub && !predicted) {
+      // under a budget, the group's lists (20 bytes per set) take at most an
+      // eighth of the room and are released afterwards, so that what later
+      // rounds and the node pool find is what one round per launch leaves
+      const uint64_t group_cap = c->budget ? std::min(kGroupSets, launch_cap(c) / 2) : kGroupSets;
+      int j = i;
+      uint64_t tot = ci;
+      while (j < imax && j - i + 1 < tim::kMaxBatchJobs) {
+        const uint64_t next = round_size(g->n, ell, j + 1);
+        if (tot + next > group_cap) break;
+        tot += next;
+        ++j;
+      }
+      if (j > i) {
+        std::vector<Totals> ts((size_t)(j - i + 1));
+        TIM_TRY(sample_rounds(c, g, model, seed, k, ell, i, j, ts.data()));
+        if (c->budget)
+          for (DevBuf* b : {&c->list1, &c->list2, &c->wbuf, &c->jobs}) release(c, *b);
+        int r = i;
+        for (; r <= j; ++r) {
+          const uint64_t cr = round_size(g->n, ell, r);
+          if (r > i && predict(r, cr)) break;  // to be stored: run on its own
+          if (finish(r, cr, ts[(size_t)(r - i)], false)) return TIM_OK;
+        }
+        i = r;
+        continue;
+      }
+    }
     bool stored = false;
     if (predicted) {
       const uint64_t expect = (uint64_t)((double)prev_nodes / (double)prev_c * 1.25 * (double)ci) + 4096;
@@ -969,34 +1149,8 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
     }
     if (!stored)
       TIM_TRY(sample_counts(c, g, model, tim::kModeWidth, seed, (uint32_t)i, 0, ci, k, nullptr, nullptr, &t));
-    out->round_c[i] = ci;
-    out->round_sum_lo[i] = (uint64_t)t.kappa;
-    out->round_sum_hi[i] = (uint64_t)(t.kappa >> 64);
-    out->round_width[i] = t.width;
-    out->round_nodes[i] = t.nodes;
-    if (sets) *sets += ci;
-    if (width) *width += t.width;
-    prev_sum = t.kappa;
-    prev_c = ci;
-    prev_nodes = t.nodes;
-    // sum/c_i > 2^-i with sum = S * 2^-53 exactly: S * 2^i > c_i * 2^53
-    if ((t.kappa << i) > ((u128)ci << 53)) {
-      const double sum = std::ldexp((double)t.kappa, -53);
-      out->kpt_star = (sum * (double)g->n) / (2.0 * (double)ci);
-      out->i_last = i;
-      out->c_last = ci;
-      if (stored) {
-        c->stored.valid = true;
-        c->stored.graph = g;
-        c->stored.model = model;
-        c->stored.seed = seed;
-        c->stored.phase = (uint32_t)i;
-        c->stored.count = ci;
-        c->stored.nodes = t.nodes;
-        c->stored.width = t.width;
-      }
-      break;
-    }
+    if (finish(i, ci, t, stored)) break;
+    ++i;
   }
   return TIM_OK;
 }
@@ -1566,6 +1720,12 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
     c->grid_lt[mode] = tim::lt_lane_blocks_per_cu(mode);
     c->grid_lt_chain[mode] = tim::lt_chain_blocks_per_cu(mode, false);
   }
+  for (int wc = 0; wc < 2; ++wc) {
+    for (int model = 0; model < 2; ++model)
+      c->grid_rounds[model][wc] = tim::batch_blocks_per_cu(model, tim::kModeWidth, wc != 0, 0);
+    c->grid_batch1[wc] = tim::batch_blocks_per_cu(0, tim::kModeWidth, wc != 0, 1);
+  }
+  c->grid_batch_chain = tim::lt_chain_blocks_per_cu(tim::kModeWidth, true);
   if (hipMalloc(&c->ctr, tim::kCtrCount * sizeof(unsigned long long)) != hipSuccess ||
       hipHostMalloc(&c->ctr_host, tim::kCtrCount * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
@@ -1585,7 +1745,7 @@ void tim_ctx_destroy(tim_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->list1, &c->list2, &c->wbuf, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
                     &c->rr_off, &c->rr_nodes, &c->sizes, &c->cnt, &c->fill, &c->inv_off, &c->inv_sets, &c->covered,
-                    &c->selected, &c->best, &c->scan_tmp, &c->seed_bits};
+                    &c->selected, &c->best, &c->scan_tmp, &c->seed_bits, &c->jobs};
   for (DevBuf* b : bufs) release(c, *b);
   if (c->ctr) (void)hipFree(c->ctr);
   if (c->ctr_host) (void)hipHostFree(c->ctr_host);

@@ -46,7 +46,8 @@ int main(void) {
          offsetof(tim_query, status), sizeof(tim_batch_info), offsetof(tim_batch_info, ms_wall));
   printf("%zu %zu %zu\n", sizeof(tim_tune_result), offsetof(tim_tune_result, ms_emit),
          offsetof(tim_tune_result, ms_lanes_emit));
-  printf("%zu %zu %zu\n", sizeof(tim_profile), offsetof(tim_profile, greedy_ms), offsetof(tim_profile, ic_wide));
+  printf("%zu %zu %zu %zu\n", sizeof(tim_profile), offsetof(tim_profile, greedy_ms), offsetof(tim_profile, ic_wide),
+         offsetof(tim_profile, grouped));
   return 0;
 }
 '''
@@ -61,7 +62,8 @@ int main(void) {
             tim.Report.ms_kpt.offset, tim.Report.sets_total.offset, ctypes.sizeof(tim.Query), tim.Query.status.offset,
             ctypes.sizeof(tim.BatchInfo), tim.BatchInfo.ms_wall.offset, ctypes.sizeof(tim.TuneResult),
             tim.TuneResult.ms_emit.offset, tim.TuneResult.ms_lanes_emit.offset,
-            ctypes.sizeof(tim.Profile), tim.Profile.greedy_ms.offset, tim.Profile.ic_wide.offset]
+            ctypes.sizeof(tim.Profile), tim.Profile.greedy_ms.offset, tim.Profile.ic_wide.offset,
+            tim.Profile.grouped.offset]
     assert got == want
 
 

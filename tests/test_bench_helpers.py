@@ -25,11 +25,13 @@ def _prof():
     s[1][0] = _kp(3, 1.0, 100, 300, 900, 6000)
     wide = [_kp() for _ in range(3)]
     wide[0] = _kp(5, 2.0, 400, 1000, 8000, 48000, 0.5, 0)
-    return SimpleNamespace(sampler=s, ic_wide=wide, index_ms=0.0, greedy_ms=0.0, index_calls=0)
+    grouped = [_kp(2, 1.0, 300, 600, 5000, 29600, 0.5, 0), _kp()]
+    return SimpleNamespace(sampler=s, ic_wide=wide, grouped=grouped, index_ms=0.0, greedy_ms=0.0, index_calls=0)
 
 
 def test_dominant_roofline_takes_the_longest_kernel():
-    # the 64-lane launches of few sets (ic_wide) are another kernel: never the roofline's
+    # the 64-lane launches of few sets (ic_wide) and the multi-job launches of the early rounds (grouped) are
+    # other kernels: never the roofline's
     r = bench.dominant_roofline(_prof(), lambda model, mode: f"k{model}{mode}", lambda model, mode: 123)
     assert r["kernel"] == "k01" and r["launches"] == 4
     assert r["achieved"] == pytest.approx(30e9 / 12e-3 / 1e9, rel=1e-6)
@@ -41,11 +43,12 @@ def test_dominant_roofline_takes_the_longest_kernel():
 def test_sampler_by_mode_counts_every_tier():
     out = bench.sampler_by_mode(_prof(), 0)
     assert set(out) == {"kpt_widths", "stored_sets"}  # no coverage launches in this profile
-    w = out["kpt_widths"]  # the 8-lane launches and the 64-lane ones of few sets together
-    assert w["sets"] == 1010 + 400 and w["gpu_ms"] == pytest.approx(12.5) and w["launches"] == 15
-    assert w["sets_per_s"] == pytest.approx(1410 / 12.5e-3)
-    assert w["tier0_edges_per_s"] == pytest.approx(78000 / 10e-3)
+    w = out["kpt_widths"]  # the 8-lane launches, the 64-lane ones of few sets and the grouped rounds together
+    assert w["sets"] == 1010 + 400 + 300 and w["gpu_ms"] == pytest.approx(14.0) and w["launches"] == 17
+    assert w["sets_per_s"] == pytest.approx(1710 / 14.0e-3)
+    assert w["tier0_edges_per_s"] == pytest.approx(83000 / 11e-3)
     assert w["wide_launches"] == 5 and "wide_launches" not in out["stored_sets"]
+    assert w["grouped_launches"] == 2 and "grouped_launches" not in out["stored_sets"]
 
 
 def test_kernel_names_follow_the_shape_table():
