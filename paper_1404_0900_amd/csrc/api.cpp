@@ -994,7 +994,7 @@ tim_status sample_rounds(tim_ctx* c, const tim_graph* g, int model, uint64_t see
     a.big_stride = (uint64_t)c->big_n;
   }
   const bool wc = g->thr == nullptr;
-  const tim::JobTable tab{c->jobs.as<SampleArgs>(), J};
+  const tim::JobTable tab{c->jobs.as<SampleArgs>(), J, 1};
   HIP_TRY(hipMemcpyAsync(c->jobs.p, jobs.data(), (size_t)J * sizeof(SampleArgs), hipMemcpyHostToDevice, c->stream));
   tim::launch_clear_counters_batch(tab, c->stream);
   const uint64_t per_block = model == TIM_MODEL_IC ? 32 : 128;  // sets a tier-0 block holds at once
@@ -1380,7 +1380,7 @@ tim_status hub_round(Hub* h, std::vector<Pending*>& subs) {
     HIP_TRY(hipStreamWaitEvent(h->stream, subs[i]->ready, 0));
   }
   HIP_TRY(hipMemcpyAsync(h->d_jobs, h->h_jobs, J * sizeof(SampleArgs), hipMemcpyHostToDevice, h->stream));
-  tim::launch_clear_counters_batch(tim::JobTable{h->d_jobs, (int)J}, h->stream);
+  tim::launch_clear_counters_batch(tim::JobTable{h->d_jobs, (int)J, 0}, h->stream);
   for (size_t lo = 0; lo < J;) {
     size_t hi = lo + 1;
     while (hi < J && cls(subs[hi]) == cls(subs[lo]) && hi - lo < (size_t)tim::kMaxBatchJobs) ++hi;
@@ -1398,7 +1398,7 @@ tim_status hub_round(Hub* h, std::vector<Pending*>& subs) {
         (uint64_t)h->num_cu;
     const bool prof = h->owner && h->owner->prof_on;
     if (prof) HIP_TRY(hipEventRecord(h->pev[0], h->stream));
-    tim::launch_sample_batch(p->model, p->mode, p->wc, tim::JobTable{h->d_jobs + lo, (int)(hi - lo)}, (int)grid0,
+    tim::launch_sample_batch(p->model, p->mode, p->wc, tim::JobTable{h->d_jobs + lo, (int)(hi - lo), 0}, (int)grid0,
                              (int)grid1, h->big_slots, maxc, h->stream, prof ? h->pev[1] : nullptr);
     if (prof) {
       // the profile needs this launch's counters: wait for it

@@ -112,6 +112,7 @@ void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int 
 struct JobTable {
   const SampleArgs* jobs;
   int njobs;
+  int spread;  // 1: wavefronts start spread over the jobs in proportion to their sets (jobs of one graph)
 };
 constexpr int kMaxBatchJobs = 64;
 // Occupancy of the batched tier-0 (tier 0) or tier-1 (tier 1, IC) kernel.

@@ -1336,6 +1336,38 @@ __device__ __forceinline__ uint64_t jobs_with_work(const JobTable& t, int tier, 
   return __ballot(w);
 }
 
+// The job a wavefront starts with.  A wavefront leaves a job only once each
+// of its segments has finished its last set there, so every move costs it
+// its slowest set in flight.  Where the jobs sample one graph (t.spread), a
+// set costs about the same in every job: wavefronts start spread over the
+// jobs in proportion to their sets in `tier`, where their work is, and most
+// make one or two moves instead of walking across every job.  Jobs of
+// different graphs start with equal shares of wavefronts.
+template <int MODEL>
+__device__ __forceinline__ int home_job(const JobTable& t, int tier, unsigned long long wave,
+                                        unsigned long long waves, int lane) {
+  if (!t.spread) return (int)(wave % (unsigned long long)t.njobs);
+  unsigned long long c = 0;
+  if (lane < t.njobs) {
+    const SampleArgs* a = t.jobs + lane;
+    c = a->count;
+    if (tier > 0) {
+      const unsigned long long d = load_ctr(a->ctr + ((MODEL == 0 && tier == 2) ? kCtrList2 : kCtrList1));
+      c = d < c ? d : c;
+    }
+  }
+  unsigned long long incl = c;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const unsigned long long y = __shfl_up(incl, o, kWave);
+    if (lane >= o) incl += y;
+  }
+  const unsigned long long total = __shfl(incl, kWave - 1, kWave);
+  const unsigned long long pos = total * wave / waves;  // total <= 64 * 2^26, wave < 2^31
+  const int j = __popcll(__ballot(lane < t.njobs && incl <= pos));
+  return j < t.njobs ? j : t.njobs - 1;
+}
+
 // The first job of mask m at or after `from`, cyclically; -1 if none.
 __device__ __forceinline__ int next_job(uint64_t m, int from) {
   if (!m) return -1;
@@ -1347,7 +1379,7 @@ template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
 __global__ __launch_bounds__(kSegThreads) void ic_seg_batch_kernel(JobTable t, int tier) {
   const int lane = threadIdx.x % kWave;
   const int wave = blockIdx.x * (kSegThreads / kWave) + threadIdx.x / kWave;
-  int from = wave % t.njobs;
+  int from = home_job<0>(t, tier, (unsigned long long)wave, (unsigned long long)gridDim.x * (kSegThreads / kWave), lane);
   for (;;) {
     const int j = __builtin_amdgcn_readfirstlane(next_job(jobs_with_work<0>(t, tier, lane), from));
     if (j < 0) break;
@@ -1380,7 +1412,7 @@ template <int MODE>
 __global__ __launch_bounds__(kLtWaves* kWave) void lt_lane_batch_kernel(JobTable t) {
   const int lane = threadIdx.x % kWave;
   const int wave = blockIdx.x * kLtWaves + threadIdx.x / kWave;
-  int from = wave % t.njobs;
+  int from = home_job<1>(t, 0, (unsigned long long)wave, (unsigned long long)gridDim.x * kLtWaves, lane);
   for (;;) {
     const int j = __builtin_amdgcn_readfirstlane(next_job(jobs_with_work<1>(t, 0, lane), from));
     if (j < 0) break;
@@ -1394,7 +1426,7 @@ template <int MODE>
 __global__ __launch_bounds__(kChainWaves* kWave) void lt_chain_batch_kernel(JobTable t) {
   const int lane = threadIdx.x % kWave;
   const int wave = blockIdx.x * kChainWaves + threadIdx.x / kWave;
-  int from = wave % t.njobs;
+  int from = home_job<1>(t, 2, (unsigned long long)wave, (unsigned long long)gridDim.x * kChainWaves, lane);
   for (;;) {
     const int j = __builtin_amdgcn_readfirstlane(next_job(jobs_with_work<1>(t, 2, lane), from));
     if (j < 0) break;
