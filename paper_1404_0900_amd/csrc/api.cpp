@@ -936,9 +936,12 @@ float elapsed_ms(tim_ctx* c) {
   return ms;
 }
 
-// Early KptEstimation rounds whose sets together number at most this many run
-// as the jobs of one multi-job launch (kpt_estimate_impl).
+// Early KptEstimation rounds whose sets together number at most kGroupSets
+// run as the jobs of one multi-job launch (kpt_estimate_impl); a later round
+// not predicted to be the last runs paired with the next one while the two
+// number at most kPairSets.
 constexpr uint64_t kGroupSets = 1ull << 19;
+constexpr uint64_t kPairSets = 1ull << 21;
 
 // Width-mode sets of rounds i0..i1 of KptEstimation, one job per round
 // (phase i, sets [0, c_i)), in one multi-job launch; t[r] receives the totals
@@ -1105,10 +1108,13 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
     Totals t;
     const bool predicted = predict(i, ci);
     if (!c->hub && !predicted) {
-      // under a budget, the group's lists (20 bytes per set) take at most an
-      // eighth of the room and are released afterwards, so that what later
-      // rounds and the node pool find is what one round per launch leaves
-      const uint64_t group_cap = c->budget ? std::min(kGroupSets, launch_cap(c) / 2) : kGroupSets;
+      // the rounds of few sets run together (up to kGroupSets sets), a later
+      // round with the next one (up to kPairSets); under a budget, the
+      // group's lists (20 bytes per set) take at most an eighth of the room
+      // and are released afterwards, so that what later rounds and the node
+      // pool find is what one round per launch leaves
+      uint64_t group_cap = std::max(kGroupSets, std::min(3 * ci, kPairSets));
+      if (c->budget) group_cap = std::min(group_cap, launch_cap(c) / 2);
       int j = i;
       uint64_t tot = ci;
       while (j < imax && j - i + 1 < tim::kMaxBatchJobs) {
