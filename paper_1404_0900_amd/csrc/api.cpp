@@ -288,16 +288,19 @@ void hub_submit(Hub* h, Pending* p) {
   h->cv_done.wait(lk, [&] { return p->done; });
 }
 
-// IC width and coverage launches of fewer sets than this (the early
-// KptEstimation rounds) cannot fill the chip with 8-lane segments: they last
-// as long as their largest set takes to cross its BFS levels, so they run the
-// 64-lane shape instead.  Stored sets keep the context's shape, which the
-// node-pool slice bound assumes.
+// IC launches of fewer sets than this cannot fill the chip with 8-lane
+// segments: they last as long as their largest set takes to cross its BFS
+// levels, so they run the 64-lane shape instead.  Stored sets take it too,
+// with the node-pool bound of that shape (tier0_cap), except in the chunked
+// collections, which plan their pool for the context's shape.  Batched
+// launches keep theirs.
 constexpr uint64_t kWideLaunchSets = 262144;
 
 // Lanes per set of the IC first tier for a launch of `count` sets.
 int launch_lanes(const tim_ctx* c, int model, int mode, uint64_t count) {
-  if (c->wide_small && model == TIM_MODEL_IC && mode != tim::kModeEmit && count < kWideLaunchSets) return 64;
+  if (c->wide_small && !c->hub && model == TIM_MODEL_IC && count < kWideLaunchSets &&
+      (mode != tim::kModeEmit || c->emit_wave_sets == 0))
+    return 64;
   return c->seg_lanes;
 }
 
@@ -328,15 +331,18 @@ uint64_t emit_waves(const tim_ctx* c, int model, uint64_t count) {
   return std::max(waves, w2);
 }
 
-// Largest set tier 0 stores (its LDS queue or chain).
-uint64_t tier0_cap(const tim_ctx* c, int model) { return tim::tier0_set_cap(model, c->seg_lanes); }
+// Largest set tier 0 stores (its LDS queue or chain) in emit launches of
+// `count` sets.
+uint64_t tier0_cap(const tim_ctx* c, int model, uint64_t count) {
+  return tim::tier0_set_cap(model, launch_lanes(c, model, tim::kModeEmit, std::min(count, kMaxLaunchSets)));
+}
 
 // Node-pool slice for launches of `count` sets holding about `nodes`
 // entries: about a quarter of a wavefront's share, a power of two between
 // four times the largest tier-0 set and max(slice_cap, that).
 uint32_t pick_slice(const tim_ctx* c, int model, uint64_t count, uint64_t nodes) {
   const uint64_t per_wave = nodes / std::max<uint64_t>(1, emit_waves(c, model, std::min(count, kMaxLaunchSets)));
-  const uint32_t lo = (uint32_t)(4 * tier0_cap(c, model));
+  const uint32_t lo = (uint32_t)(4 * tier0_cap(c, model, count));
   const uint32_t hi = std::max(lo, c->slice_cap);
   uint32_t s = lo;
   while (s < hi && (uint64_t)s * 8 <= per_wave) s <<= 1;
@@ -349,7 +355,7 @@ uint32_t pick_slice(const tim_ctx* c, int model, uint64_t count, uint64_t nodes)
 // crosses a boundary once per slice - cap entries stored plus once more
 // after its last slice, whose rest (at most a slice) is also lost.
 uint64_t pool_need(const tim_ctx* c, int model, uint64_t count, uint64_t nodes, uint32_t slice) {
-  const uint64_t cap = tier0_cap(c, model);
+  const uint64_t cap = tier0_cap(c, model, count);
   const uint64_t launches = (count + kMaxLaunchSets - 1) / kMaxLaunchSets;
   const uint64_t waves = emit_waves(c, model, std::min(count, kMaxLaunchSets));
   const uint64_t boundary = (nodes * cap + (slice - cap) - 1) / (slice - cap);
@@ -769,7 +775,7 @@ tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t
   const uint64_t avail = room - fixed;
   // per chunk set: offsets and size, deferral lists, its nodes with their
   // slice-boundary loss, and its share of the last slices of the wavefronts
-  const double cap = (double)tier0_cap(c, model), slice = 4.0 * cap;
+  const double cap = (double)tier0_cap(c, model, count), slice = 4.0 * cap;
   const double node_bytes = 4.0 * nps * (1.0 + cap / (slice - cap));
   const double slice_per_set = 4.0 * (slice + cap) / (double)c->emit_wave_sets;
   const uint64_t slack_fixed = 4 * (uint64_t)(slice + cap) * 8 + 8 * 256;
