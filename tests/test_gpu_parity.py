@@ -487,9 +487,10 @@ _LARGE = {}
 
 
 @pytest.mark.parametrize("lanes", ["4", "8", "16", "32", "64"])
-def test_large_width_and_cover_launches_every_shape(cfg1, lanes, monkeypatch):
-    # width and coverage launches of 262144 sets or more run the context's first-tier shape (smaller
-    # ones take the 64-lane shape): every shape's widths, sizes, exact kappa sum and coverage count
+def test_large_launches_every_shape(cfg1, lanes, monkeypatch):
+    # width, stored-set and coverage launches of 262144 sets or more run the context's first-tier shape
+    # (smaller ones take the 64-lane shape): every shape's widths, sizes, exact kappa sum, stored sets and
+    # coverage count
     import paper_1404_0900_amd as tim
     monkeypatch.setenv("TIM_IC_SEG_LANES", lanes)
     count, seed, phase, k = 300_000, 4, 11, 5
@@ -499,7 +500,7 @@ def test_large_width_and_cover_launches_every_shape(cfg1, lanes, monkeypatch):
         sid = np.repeat(np.arange(count), np.diff(so))
         hit = np.zeros(count, dtype=bool)
         hit[sid[np.isin(nodes, seeds)]] = True
-        _LARGE.update(so=so, ww=ww, covered=int(hit.sum()),
+        _LARGE.update(so=so, nodes=nodes, ww=ww, covered=int(hit.sum()),
                       kappa=oracle.round_sum(cfg1, IC, seed, phase, 0, count, k)["sum"])
     want = _LARGE
     _say(f"large launches: {lanes} lanes per set")
@@ -512,6 +513,9 @@ def test_large_width_and_cover_launches_every_shape(cfg1, lanes, monkeypatch):
         assert st.width_sum == int(want["ww"].sum()) and st.node_sum == int(want["so"][-1])
         cst = e.sample_cover(dg, IC, seed, phase, 0, count, seeds)
         assert cst.covered == want["covered"]
+        so, nd, w2, st2 = _gpu_sets(e, dg, IC, seed, phase, 0, count)
+        assert np.array_equal(so, want["so"]) and np.array_equal(nd, want["nodes"])
+        assert np.array_equal(w2, want["ww"]) and st2.node_sum == int(want["so"][-1])
 
 
 @pytest.mark.parametrize("lanes", ["4", "16", "32", "64"])
