@@ -315,6 +315,21 @@ def test_tim_plus_cfg2_k50(eng, cfg2, model):
     _run_equal(eng, cfg2, dg, model, 50, 0.2, 1.0, 2)
 
 
+@pytest.mark.parametrize("k", [10, 50])
+def test_grouped_rounds_count_once_and_keep_the_last_round(eng, cfg2, k):
+    # The early KptEstimation rounds run together and the next ones in pairs.  Rounds computed past the
+    # stopping one are dropped and not counted, and the last round, predicted here right after a group
+    # (k = 50) or a pair (k = 10), is stored and reused as R' instead of being generated again: the sets
+    # generated are exactly the rounds up to i_last, theta' and theta.
+    import paper_1404_0900_amd as tim
+    dg = eng.upload(cfg2)
+    _, _, rep = eng.run(dg, IC, k, 0.2, 1.0, 2)
+    r = tim.report_dict(rep, k)
+    _say(f"grouped rounds: k={k} i_last={r['i_last']} sets_total={r['sets_total']}")
+    assert r["i_last"] >= 12
+    assert r["sets_total"] == sum(r["round_c"].values()) + r["theta_prime"] + r["theta"]
+
+
 @pytest.mark.parametrize("model", [IC, LT])
 def test_kpt_cfg2_k1_sampled(eng, cfg2, model):
     # k = 1 takes the oracle minutes end to end; check the GPU's rounds on
