@@ -945,9 +945,11 @@ float elapsed_ms(tim_ctx* c) {
 // Early KptEstimation rounds whose sets together number at most kGroupSets
 // run as the jobs of one multi-job launch (kpt_estimate_impl); a later round
 // not predicted to be the last runs paired with the next one while the two
-// number at most kPairSets.
+// number at most kPairSets (IC) or kPairSetsLt (LT).  Larger IC pairs lose
+// to the single-launch kernel's higher occupancy; LT chains gain up to 2^23.
 constexpr uint64_t kGroupSets = 1ull << 19;
 constexpr uint64_t kPairSets = 1ull << 21;
+constexpr uint64_t kPairSetsLt = 1ull << 23;
 
 // Width-mode sets of rounds i0..i1 of KptEstimation, one job per round
 // (phase i, sets [0, c_i)), in one multi-job launch; t[r] receives the totals
@@ -1119,7 +1121,8 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
       // group's lists (20 bytes per set) take at most an eighth of the room
       // and are released afterwards, so that what later rounds and the node
       // pool find is what one round per launch leaves
-      uint64_t group_cap = std::max(kGroupSets, std::min(3 * ci, kPairSets));
+      const uint64_t pair_cap = model == TIM_MODEL_LT ? kPairSetsLt : kPairSets;
+      uint64_t group_cap = std::max(kGroupSets, std::min(3 * ci, pair_cap));
       if (c->budget) group_cap = std::min(group_cap, launch_cap(c) / 2);
       int j = i;
       uint64_t tot = ci;
