@@ -479,6 +479,77 @@ def test_round_sizes_double():
             assert 2 * a - 1 <= b <= 2 * a
 
 
+@pytest.mark.parametrize("n,ell", [(15000, 1.0), (10**6, 1.0), (41_600_000, 1.0), (10**5, 1.0), (10**7, 1.0),
+                                   (1000, 2.0), (4, 0.5)])
+def test_round_sizes_meet_lemma6_failure_bound(n, ell):
+    # Lemma 6's proof bounds an early stop in round i by exp(-c_i 2^(-i-1) / 3)
+    # and needs it to be at most 1 / (n^ell log2 n): c_i is the least integer
+    # with c_i 2^(-i-1) / 3 >= ell ln n + ln log2 n.
+    target = ell * math.log(n) + math.log(math.log2(n))
+    for i in range(1, max(2, oracle.i_max(n) + 1)):
+        c = oracle.c_i(n, ell, i)
+        assert c * 2.0 ** (-i - 1) / 3 >= target * (1 - 1e-14)
+        assert (c - 1) * 2.0 ** (-i - 1) / 3 < target
+
+
+@pytest.mark.parametrize("n,ell", [(15000, 1.0), (10**6, 1.0), (1000, 2.0)])
+def test_round_sizes_meet_lemma7_bound(n, ell):
+    # Lemma 7's proof: with mu >= 2^-j and i >= j+1 a late round misses its stop
+    # with probability at most exp(-c_i mu / 8) < n^(-ell 2^(i-j-1)) / log2 n.
+    for j in range(1, oracle.i_max(n)):
+        mu = 2.0 ** -j
+        for i in range(j + 1, oracle.i_max(n) + 1):
+            c = oracle.c_i(n, ell, i)
+            assert -c * mu / 8 < -ell * 2 ** (i - j - 1) * math.log(n) - math.log(math.log2(n))
+
+
+def test_first_round_sizes_by_hand():
+    # c_1 = ceil(2 (6 ell ln n + 6 ln log2 n)) at the benchmark sizes, worked by hand:
+    # n = 15000: 2 (57.69 + 6 ln 13.87) = 146.9; n = 10^6: 2 (82.89 + 17.98) = 201.7;
+    # n = 41.6M: 2 (105.2 + 19.45) = 249.3.
+    assert oracle.c_i(15000, 1.0, 1) == 147
+    assert oracle.c_i(10**6, 1.0, 1) == 202
+    assert oracle.c_i(41_600_000, 1.0, 1) == 250
+
+
+@pytest.mark.parametrize("n,k,eps,ell", [(15000, 50, 0.5, 1.0), (10**6, 1, 0.2, 1.0), (10**6, 10, 0.2, 1.0),
+                                         (10**6, 50, 0.2, 1.0), (41_600_000, 50, 0.2, 1.0), (50, 3, 0.1, 2.0)])
+def test_lambda_prime_meets_lemma8_failure_bound(n, k, eps, ell):
+    # Lemma 8's proof: with theta' = lambda'/KPT* the event f n > (1+eps') OPT has
+    # probability at most exp(-eps'^2 lambda' / ((2+eps') n)), which must be n^-ell.
+    ep = oracle.eps_prime(k, eps, ell)
+    lp = oracle.lambda_prime(n, ep, ell)
+    assert -ep * ep * lp / ((2 + ep) * n) == pytest.approx(-ell * math.log(n), rel=1e-12)
+
+
+def _eps_prime_hand_values():
+    rows = []
+    with open(os.path.join(GOLDEN, "eps_prime_hand_values.txt")) as f:
+        for line in f:
+            if line.strip() and not line.startswith("#"):
+                k, eps, ell, want = line.split()
+                rows.append((int(k), float(eps), float(ell), want))
+    return rows
+
+
+@pytest.mark.parametrize("k,eps,ell,want", _eps_prime_hand_values())
+def test_eps_prime_hand_values(k, eps, ell, want):
+    got = oracle.eps_prime(k, eps, ell)
+    assert f"{got:.4g}" == f"{float(want):.4g}"
+
+
+def test_eps_prime_scales_as_a_cube_root():
+    # The rule of Section 4.1 grows as eps^(2/3) and ell^(1/3) and falls as (k+ell)^(-1/3);
+    # for every eps <= 1 it stays above eps / sqrt(k), where TIM+ keeps TIM's time bound.
+    for k in (1, 3, 10, 50, 100):
+        for eps in (0.05, 0.1, 0.2, 0.5, 1.0):
+            a = oracle.eps_prime(k, eps, 1.0)
+            assert oracle.eps_prime(k, eps / 8, 1.0) == pytest.approx(a / 4, rel=1e-14)
+            assert oracle.eps_prime(8 * k + 7, eps, 1.0) == pytest.approx(a / 2, rel=1e-14)
+            assert oracle.eps_prime(8 * k, eps, 8.0) == pytest.approx(a, rel=1e-14)
+            assert a >= eps / math.sqrt(k)
+
+
 # ------------------------------------------------ closed-form pipeline --
 @pytest.mark.parametrize("n", [16, 50])
 @pytest.mark.parametrize("model", [IC, LT])
