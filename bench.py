@@ -60,13 +60,13 @@ MODES = ("widths", "store", "cover")
 # picks on this graph.  Valid only for the kernel sources they were taken on.
 TRAFFIC = {
     "ic_seg_kernel<1, true, 8, 128, 0, 512, 1> (store)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "fetch_bytes": 3318178006, "write_bytes": 556814720},
+        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3318178006, "write_bytes": 556814720},
     "ic_seg_kernel<1, true, 16, 128, 8, 512, 1> (store)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "fetch_bytes": 3273551591, "write_bytes": 437677184},
+        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3273551591, "write_bytes": 437677184},
     "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "fetch_bytes": 3070146813, "write_bytes": 90828587},
+        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3070146813, "write_bytes": 90828587},
     "ic_seg_kernel<0, true, 16, 128, 8, 512, 1> (widths)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "fetch_bytes": 3060404808, "write_bytes": 69464651},
+        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3060404808, "write_bytes": 69464651},
 }
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/pick.hpp", "paper_1404_0900_amd/csrc/engine.hpp")
@@ -147,12 +147,15 @@ def main():
         tune = eng.autotune(dg, tim.IC, 1 << 22)
     log(f"sampler shape: {tune.seg_lanes} lanes per set, slice cap {tune.slice_cap}")
 
+    last = {}  # per k: seeds, gains and report of the last run (compared with the oracle below)
+
     def step():
         out = []
         for k in KS:
             t0 = time.perf_counter()
             seeds, gains, rep = eng.run(dg, tim.IC, k, EPS, ELL, SEED)
             out.append((k, time.perf_counter() - t0, rep))
+            last[k] = (seeds, gains, rep)
         return out
 
     phases = {}  # per k: GPU milliseconds of each phase and the collection sizes (last timed step)
@@ -191,6 +194,12 @@ def main():
             return t["fetch_bytes"] + t["write_bytes"]
         return None
     roofline = dominant_roofline(prof, name_of, traffic_of)
+    t = TRAFFIC.get(roofline["kernel"])
+    roofline["traffic_source"] = (
+        f"stored figure: rocprofv3 FETCH_SIZE and WRITE_SIZE runs of {t['taken']} on kernel sources "
+        f"{t['sources_sha256_16']} (profiles/), scaled by a plain-copy calibration"
+        if roofline["traffic"] is not None else
+        "null: no counter run on the current kernel sources " + sources_sha())
     sampler_ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
     sampler_ms += sum(prof.ic_wide[b].kernel_ms + prof.ic_wide[b].large_ms for b in (0, 1, 2))
     sampler_ms += sum(prof.grouped[a].kernel_ms + prof.grouped[a].large_ms for a in (0, 1))
@@ -250,6 +259,7 @@ def main():
     line["lt_weighted"] = {"sets_per_s": round(lw_sets / (time.perf_counter() - t0), 1), "tim_plus_s": lw_per_k}
     eng.set_lt_weights(dg, g, None)
 
+    line["parity"] = None
     if not args.no_cpu_baseline:
         import oracle
         log("timing the CPU oracle: one TIM+ run, IC, k=50")
@@ -260,9 +270,49 @@ def main():
         line["cpu_baseline"] = {
             "value": round(osets / dt, 1), "unit": "RR sets/s", "cores": 1, "kind": "oracle",
             "sample": f"one oracle TIM+ run (IC, k=50) on the same graph: {osets} RR sets in {dt:.2f} s",
+            "cpu_model": cpu_model(), "host_cpus": host_cpus(),
         }
+        line["parity"] = parity_with_oracle(tim, last[50], r, 50)
+        log(f"parity of the last timed k=50 run with the oracle: {line['parity']}")
     eng.close()
     print(json.dumps(line), flush=True)
+
+
+def cpu_model():
+    """The host CPU's model name (Linux /proc/cpuinfo), or None."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_cpus():
+    """CPUs this process may run on, and the machine's count."""
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count()
+    return {"usable": usable, "online": os.cpu_count()}
+
+
+def parity_with_oracle(tim, gpu, want, k):
+    """Bit-exact comparison of one GPU TIM+ run (seeds, gains, report) with the oracle's."""
+    import numpy as np
+    seeds, gains, rep = gpu
+    r = tim.report_dict(rep, k)
+    fields = ["i_last", "c_last", "kpt_star", "round_sums", "theta_prime", "covered_prime", "kpt_prime", "kpt_plus",
+              "theta", "ns_nodes", "ns_width", "ns_covered"]
+    bad = [f for f in fields if r[f] != want[f]]
+    if not np.array_equal(seeds, want["seeds"]):
+        bad.append("seeds")
+    if not np.array_equal(gains, want["gains"]):
+        bad.append("gains")
+    return {"run": f"IC k={k} eps={EPS} ell={ELL} seed={SEED}, last timed step", "identical": not bad,
+            "compared": fields + ["seeds", "gains"], "mismatch": bad}
 
 
 def sampler_by_mode(prof, model):

@@ -436,6 +436,8 @@ def report_dict(rep: Report, k: int) -> dict:
         ell_used=rep.ell_used, **{"lambda": rep.lambda_},
         i_max=kp.i_max, i_last=kp.i_last, c_last=int(kp.c_last), kpt_star=kp.kpt_star, round_sums=kp.round_sums(),
         round_c={i: int(kp.round_c[i]) for i in range(1, kp.i_last + 1)},
+        round_width={i: int(kp.round_width[i]) for i in range(1, kp.i_last + 1)},
+        round_nodes={i: int(kp.round_nodes[i]) for i in range(1, kp.i_last + 1)},
         eps_prime=rep.refine.eps_prime, lambda_prime=rep.refine.lambda_prime,
         theta_prime=int(rep.refine.theta_prime), covered_prime=int(rep.refine.covered_prime),
         kpt_prime=rep.refine.kpt_prime, kpt_plus=rep.refine.kpt_plus,

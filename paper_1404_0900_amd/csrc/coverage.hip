@@ -584,7 +584,11 @@ void launch_argmax_step(const GreedyArgs& a, int j, hipStream_t s) {
 }
 
 void launch_cover_step(const GreedyArgs& a, int j, hipStream_t s) {
-  if (!a.nsets) return;
+  if (!a.nsets) {
+    // nothing to cover, but the choice must still leave the candidates
+    hipLaunchKernelGGL(select_kernel, dim3(1), dim3(64), 0, s, a.best + j, a.selected);
+    return;
+  }
   // the chosen node's list holds at most nsets sets: no more blocks than its tiles
   const dim3 grid((unsigned)std::min<uint64_t>(1024, (a.nsets + kTileSets - 1) / kTileSets));
   if (a.set_off)

@@ -221,6 +221,18 @@ def test_max_coverage_random_collections(eng):
         assert np.array_equal(seeds, ws) and np.array_equal(gains, wg), trial
 
 
+@pytest.mark.parametrize("k", [1, 2, 5])
+def test_max_coverage_empty_collection(eng, k):
+    # no sets: every gain is 0 and the tie rule takes the lowest unselected ids
+    import torch
+    off = _dev([0], torch.int64)
+    nodes = _dev(np.zeros(0, dtype=np.int32), torch.int32)
+    seeds, gains = eng.max_coverage(7, off, nodes, k)
+    ws, wg = oracle.greedy(7, np.zeros(1, dtype=np.int64), np.zeros(0, dtype=np.int32), k)
+    assert list(ws) == list(range(k))
+    assert np.array_equal(seeds, ws) and np.array_equal(gains, wg)
+
+
 def test_max_coverage_rejects_bad_ids(eng):
     import torch
 
@@ -313,6 +325,48 @@ def test_tim_plus_degenerate_graphs(eng, model):
 def test_tim_plus_cfg2_k50(eng, cfg2, model):
     dg = eng.upload(cfg2)
     _run_equal(eng, cfg2, dg, model, 50, 0.2, 1.0, 2)
+
+
+def _golden_timplus():
+    import json
+    import os
+    with open(os.path.join(os.path.dirname(__file__), "golden", "timplus_chunglu_n1e6_m1e7_k1_k10.json")) as f:
+        return json.load(f)
+
+
+def _decode(v):
+    if isinstance(v, str):
+        return float.fromhex(v)
+    if isinstance(v, dict):
+        return {int(i): x for i, x in v.items()}
+    return v
+
+
+@pytest.mark.parametrize("model", [IC, LT])
+@pytest.mark.parametrize("k", [1, 10])
+def test_tim_plus_cfg2_k1_k10_against_stored_oracle(eng, cfg2, model, k):
+    # The oracle needs minutes for these runs, so its results come from
+    # tests/golden/make_timplus_golden.py (oracle only), stored with the graph's hash.
+    import hashlib
+
+    import paper_1404_0900_amd as tim
+    doc = _golden_timplus()
+    h = hashlib.sha256()
+    h.update(cfg2.off.astype("<i8").tobytes())
+    h.update(cfg2.src.astype("<i4").tobytes())
+    assert doc["graph"]["sha256"] == h.hexdigest(), "stored oracle values belong to another graph"
+    want = {key: _decode(v) for key, v in
+            next(r["result"] for r in doc["runs"] if r["model"] == model and r["k"] == k).items()}
+    dg = eng.upload(cfg2)
+    _say(f"tim_run: cfg2 model={model} k={k} against the stored oracle run")
+    seeds, gains, rep = eng.run(dg, model, k, doc["eps"], doc["ell"], doc["seed"])
+    r = tim.report_dict(rep, k)
+    assert list(seeds) == want["seeds"] and [int(x) for x in gains] == want["gains"]
+    for key in ("ell_used", "lambda", "i_max", "i_last", "c_last", "kpt_star", "round_sums", "round_c",
+                "round_width", "round_nodes", "eps_prime", "lambda_prime", "theta_prime", "covered_prime",
+                "kpt_prime", "kpt_plus", "theta", "ns_nodes", "ns_width", "ns_covered"):
+        assert r[key] == want[key], key
+    assert [int(x) for x in r["s_prime"][:k]] == want["s_prime"][:128]
 
 
 @pytest.mark.parametrize("k", [10, 50])
