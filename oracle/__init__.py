@@ -19,7 +19,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
 _lib = None
 
-IC, LT = 0, 1
+IC, LT, TRIGGER = 0, 1, 2
 PHASE_REFINE, PHASE_SELECT = 63, 64
 FLAG_PLAIN, FLAG_ELL_ADJUST = 1, 2
 _MAX_ROUNDS = 64
@@ -86,6 +86,8 @@ def _load():
         "orc_wc_threshold": (ctypes.c_uint32, [ctypes.c_int64]),
         "orc_lt_pick": (ctypes.c_int64, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64,
                                          ctypes.c_int64]),
+        "orc_trig_pick": (ctypes.c_int64, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int64, _P,
+                                           _P]),
         "orc_lt_pick_cumulative": (ctypes.c_int64, [ctypes.c_uint64, ctypes.c_uint32, ctypes.c_uint64,
                                                     ctypes.c_int64, _P, ctypes.c_int64]),
         "orc_forward_spread": (ctypes.c_int, _G + [ctypes.c_int, ctypes.c_uint64, ctypes.c_uint64, ctypes.c_uint64,
@@ -128,14 +130,40 @@ def _load():
     return lib
 
 
+class _TriggerC(ctypes.Structure):
+    """orc_trigger: the explicit triggering distribution of reading R11 (model 2)."""
+    _fields_ = [("toff", ctypes.c_void_p), ("tthr", ctypes.c_void_p), ("tset", ctypes.c_void_p),
+                ("tmem", ctypes.c_void_p)]
+
+
+class _TriggerArg:
+    """A triggering distribution handed to the C code in place of a threshold array."""
+
+    def __init__(self, t):
+        arrs = [np.ascontiguousarray(t.toff, dtype=np.int64), np.ascontiguousarray(t.tthr, dtype=np.uint32),
+                np.ascontiguousarray(t.tset, dtype=np.int64), np.ascontiguousarray(t.tmem, dtype=np.uint32)]
+        self.arrays = tuple(a if a.size else np.zeros(1, dtype=a.dtype) for a in arrs)
+        self.c = _TriggerC(*(a.ctypes.data for a in self.arrays))
+        self.address = ctypes.addressof(self.c)
+
+
 def _ptr(a):
-    return None if a is None else a.ctypes.data
+    if a is None:
+        return None
+    if isinstance(a, _TriggerArg):
+        return a.address
+    return a.ctypes.data
 
 
 def _garr(g, thr):
     off = np.ascontiguousarray(g.off, dtype=np.int64)
     src = np.ascontiguousarray(g.src, dtype=np.int32)
-    t = None if thr is None else np.ascontiguousarray(thr, dtype=np.uint32)
+    if thr is None:
+        t = None
+    elif hasattr(thr, "tmem"):  # a triggering distribution (model 2, reading R11)
+        t = _TriggerArg(thr)
+    else:
+        t = np.ascontiguousarray(thr, dtype=np.uint32)
     return off, src, t
 
 
@@ -172,6 +200,12 @@ def wc_threshold(d) -> int:
 
 def lt_pick(seed, phase, set_id, v, d) -> int:
     return int(_load().orc_lt_pick(seed, phase, set_id, v, d))
+
+
+def trig_pick(seed, phase, set_id, v, trig) -> int:
+    """Outcome index (into trig.tthr / trig.tset) that node v draws under reading R11, or -1 (empty set)."""
+    a = _TriggerArg(trig)
+    return int(_load().orc_trig_pick(seed, phase, set_id, v, a.arrays[0].ctypes.data, a.arrays[1].ctypes.data))
 
 
 def lt_pick_cumulative(seed, phase, set_id, v, t) -> int:

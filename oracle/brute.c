@@ -16,6 +16,11 @@
  * at most one in-edge: without thresholds each with probability 1/d; with
  * cumulative thresholds t_0 <= .. <= t_{d-1} edge j with probability
  * (t_j - t_{j-1}) / 2^32 (t_{-1} = -1) and none with (2^32 - 1 - t_{d-1}) / 2^32.
+ * General triggering (model 2, the explicit distributions of the oracle's
+ * reading R11; Section 4.2): node v takes outcome j (its member in-edges are
+ * live) with probability (t_j - t_{j-1}) / 2^32, and no in-edge with the rest.
+ * For model 2 the thr argument is the address of the distribution (the
+ * oracle's orc_trigger layout).
  * Node sets are bit masks, so n <= 20.
  */
 #include <math.h>
@@ -23,8 +28,20 @@
 #include <stdlib.h>
 #include <string.h>
 
+#define MAX_TRIG 16 /* outcomes per node, the empty one included */
+
+typedef struct {
+  const int64_t *toff;
+  const uint32_t *tthr;
+  const int64_t *tset;
+  const uint32_t *tmem;
+} btrigger;
+
 typedef struct {
   int n, m;
+  int trig_choices[32];                 /* triggering outcomes at v (0: none) */
+  uint64_t trig_live[32][MAX_TRIG];     /* live in-edges of each outcome */
+  long double trig_p[32][MAX_TRIG];     /* its probability */
   int eu[64], ev[64]; /* edge e: eu[e] -> ev[e] */
   int indeg[32];
   long double p[64];  /* IC keep probability */
@@ -33,8 +50,37 @@ typedef struct {
   long double lt_p[64 + 32]; /* LT: probability of outcome c of v at lt_p[first_in[v] + v + c] */
 } bgraph;
 
-static int load(bgraph *g, int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr) {
+static int load_trigger(bgraph *g, const int64_t *off, const btrigger *tr) {
+  for (int v = 0; v < g->n; ++v) {
+    int c = 0;
+    int64_t prev = -1;
+    for (int64_t j = tr->toff[v]; j < tr->toff[v + 1]; ++j) {
+      if (c >= MAX_TRIG - 1) return -1;
+      uint64_t live = 0;
+      for (int64_t i = tr->tset[j]; i < tr->tset[j + 1]; ++i) live |= (uint64_t)1 << (off[v] + tr->tmem[i]);
+      g->trig_live[v][c] = live;
+      g->trig_p[v][c] = (long double)((int64_t)tr->tthr[j] - prev) / 4294967296.0L;
+      prev = (int64_t)tr->tthr[j];
+      ++c;
+    }
+    if (prev < 0xFFFFFFFFLL) {
+      g->trig_live[v][c] = 0;
+      g->trig_p[v][c] = (long double)(0xFFFFFFFFLL - prev) / 4294967296.0L;
+      ++c;
+    }
+    g->trig_choices[v] = c;
+  }
+  return 0;
+}
+
+static int load(bgraph *g, int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr,
+                int model) {
   if (n < 1 || n > 20 || m < 0 || m > 63) return -1;
+  const btrigger *tr = NULL;
+  if (model == 2) {
+    tr = (const btrigger *)(const void *)thr;
+    thr = NULL;
+  }
   g->n = (int)n;
   g->m = (int)m;
   for (int v = 0; v < n; ++v) {
@@ -67,6 +113,7 @@ static int load(bgraph *g, int64_t n, int64_t m, const int64_t *off, const int32
     }
   }
   g->first_in[n] = (int)m;
+  if (tr) return load_trigger(g, off, tr);
   return 0;
 }
 
@@ -100,6 +147,30 @@ static int64_t for_each_world(const bgraph *g, int model, world_fn fn, void *ctx
       fn(g, live, prob, ctx);
     }
     return (int64_t)worlds;
+  }
+  if (model == 2) {
+    /* a mixed-radix counter over the triggering outcome at each node */
+    int tc[32];
+    int64_t tw = 1;
+    for (int v = 0; v < g->n; ++v) {
+      tc[v] = 0;
+      tw *= g->trig_choices[v];
+      if (tw > ((int64_t)1 << 26)) return -1;
+    }
+    for (int64_t w = 0; w < tw; ++w) {
+      uint64_t live = 0;
+      long double prob = 1.0L;
+      for (int v = 0; v < g->n; ++v) {
+        live |= g->trig_live[v][tc[v]];
+        prob *= g->trig_p[v][tc[v]];
+      }
+      if (prob != 0.0L) fn(g, live, prob, ctx);
+      for (int v = 0; v < g->n; ++v) {
+        if (++tc[v] < g->trig_choices[v]) break;
+        tc[v] = 0;
+      }
+    }
+    return tw;
   }
   /* LT: a mixed-radix counter over the outcome at each node (one of its
    * in-edges, or none) */
@@ -150,7 +221,7 @@ static void spread_world(const bgraph *g, uint64_t live, long double prob, void 
 int brute_all_spreads(int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr, int model,
                       double *out) {
   bgraph g;
-  if (load(&g, n, m, off, src, thr) || n > 16) return -1;
+  if (load(&g, n, m, off, src, thr, model) || n > 16) return -1;
   uint32_t full = 1u << n;
   spread_ctx c;
   c.acc = (long double *)calloc(full, sizeof(long double));
@@ -195,7 +266,7 @@ static void rr_world(const bgraph *g, uint64_t live, long double prob, void *vct
 int brute_rr_stats(int64_t n, int64_t m, const int64_t *off, const int32_t *src, const uint32_t *thr, int model, int k,
                    double *p_in, double *ew, double *ekappa, double *esize) {
   bgraph g;
-  if (load(&g, n, m, off, src, thr) || m < 1) return -1;
+  if (load(&g, n, m, off, src, thr, model) || m < 1) return -1;
   rr_ctx c;
   memset(&c, 0, sizeof(c));
   c.k = k;

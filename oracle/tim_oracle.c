@@ -26,7 +26,8 @@
  *   R1 random numbers: Philox4x32-10 (Salmon et al., SC'11).  key = (seed lo,
  *      seed hi); counter = (idx lo, phase<<24 | kind<<16 | (idx>>32 & 0xFFFF),
  *      set lo, set hi).  kind 0 = root (idx 0), 1 = IC coin group (idx = e>>2,
- *      output word e&3), 2 = LT pick (idx = node).  phase i in [1,62] =
+ *      output word e&3), 2 = LT pick (idx = node), 3 = triggering-set pick
+ *      (idx = node, reading R11).  phase i in [1,62] =
  *      KptEstimation round i, 63 = RefineKPT's fresh sets, 64 = NodeSelection.
  *   R2 an IC edge e is live iff its 32-bit word x satisfies x <= t(e), where
  *      t(e) = floor(p(e) * 2^32) - 1 is the edge's uint32 threshold; under the
@@ -43,9 +44,21 @@
  *      probability (t_j - t_{j-1}) / 2^32 with t_{-1} = -1.
  *  R10 spread evaluation (the live-edge view of Section 2.2; Monte-Carlo runs
  *      as in the paper's experiments, Section 7): run r uses the live-edge
- *      world of phase 65 and set id r, with the coins and picks of R2, R4 and
- *      R9.  Its spread is the number of nodes reachable from S along live
+ *      world of phase 65 and set id r, with the coins and picks of R2, R4,
+ *      R9 and R11.  Its spread is the number of nodes reachable from S along live
  *      edges (S included); E[I(S)] is estimated by the mean over runs.
+ *  R11 general triggering model (Section 4.2): each node v draws its
+ *      triggering set T(v), a subset of its in-neighbours, from a distribution
+ *      given explicitly as outcomes j in [toff[v], toff[v+1]) with uint32
+ *      cumulative thresholds tthr[j] (t_j = floor(C_j * 2^32) - 1 for the
+ *      cumulative probability C_j, non-decreasing within v) and members
+ *      tmem[tset[j] .. tset[j+1]): local in-edge indices i (the in-edge
+ *      off[v] + i), increasing within an outcome.  With x = word0 of the draw
+ *      of kind 3 at (phase, set, idx = v), T(v) is the first outcome with
+ *      x <= t_j, and empty if there is none (probability 1 - C_last).  The RR
+ *      set is the randomized BFS of Section 4.2: every dequeued node draws its
+ *      T(v) and its unvisited members are queued.  Entry points take, for
+ *      model 2, the address of an orc_trigger in place of their thr argument.
  *   R5 kappa in IEEE binary64 without contraction: q = 1 - w/m, r = q^k by
  *      binary exponentiation (r=1,b=q; per bit: if set r*=b; shift; if more
  *      bits b*=b), kappa = 1 - r.  kappa*2^53 is an integer; the round sum is
@@ -142,6 +155,25 @@ int64_t orc_lt_pick_cumulative(uint64_t seed, uint32_t phase, uint64_t set, int6
   return -1;
 }
 
+/* The triggering distribution of reading R11. */
+typedef struct {
+  const int64_t *toff;  /* n+1 */
+  const uint32_t *tthr; /* one per outcome */
+  const int64_t *tset;  /* outcomes + 1 */
+  const uint32_t *tmem; /* local in-edge indices */
+} orc_trigger;
+
+/* Outcome drawn at node v under reading R11 (an index into tthr / tset), or
+ * -1 for the empty triggering set. */
+int64_t orc_trig_pick(uint64_t seed, uint32_t phase, uint64_t set, int64_t v, const int64_t *toff,
+                      const uint32_t *tthr) {
+  uint32_t x[4];
+  orc_draw(seed, phase, 3, (uint64_t)v, set, x);
+  for (int64_t j = toff[v]; j < toff[v + 1]; ++j)
+    if (x[0] <= tthr[j]) return j;
+  return -1;
+}
+
 /* ------------------------------------------------------------------------- */
 /* Graph and per-set workspace.                                              */
 /* ------------------------------------------------------------------------- */
@@ -217,6 +249,22 @@ static int64_t rr_set(const orc_graph *g, int model, uint64_t seed, uint32_t pha
           w->mark[u] = w->stamp;
           w->queue[len++] = u;
         }
+      }
+    }
+  } else if (model == 2) {
+    const orc_trigger *tr = (const orc_trigger *)(const void *)g->thr;
+    int64_t head = 0;
+    while (head < len) {
+      int64_t v = w->queue[head++];
+      int64_t a = g->off[v];
+      wsum += (uint64_t)(g->off[v + 1] - a);
+      int64_t j = orc_trig_pick(seed, phase, set, v, tr->toff, tr->tthr);
+      if (j < 0) continue;
+      for (int64_t i = tr->tset[j]; i < tr->tset[j + 1]; ++i) {
+        int32_t u = g->src[a + tr->tmem[i]];
+        if (w->mark[u] == w->stamp) continue;
+        w->mark[u] = w->stamp;
+        w->queue[len++] = u;
       }
     }
   } else {
@@ -614,6 +662,14 @@ enum { ORC_PHASE_EVAL = 65 };
 static int edge_live_in_world(const orc_graph *g, int model, uint64_t seed, uint32_t phase, uint64_t run,
                               int64_t v, int64_t a, int64_t d, int64_t e) {
   if (model == 0) return edge_is_live(g, seed, phase, run, e, d);
+  if (model == 2) {
+    const orc_trigger *tr = (const orc_trigger *)(const void *)g->thr;
+    int64_t jt = orc_trig_pick(seed, phase, run, v, tr->toff, tr->tthr);
+    if (jt < 0) return 0;
+    for (int64_t i = tr->tset[jt]; i < tr->tset[jt + 1]; ++i)
+      if (a + (int64_t)tr->tmem[i] == e) return 1;
+    return 0;
+  }
   int64_t j = g->thr ? orc_lt_pick_cumulative(seed, phase, run, v, g->thr + a, d) : orc_lt_pick(seed, phase, run, v, d);
   return j >= 0 && a + j == e;
 }

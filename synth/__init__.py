@@ -133,6 +133,66 @@ def random_lt_thresholds(g: Graph, seed: int, total=None) -> np.ndarray:
     return np.clip(t, 0, 0xFFFFFFFF).astype(np.uint32)
 
 
+@dataclass
+class Triggering:
+    """An explicit triggering distribution per node (general triggering model, Section 4.2): the outcomes of v
+    are j in [toff[v], toff[v+1]) with uint32 cumulative thresholds tthr[j] (t_j = floor(C_j * 2^32) - 1 for
+    the cumulative probability C_j), and outcome j's triggering set is the in-edges off[v] + tmem[i] for i in
+    [tset[j], tset[j+1]) (local in-edge indices, increasing).  Probability left over is the empty set."""
+    toff: np.ndarray  # int64[n+1]
+    tthr: np.ndarray  # uint32[J]
+    tset: np.ndarray  # int64[J+1]
+    tmem: np.ndarray  # uint32[total]
+
+
+def random_triggering(g: Graph, seed: int, max_outcomes: int = 4, max_size: int = 3, mass=(0.3, 0.8),
+                      p_full: float = 0.25) -> Triggering:
+    """A random triggering distribution for every node of g.
+
+    A node of in-degree d >= 1 gets 1..max_outcomes outcomes (uniform); each outcome is a uniformly drawn
+    subset of 1..min(d, max_size) of its in-edges (outcomes may repeat a subset).  Outcome weights are
+    integers uniform in [1, 2^16]; the node's total probability F / 2^16 is 1 with probability p_full,
+    else F is uniform in [mass[0] * 2^16, mass[1] * 2^16].  With S_j the sum of the first j+1 weights and
+    S their sum, t_j = floor(S_j * F * 2^16 / S) - 1 in exact integers (clamped to >= 0)."""
+    rng = np.random.default_rng(seed)
+    d = np.diff(g.off).astype(np.int64)
+    nout = np.where(d > 0, rng.integers(1, max_outcomes + 1, size=g.n), 0).astype(np.int64)
+    toff = np.zeros(g.n + 1, dtype=np.int64)
+    toff[1:] = np.cumsum(nout)
+    J = int(toff[-1])
+    od = np.repeat(d, nout)  # in-degree of each outcome's node
+    size = 1 + (rng.integers(0, 2**31, size=J) % np.minimum(od, max_size))
+    # up to three distinct local indices per outcome (sequential draws skipping the ones taken)
+    r = rng.integers(0, 2**62, size=(J, 3))
+    a = r[:, 0] % od
+    b = r[:, 1] % np.maximum(od - 1, 1)
+    b = np.where(b >= a, b + 1, b)
+    lo_ab, hi_ab = np.minimum(a, b), np.maximum(a, b)
+    c = r[:, 2] % np.maximum(od - 2, 1)
+    c = np.where(c >= lo_ab, c + 1, c)
+    c = np.where(c >= hi_ab, c + 1, c)
+    picks = np.stack([a, b, c], axis=1)
+    keep = np.arange(3)[None, :] < size[:, None]
+    picks = np.where(keep, picks, np.iinfo(np.int64).max)
+    picks.sort(axis=1)
+    tset = np.zeros(J + 1, dtype=np.int64)
+    tset[1:] = np.cumsum(size)
+    tmem = picks[keep].astype(np.uint32) if J else np.zeros(0, dtype=np.uint32)
+    # cumulative thresholds
+    w = rng.integers(1, 2**16 + 1, size=J).astype(object)
+    full = rng.random(g.n) < p_full
+    F = np.where(full, 2**16, rng.integers(int(mass[0] * 2**16), int(mass[1] * 2**16) + 1, size=g.n))
+    tthr = np.zeros(J, dtype=np.uint32)
+    for v in np.flatnonzero(nout):
+        j0, j1 = int(toff[v]), int(toff[v + 1])
+        ws = [int(x) for x in w[j0:j1]]
+        S, acc = sum(ws), 0
+        for j, x in enumerate(ws):
+            acc += x
+            tthr[j0 + j] = max(0, (acc * int(F[v]) * 2**16) // S - 1)
+    return Triggering(toff, tthr, tset, tmem)
+
+
 def random_small_graph(n: int, m: int, seed: int) -> Graph:
     """Uniform random simple digraph with exactly m edges (tiny sizes, for exhaustive tests)."""
     rng = np.random.default_rng(seed)

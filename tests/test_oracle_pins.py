@@ -17,7 +17,7 @@ import oracle
 import synth
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
-IC, LT = oracle.IC, oracle.LT
+IC, LT, TRIG = oracle.IC, oracle.LT, oracle.TRIGGER
 
 
 def _read_kat():
@@ -172,6 +172,12 @@ def _live_world(g, model, seed, phase, s, thr):
             t = thr[e] if thr is not None else (2**32 // indeg[v]) - 1
             if oracle.coin_word(seed, phase, s, e) <= t:
                 live.append((u, v))
+    elif model == TRIG:
+        for v in range(g.n):
+            j = oracle.trig_pick(seed, phase, s, v, thr)
+            if j >= 0:
+                for i in range(int(thr.tset[j]), int(thr.tset[j + 1])):
+                    live.append((int(g.src[g.off[v] + int(thr.tmem[i])]), v))
     else:
         for v in range(g.n):
             d = g.off[v + 1] - g.off[v]
@@ -185,13 +191,15 @@ def _live_world(g, model, seed, phase, s, thr):
     return live
 
 
-@pytest.mark.parametrize("model", [IC, LT, "LT-weighted"])
+@pytest.mark.parametrize("model", [IC, LT, "LT-weighted", TRIG])
 @pytest.mark.parametrize("gseed", [1, 2, 3])
 def test_rr_set_is_reverse_reachable_set(model, gseed):
     g = synth.random_small_graph(9, 24, gseed)
     thr = synth.random_thresholds(g.m, gseed, choices=[0x3FFFFFFF, 0x7FFFFFFF, 0xBFFFFFFF]) if model == IC else None
     if model == "LT-weighted":
         model, thr = LT, synth.random_lt_thresholds(g, gseed, total=0.8)
+    if model == TRIG:
+        thr = synth.random_triggering(g, gseed)
     indeg = g.indeg()
     for s in range(60):
         nodes, w = oracle.rr_set(g, model, 77, 64, s, thr=thr)
@@ -225,6 +233,70 @@ def test_p_one_gives_ancestors_in_g():
         root = oracle.root(1, 2, s, g.n)
         nodes, w = oracle.rr_set(g, IC, 1, 2, s, thr=thr)
         assert list(nodes) == list(np.flatnonzero(reach[:, root]))
+
+
+def _trigger_of(g, outcomes):
+    """A triggering distribution from, per node, a list of (probability numerator over 2^32, local indices)."""
+    toff, tthr, tset, tmem = [0], [], [0], []
+    for v in range(g.n):
+        acc = 0
+        for num, members in outcomes(v, int(g.off[v + 1] - g.off[v])):
+            acc += num
+            tthr.append(acc - 1)
+            tmem.extend(members)
+            tset.append(len(tmem))
+        toff.append(len(tthr))
+    return synth.Triggering(np.array(toff, dtype=np.int64), np.array(tthr, dtype=np.uint32),
+                            np.array(tset, dtype=np.int64), np.array(tmem, dtype=np.uint32))
+
+
+def test_trigger_pick_follows_the_distribution():
+    # three outcomes of probability 1/8, 3/8, 1/4 and the empty set with the remaining 1/4
+    g = synth.from_edges(4, [(1, 0), (2, 0), (3, 0)])
+    tr = _trigger_of(g, lambda v, d: [(2**29, [0]), (3 * 2**29, [1, 2]), (2**30, [0, 2])] if v == 0 else [])
+    N = 40000
+    picks = np.array([oracle.trig_pick(9, 64, s, 0, tr) for s in range(N)])
+    counts = np.array([(picks == j).sum() for j in range(3)] + [(picks == -1).sum()])
+    p = np.array([1 / 8, 3 / 8, 1 / 4, 1 / 4])
+    chi2 = ((counts - N * p) ** 2 / (N * p)).sum()
+    assert chi2 < 25.0  # 3 degrees of freedom
+    # the pick compares word 0 of the kind-3 draw with each threshold, inclusively
+    for s in range(30):
+        x = oracle.draw(9, 64, 3, 0, s)[0]
+        if 1 <= x <= 0xFFFFFFFE:
+            t = _trigger_of(g, lambda v, d: [(x, [0]), (1, [1]), (0xFFFFFFFF - x, [2])] if v == 0 else [])
+            assert oracle.trig_pick(9, 64, s, 0, t) == 1  # x <= t_1 = x, x > t_0 = x - 1
+
+
+def test_trigger_with_every_in_edge_certain_gives_ancestors_in_g():
+    # one outcome holding all in-edges with probability 1: the RR set is the set of ancestors in G
+    g = synth.random_small_graph(12, 30, 6)
+    tr = _trigger_of(g, lambda v, d: [(2**32, list(range(d)))] if d else [])
+    reach = np.eye(g.n, dtype=bool)
+    for u, v in synth.edge_list(g):
+        reach[u, v] = True
+    for k in range(g.n):
+        reach |= reach[:, k:k + 1] & reach[k:k + 1, :]
+    indeg = g.indeg()
+    for s in range(40):
+        root = oracle.root(3, 5, s, g.n)
+        nodes, w = oracle.rr_set(g, TRIG, 3, 5, s, thr=tr)
+        want = np.flatnonzero(reach[:, root])
+        assert list(nodes) == list(want) and w == int(indeg[want].sum())
+
+
+def test_trigger_with_single_certain_members_is_a_chain():
+    # every node's triggering set is always its first in-edge: the RR set is the chain of first in-edges
+    g = synth.chung_lu(300, 1500, 2.1, 5)
+    tr = _trigger_of(g, lambda v, d: [(2**32, [0])] if d else [])
+    for s in range(100):
+        root = oracle.root(6, 64, s, g.n)
+        chain, v = [root], root
+        while g.off[v + 1] > g.off[v] and int(g.src[g.off[v]]) not in chain:
+            v = int(g.src[g.off[v]])
+            chain.append(v)
+        nodes, w = oracle.rr_set(g, TRIG, 6, 64, s, thr=tr)
+        assert list(nodes) == sorted(chain)
 
 
 def test_lt_functional_graph_chain():
@@ -266,14 +338,19 @@ def _tiny_cases():
         out.append((g, LT, None))
         out.append((g, LT, synth.random_lt_thresholds(g, gs)))                # normalized in-weights
         out.append((g, LT, synth.random_lt_thresholds(g, gs + 1, total=0.7)))  # weights summing to 0.7
+        out.append((g, TRIG, synth.random_triggering(g, gs)))                      # general triggering sets
+        out.append((g, TRIG, synth.random_triggering(g, gs + 7, max_outcomes=3, p_full=1.0)))  # total mass 1
     return out
+
+
+_NCASES = len(_tiny_cases())
 
 
 def _mask(nodes):
     return sum(1 << int(u) for u in nodes)
 
 
-@pytest.mark.parametrize("case", range(10))
+@pytest.mark.parametrize("case", range(_NCASES))
 def test_lemma2_and_corollary1_rr_frequency_matches_exact_spread(case):
     g, model, thr = _tiny_cases()[case]
     spreads = oracle.brute_all_spreads(g, model, thr=thr)
@@ -297,7 +374,7 @@ def test_lemma2_and_corollary1_rr_frequency_matches_exact_spread(case):
         assert abs(hit - q) <= 5 * math.sqrt(q * (1 - q) / N) + 1e-12
 
 
-@pytest.mark.parametrize("case", range(10))
+@pytest.mark.parametrize("case", range(_NCASES))
 def test_lemma4_ept_and_sampled_width(case):
     g, model, thr = _tiny_cases()[case]
     spreads = oracle.brute_all_spreads(g, model, thr=thr)
@@ -313,7 +390,7 @@ def test_lemma4_ept_and_sampled_width(case):
     assert abs(wv.mean() - st["ept"]) <= 5 * wv.std() / math.sqrt(N) + 1e-9
 
 
-@pytest.mark.parametrize("case", range(10))
+@pytest.mark.parametrize("case", range(_NCASES))
 @pytest.mark.parametrize("k", [1, 2, 3])
 def test_lemma5_kpt_equals_n_expected_kappa(case, k):
     g, model, thr = _tiny_cases()[case]
@@ -772,7 +849,7 @@ def test_forward_spread_is_reach_in_the_runs_world(model):
         assert int(got[r]) == want, r
 
 
-@pytest.mark.parametrize("case", range(10))
+@pytest.mark.parametrize("case", range(_NCASES))
 def test_forward_spread_mean_matches_exact_spread(case):
     g, model, thr = _tiny_cases()[case]
     spreads = oracle.brute_all_spreads(g, model, thr=thr)
