@@ -301,6 +301,20 @@ tim_status tim_sample_cover(tim_ctx *ctx, const tim_graph *g, int model, uint64_
 tim_status tim_max_coverage(tim_ctx *ctx, int64_t n, uint64_t nsets, const int64_t *d_set_off, const int32_t *d_nodes,
                             int k, int32_t *seeds, uint64_t *gains);
 
+/* tim_max_coverage for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same greedy, results identical to tim_max_coverage, with its work
+ * arrays (counts, index, marks) in one fixed device array that the library
+ * holds on each GPU until the process ends (about 53 MB, located when a
+ * context is first created on the device).  It calls no allocator.  Limits
+ * of that array: n <= 2^20 nodes, nsets <= 2^22 sets, at most 2^23 entries in
+ * all, k <= 1024; larger inputs return TIM_EINVAL and change nothing.  Every
+ * call on a GPU uses that GPU's one array (each call clears what it needs),
+ * so calls that overlap on one GPU, from any contexts or threads, race and
+ * must be serialized by the caller. */
+tim_status tim_max_coverage_noalloc(tim_ctx *ctx, int64_t n, uint64_t nsets, const int64_t *d_set_off,
+                                    const int32_t *d_nodes, int k, int32_t *seeds, uint64_t *gains);
+
 /* ---- the three phases ---------------------------------------------------- */
 
 /* KptEstimation (Algorithm 2): rounds i = 1 .. floor(log2 n)-1 of

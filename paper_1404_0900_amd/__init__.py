@@ -28,6 +28,7 @@ _STATUS = {1: "TIM_EINVAL", 2: "TIM_ENOMEM", 3: "TIM_EBUDGET", 4: "TIM_EDEVICE",
 EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_device_bytes", "tim_set_resident_limit",
             "tim_graph_upload", "tim_graph_set_lt_weights",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
+            "tim_max_coverage_noalloc",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
             "tim_profile_read", "tim_autotune", "tim_spread_mc", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
             "tim_server_stop")
@@ -132,6 +133,7 @@ def load_library():
         "tim_sample_cover": (ctypes.c_int, [P, P, ctypes.c_int, U64, U32, U64, U64, P, ctypes.c_int,
                                             ctypes.POINTER(BatchStats)]),
         "tim_max_coverage": (ctypes.c_int, [P, I64, U64, P, P, ctypes.c_int, P, P]),
+        "tim_max_coverage_noalloc": (ctypes.c_int, [P, I64, U64, P, P, ctypes.c_int, P, P]),
         "tim_kpt_estimate": (ctypes.c_int, [P, P, ctypes.c_int, U64, ctypes.c_int, DBL, ctypes.POINTER(KptResult)]),
         "tim_refine_kpt": (ctypes.c_int, [P, P, ctypes.c_int, U64, ctypes.c_int, DBL, DBL, DBL, ctypes.c_int, U64, P,
                                           ctypes.POINTER(RefineResult)]),
@@ -307,6 +309,17 @@ class Engine:
         self._sync_torch()
         _check(self.lib.tim_max_coverage(self.ctx, n, nsets, _dev_ptr(set_off), _dev_ptr(nodes) if nodes.numel() else
                                          None, k, seeds.ctypes.data, gains.ctypes.data))
+        return seeds, gains
+
+    def max_coverage_noalloc(self, n: int, set_off, nodes, k: int):
+        """tim_max_coverage_noalloc: the same greedy with the library's fixed work area (no allocation)."""
+        seeds = np.zeros(k, dtype=np.int32)
+        gains = np.zeros(k, dtype=np.uint64)
+        nsets = int(set_off.numel()) - 1
+        self._sync_torch()
+        _check(self.lib.tim_max_coverage_noalloc(self.ctx, n, nsets, _dev_ptr(set_off),
+                                                 _dev_ptr(nodes) if nodes.numel() else None, k,
+                                                 seeds.ctypes.data, gains.ctypes.data))
         return seeds, gains
 
     # ---- phases ----

@@ -1741,6 +1741,15 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
     c->grid_batch1[wc] = tim::batch_blocks_per_cu(0, tim::kModeWidth, wc != 0, 1);
   }
   c->grid_batch_chain = tim::lt_chain_blocks_per_cu(tim::kModeWidth, true);
+  {
+    // the fixed work area of tim_max_coverage_noalloc on this device (once per device)
+    const hipError_t e = tim::static_scratch_init(device);
+    if (e != hipSuccess) {
+      if (c->own_stream) (void)hipStreamDestroy(c->stream);
+      delete c;
+      return fail(TIM_EDEVICE, "hipGetSymbolAddress of the fixed work area: %s", hipGetErrorString(e));
+    }
+  }
   if (hipMalloc(&c->ctr, tim::kCtrCount * sizeof(unsigned long long)) != hipSuccess ||
       hipHostMalloc(&c->ctr_host, tim::kCtrCount * sizeof(unsigned long long), hipHostMallocDefault) != hipSuccess ||
       hipEventCreate(&c->ev[0]) != hipSuccess || hipEventCreate(&c->ev[1]) != hipSuccess ||
@@ -1973,6 +1982,68 @@ tim_status tim_max_coverage(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t
     off = c->rr_off.as<int64_t>();
   }
   return greedy(c, n, nsets, off, nullptr, nullptr, d_nodes, (uint64_t)total, k, seeds, gains);
+}
+
+tim_status tim_max_coverage_noalloc(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* d_set_off,
+                                    const int32_t* d_nodes, int k, int32_t* seeds, uint64_t* gains) {
+  if (!c || !seeds || (nsets && (!d_set_off || !d_nodes))) return fail(TIM_EINVAL, "null argument");
+  if (n < 1 || n > tim::kStaticMaxN || k < 1 || k > n || k > tim::kStaticMaxK)
+    return fail(TIM_EINVAL, "n = %lld and k = %d must satisfy 1 <= k <= n, n <= %lld, k <= %d", (long long)n, k,
+                (long long)tim::kStaticMaxN, tim::kStaticMaxK);
+  if (nsets > tim::kStaticMaxSets)
+    return fail(TIM_EINVAL, "%llu sets exceed the fixed work area's %llu", (unsigned long long)nsets,
+                (unsigned long long)tim::kStaticMaxSets);
+  HIP_TRY(hipSetDevice(c->device));
+  const tim::StaticGreedy st = tim::static_greedy_layout(c->device);
+  if (!st.cnt) return fail(TIM_EDEVICE, "the fixed work area of device %d was not set up", c->device);
+  int64_t total = 0;
+  if (nsets) {
+    HIP_TRY(hipMemcpyAsync(&total, d_set_off + nsets, 8, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+  }
+  if (total < 0) return fail(TIM_EINVAL, "negative collection size");
+  if ((uint64_t)total > tim::kStaticMaxEntries)
+    return fail(TIM_EINVAL, "%lld entries exceed the fixed work area's %llu", (long long)total,
+                (unsigned long long)tim::kStaticMaxEntries);
+  if (total) {
+    tim::launch_check_ids(d_nodes, (uint64_t)total, n, st.flag, c->stream);
+    unsigned int bad = 0;
+    HIP_TRY(hipMemcpyAsync(&bad, st.flag, 4, hipMemcpyDeviceToHost, c->stream));
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    if (bad) return fail(TIM_EINVAL, "a node id of the collection lies outside [0, n)");
+  }
+  const int64_t* off = d_set_off;
+  if (!nsets) {
+    tim::launch_set_u64(reinterpret_cast<unsigned long long*>(st.zero_off), 0ull, c->stream);
+    off = st.zero_off;
+  }
+  tim::GreedyArgs a;
+  memset(&a, 0, sizeof(a));
+  a.n = n;
+  a.nsets = nsets;
+  a.total = (uint64_t)total;
+  a.set_off = off;
+  a.nodes = d_nodes;
+  a.cnt = st.cnt;
+  a.fill = st.fill;
+  a.inv_off = st.inv_off;
+  a.inv_sets = st.inv_sets;
+  a.scan_temp = st.scan_temp;
+  a.covered = st.covered;
+  a.selected = st.selected;
+  a.best = st.best;
+  if (k > 1) tim::launch_index(a, c->stream);
+  else tim::launch_counts(a, c->stream);
+  tim::launch_greedy(a, k, c->stream);
+  HIP_TRY(hipGetLastError());
+  unsigned long long keys[tim::kStaticMaxK];
+  HIP_TRY(hipMemcpyAsync(keys, a.best, (size_t)k * 8, hipMemcpyDeviceToHost, c->stream));
+  HIP_TRY(hipStreamSynchronize(c->stream));
+  for (int j = 0; j < k; ++j) {
+    seeds[j] = (int32_t)(0xFFFFFFFFull - (keys[j] & 0xFFFFFFFFull));
+    if (gains) gains[j] = keys[j] >> 32;
+  }
+  return TIM_OK;
 }
 
 tim_status tim_kpt_estimate(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, int k, double ell,

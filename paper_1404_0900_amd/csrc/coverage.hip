@@ -9,7 +9,10 @@
 // that a single atomicMax selects the largest count with ties to the lowest
 // id, and one cover kernel marks the chosen node's uncovered sets and
 // decrements the counts of their members.
+#include <string.h>
+
 #include <algorithm>
+#include <mutex>
 
 #include "engine.hpp"
 
@@ -611,6 +614,76 @@ void launch_pool_cover(const unsigned long long* best, const int32_t* pool, cons
   if (!nsets) return;
   hipLaunchKernelGGL(scan_cover_kernel, dim3(tile_grid(nsets, kTileSets)), dim3(kThreads), 0, s, best,
                      PoolSets{set_start, set_len, pool}, nsets, covered, cnt);
+}
+
+// ---- a greedy that allocates nothing ----
+//
+// For callers that cannot allocate device memory (under HIP graph capture, in
+// serving loops), the greedy's work arrays can live in one fixed device array
+// instead of context buffers.  Each GPU holds its own copy at its own
+// address, found once per device with hipGetSymbolAddress; in host code the
+// array's name is not a device address, so only that address is ever used.
+namespace {
+constexpr size_t kStaticCnt = 0;                                             // uint32 [kStaticMaxN]
+constexpr size_t kStaticFill = kStaticCnt + 4 * kStaticMaxN;                 // uint32 [kStaticMaxN]
+constexpr size_t kStaticInvOff = kStaticFill + 4 * kStaticMaxN;              // int64 [kStaticMaxN + 1]
+constexpr size_t kStaticInvSets = kStaticInvOff + 8 * (kStaticMaxN + 64);   // uint32 [kStaticMaxEntries]
+constexpr size_t kStaticCovered = kStaticInvSets + 4 * kStaticMaxEntries;    // uint8 [kStaticMaxSets]
+constexpr size_t kStaticSelected = kStaticCovered + kStaticMaxSets;          // uint8 [kStaticMaxN]
+constexpr size_t kStaticBest = kStaticSelected + kStaticMaxN;                // uint64 [kStaticMaxK]
+constexpr size_t kStaticMisc = kStaticBest + 8 * kStaticMaxK;                // id-check flag, an empty CSR offset
+constexpr size_t kStaticScan = kStaticMisc + 256;                            // scan tile sums
+constexpr size_t kStaticBytes = kStaticScan + ((kStaticMaxN + 1 + kTile - 1) / kTile + 1) * 8 + 256;
+static_assert(kStaticInvSets % 256 == 0 && kStaticBest % 8 == 0, "alignment");
+
+__device__ __align__(256) unsigned char scratch[kStaticBytes];
+
+std::mutex g_static_mu;
+void* g_static_ptr[kStaticMaxDevices] = {};
+
+__global__ void set_u64_kernel(unsigned long long* p, unsigned long long v) {
+  if (threadIdx.x == 0) *p = v;
+}
+}  // namespace
+
+size_t static_scratch_bytes() { return kStaticBytes; }
+
+hipError_t static_scratch_init(int device) {
+  if (device < 0 || device >= kStaticMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_ptr[device]) return hipSuccess;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  g_static_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+StaticGreedy static_greedy_layout(int device) {
+  StaticGreedy st;
+  memset(&st, 0, sizeof(st));
+  void* base = nullptr;
+  if (device >= 0 && device < kStaticMaxDevices) {
+    std::lock_guard<std::mutex> lk(g_static_mu);
+    base = g_static_ptr[device];
+  }
+  if (!base) return st;
+  unsigned char* b = static_cast<unsigned char*>(base);
+  st.cnt = reinterpret_cast<uint32_t*>(b + kStaticCnt);
+  st.fill = reinterpret_cast<uint32_t*>(b + kStaticFill);
+  st.inv_off = reinterpret_cast<int64_t*>(b + kStaticInvOff);
+  st.inv_sets = reinterpret_cast<uint32_t*>(b + kStaticInvSets);
+  st.covered = b + kStaticCovered;
+  st.selected = b + kStaticSelected;
+  st.best = reinterpret_cast<unsigned long long*>(b + kStaticBest);
+  st.flag = reinterpret_cast<unsigned int*>(b + kStaticMisc);
+  st.zero_off = reinterpret_cast<int64_t*>(b + kStaticMisc + 8);
+  st.scan_temp = b + kStaticScan;
+  return st;
+}
+
+void launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s) {
+  hipLaunchKernelGGL(set_u64_kernel, dim3(1), dim3(64), 0, s, p, v);
 }
 
 void launch_greedy(const GreedyArgs& a, int k, hipStream_t s) {

@@ -197,4 +197,30 @@ void launch_pool_hist(const int32_t* pool, const uint64_t* set_start, const uint
 void launch_pool_cover(const unsigned long long* best, const int32_t* pool, const uint64_t* set_start,
                        const uint32_t* set_len, uint64_t nsets, uint8_t* covered, uint32_t* cnt, hipStream_t s);
 
+// The greedy's work arrays in one fixed device array (for callers that cannot
+// allocate): limits, the per-device lookup of its address (call once per
+// device with that device current), and the layout of the arrays in it.
+constexpr int64_t kStaticMaxN = 1 << 20;          // nodes
+constexpr uint64_t kStaticMaxSets = 1ull << 22;   // sets of the collection
+constexpr uint64_t kStaticMaxEntries = 1ull << 23;  // total size of the collection
+constexpr int kStaticMaxK = 1024;                 // greedy steps
+constexpr int kStaticMaxDevices = 64;
+struct StaticGreedy {
+  uint32_t* cnt;
+  uint32_t* fill;
+  int64_t* inv_off;
+  uint32_t* inv_sets;
+  uint8_t* covered;
+  uint8_t* selected;
+  unsigned long long* best;
+  unsigned int* flag;  // id check
+  int64_t* zero_off;   // CSR offset of an empty collection
+  void* scan_temp;
+};
+size_t static_scratch_bytes();
+hipError_t static_scratch_init(int device);
+// All pointers null if static_scratch_init has not succeeded on the device.
+StaticGreedy static_greedy_layout(int device);
+void launch_set_u64(unsigned long long* p, unsigned long long v, hipStream_t s);
+
 }  // namespace tim
