@@ -259,6 +259,23 @@ def main():
     line["lt_weighted"] = {"sets_per_s": round(lw_sets / (time.perf_counter() - t0), 1), "tim_plus_s": lw_per_k}
     eng.set_lt_weights(dg, g, None)
 
+    # the general triggering model (explicit per-node distributions over in-edge subsets), outside the timed steps
+    log("general triggering model: drawing the distributions")
+    eng.set_triggering(dg, g, synth.random_triggering(g, SEED))
+    for k in KS:  # warm-up
+        eng.run(dg, tim.TRIGGER, k, EPS, ELL, SEED)
+    tr_sets, t0 = 0, time.perf_counter()
+    tr_per_k = {}
+    for k in KS:
+        t1 = time.perf_counter()
+        _, _, rep = eng.run(dg, tim.TRIGGER, k, EPS, ELL, SEED)
+        tr_per_k[str(k)] = round(time.perf_counter() - t1, 6)
+        tr_sets += rep.sets_total
+    line["trigger"] = {"sets_per_s": round(tr_sets / (time.perf_counter() - t0), 1), "tim_plus_s": tr_per_k,
+                       "distribution": "synth.random_triggering(seed 2): 1-4 outcomes per node, 1-3 in-edges each, "
+                                       "total probability 1 (a quarter of the nodes) or uniform in [0.3, 0.8]"}
+    eng.set_triggering(dg, g, None)
+
     line["parity"] = None
     if not args.no_cpu_baseline:
         import oracle

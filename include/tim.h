@@ -23,6 +23,8 @@
  *           live iff word <= t(e) (t(e) = uint32 threshold; weighted cascade:
  *           t = floor(2^32 / indeg(dst)) - 1)
  *   kind 2: LT pick at node v (idx = v); in-edge off[v] + floor(X64*indeg/2^64)
+ *   kind 3: triggering-set pick at node v (idx = v), by word 0 (general
+ *           triggering model; see tim_graph_set_triggering)
  *   phase i in [1, 62]: KptEstimation round i; 63: RefineKPT's fresh sets;
  *   64: NodeSelection's sets.  Set ids start at 0 in every phase.
  *
@@ -59,11 +61,15 @@ typedef enum {
 } tim_status;
 
 typedef enum {
-  TIM_MODEL_IC = 0, /* independent cascade (Section 2.1) */
-  TIM_MODEL_LT = 1  /* linear threshold: a triggering model whose triggering set
-                       is one in-neighbour or none (Section 4.2; Section 7.1);
-                       in-weights 1/indeg(v) unless tim_graph_set_lt_weights
-                       gave the graph others */
+  TIM_MODEL_IC = 0,     /* independent cascade (Section 2.1) */
+  TIM_MODEL_LT = 1,     /* linear threshold: a triggering model whose triggering set
+                           is one in-neighbour or none (Section 4.2; Section 7.1);
+                           in-weights 1/indeg(v) unless tim_graph_set_lt_weights
+                           gave the graph others */
+  TIM_MODEL_TRIGGER = 2 /* general triggering model (Section 4.2): each node draws its
+                           triggering set from the explicit distribution that
+                           tim_graph_set_triggering gave the graph (tim_run and the
+                           phase, sampling and spread calls; not batches or servers) */
 } tim_model;
 
 enum { TIM_PHASE_REFINE = 63, TIM_PHASE_SELECT = 64 };
@@ -258,6 +264,27 @@ void tim_graph_free(tim_graph *g);
  * the order).  Later LT calls on g use these weights; NULL restores 1/indeg.
  * TIM_EINVAL names the first decreasing pair. */
 tim_status tim_graph_set_lt_weights(tim_ctx *ctx, tim_graph *g, const uint32_t *lt_thr, const int64_t *in_off);
+
+/* General triggering model (Section 4.2: node v is activated when a node of
+ * its triggering set T(v), a random subset of its in-neighbours, is active).
+ * The distribution of T(v) is given explicitly per node, all arrays host:
+ *   toff int64[n+1]: the outcomes of v are j in [toff[v], toff[v+1])
+ *   tthr uint32[J]:  cumulative thresholds, non-decreasing within a node:
+ *                    t_j = floor(C_j * 2^32) - 1 for the cumulative
+ *                    probability C_j of v's outcomes up to j
+ *   tset int64[J+1]: outcome j's members are tmem[tset[j] .. tset[j+1])
+ *   tmem uint32[...]: local in-edge indices i (the in-edge in_off[v] + i),
+ *                    strictly increasing within an outcome
+ *   in_off:          the graph's host offsets (to check the members)
+ * With x = word 0 of v's draw of kind 3, T(v) is the first outcome with
+ * x <= t_j, and empty if there is none (probability 1 - C of v's last
+ * outcome), so outcome j has probability (t_j - t_{j-1}) / 2^32.  An RR set
+ * is the randomized BFS of Section 4.2: every dequeued node draws T(v) and
+ * its unvisited members join.  Widths stay sum of in-degrees (Equation (1)).
+ * toff NULL removes the distribution.  TIM_EINVAL names the first violation
+ * (J < 2^32); nothing changes then. */
+tim_status tim_graph_set_triggering(tim_ctx *ctx, tim_graph *g, const int64_t *toff, const uint32_t *tthr,
+                                    const int64_t *tset, const uint32_t *tmem, const int64_t *in_off);
 
 /* ---- RR sets (Definitions 1-2; Section 3.1; Section 4.2) ---------------- */
 

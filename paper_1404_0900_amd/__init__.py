@@ -17,7 +17,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libtim.so")
 
-IC, LT = 0, 1
+IC, LT, TRIGGER = 0, 1, 2
 PHASE_REFINE, PHASE_SELECT = 63, 64
 FLAG_PLAIN, FLAG_ELL_ADJUST = 1, 2
 MAX_ROUNDS = 64
@@ -26,7 +26,7 @@ OK, EINVAL, ENOMEM, EBUDGET, EDEVICE, ECAPACITY = range(6)
 _STATUS = {1: "TIM_EINVAL", 2: "TIM_ENOMEM", 3: "TIM_EBUDGET", 4: "TIM_EDEVICE", 5: "TIM_ECAPACITY"}
 
 EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_device_bytes", "tim_set_resident_limit",
-            "tim_graph_upload", "tim_graph_set_lt_weights",
+            "tim_graph_upload", "tim_graph_set_lt_weights", "tim_graph_set_triggering",
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_max_coverage_noalloc",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
@@ -126,6 +126,7 @@ def load_library():
         "tim_graph_upload": (ctypes.c_int, [P, I64, I64, P, P, P, ctypes.POINTER(P)]),
         "tim_graph_free": (None, [P]),
         "tim_graph_set_lt_weights": (ctypes.c_int, [P, P, P, P]),
+        "tim_graph_set_triggering": (ctypes.c_int, [P, P, P, P, P, P, P]),
         "tim_sample_rr": (ctypes.c_int, [P, P, ctypes.c_int, U64, U32, U64, U64, P, P, U64, P,
                                          ctypes.POINTER(U64), ctypes.POINTER(BatchStats)]),
         "tim_sample_widths": (ctypes.c_int, [P, P, ctypes.c_int, U64, U32, U64, U64, ctypes.c_int, P, P,
@@ -250,6 +251,19 @@ class Engine:
         off = np.ascontiguousarray(graph.off, dtype=np.int64)
         t = None if lt_thr is None else np.ascontiguousarray(lt_thr, dtype=np.uint32)
         _check(self.lib.tim_graph_set_lt_weights(self.ctx, g.handle, _np_ptr(t), off.ctypes.data))
+
+    def set_triggering(self, g: DeviceGraph, graph, trig):
+        """The general triggering model's distribution of every node of g (toff, tthr, tset, tmem arrays as in
+        include/tim.h), or None to remove it."""
+        off = np.ascontiguousarray(graph.off, dtype=np.int64)
+        if trig is None:
+            _check(self.lib.tim_graph_set_triggering(self.ctx, g.handle, None, None, None, None, off.ctypes.data))
+            return
+        arrs = [np.ascontiguousarray(trig.toff, dtype=np.int64), np.ascontiguousarray(trig.tthr, dtype=np.uint32),
+                np.ascontiguousarray(trig.tset, dtype=np.int64), np.ascontiguousarray(trig.tmem, dtype=np.uint32)]
+        arrs = [a if a.size else np.zeros(1, dtype=a.dtype) for a in arrs]
+        _check(self.lib.tim_graph_set_triggering(self.ctx, g.handle, *(a.ctypes.data for a in arrs),
+                                                 off.ctypes.data))
 
     def free(self, g: DeviceGraph):
         self.lib.tim_graph_free(g.handle)

@@ -66,6 +66,12 @@ struct DevBuf {
 // Sets per sampling launch: bounds the deferred-set list of one launch.
 constexpr uint64_t kMaxLaunchSets = 1ull << 26;
 
+// Algorithmic bytes per visited node of the general triggering model: its
+// two CSR offsets (16), its two outcome offsets (16), one outcome threshold
+// (4), the outcome's two member offsets (16), and the member and source that
+// brought it in (8).
+constexpr uint64_t kTriggerNodeBytes = 60;
+
 struct Hub;
 
 }  // namespace
@@ -98,6 +104,7 @@ struct tim_ctx {
   bool wide_small = true;       // launches of few sets take the 64-lane shape (off while tim_autotune times shapes)
   int grid_lt[3] = {};
   int grid_lt_chain[3] = {};
+  int grid_trig[3] = {};          // general-triggering first tier
   int grid_rounds[2][2] = {};     // multi-job launches of KptEstimation rounds: tier 0 per [model][wc]
   int grid_batch1[2] = {};        // their IC tier 1, per wc
   int grid_batch_chain = 0;       // their LT long-chain tier
@@ -132,6 +139,11 @@ struct tim_graph {
   int32_t* src = nullptr;
   uint32_t* thr = nullptr;
   uint32_t* lthr = nullptr;  // LT cumulative in-weight thresholds, or nullptr (1/indeg)
+  // general triggering model: explicit per-node distributions over in-edge subsets (or none)
+  int64_t* toff = nullptr;
+  uint32_t* tthr = nullptr;
+  int64_t* tset = nullptr;
+  uint32_t* tmem = nullptr;
   // out-edge lists for the spread evaluator, built on first use
   int64_t* out_off = nullptr;
   int32_t* out_dst = nullptr;
@@ -307,11 +319,12 @@ int launch_lanes(const tim_ctx* c, int model, int mode, uint64_t count) {
 // Blocks of the tier-0 sampler over `count` sets (and its wavefronts).
 uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t count, uint64_t* waves) {
   const int lanes = launch_lanes(c, model, mode, count);
-  const int per_cu = model != TIM_MODEL_IC ? c->grid_lt[mode]
+  const int per_cu = model == TIM_MODEL_TRIGGER ? c->grid_trig[mode]
+                     : model != TIM_MODEL_IC ? c->grid_lt[mode]
                      : lanes == c->seg_lanes ? c->grid_ic[mode][wc ? 1 : 0]
                                              : c->grid_ic_wide[mode][wc ? 1 : 0];
-  const uint64_t waves_per_block = model == TIM_MODEL_IC ? 4 : 2;
-  uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)lanes) : 128;
+  const uint64_t waves_per_block = model == TIM_MODEL_LT ? 2 : 4;
+  uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)lanes) : model == TIM_MODEL_LT ? 128 : 4;
   if (mode == tim::kModeEmit && c->emit_wave_sets)
     sets_per_block = std::max<uint64_t>(sets_per_block, waves_per_block * c->emit_wave_sets);
   uint64_t grid = (uint64_t)per_cu * (uint64_t)c->num_cu;
@@ -324,7 +337,7 @@ uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t co
 // Wavefronts of the tier-0 launch over `count` sets (the only tier that
 // reserves node-pool slices; the others reserve exactly what they store).
 uint64_t emit_waves(const tim_ctx* c, int model, uint64_t count) {
-  if (c->hub) return c->hub->emit_waves[model];  // any wavefront of a batched launch may visit a job
+  if (c->hub && model != TIM_MODEL_TRIGGER) return c->hub->emit_waves[model];  // any wavefront of a batched launch may visit a job
   uint64_t waves = 0, w2 = 0;
   sample_grid(c, model, tim::kModeEmit, true, count, &waves);
   sample_grid(c, model, tim::kModeEmit, false, count, &w2);
@@ -369,7 +382,7 @@ uint64_t pool_need(const tim_ctx* c, int model, uint64_t count, uint64_t nodes, 
 tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, uint64_t seed, uint32_t phase,
                          uint64_t first, uint64_t count, int k, uint64_t* widths, uint32_t* sizes,
                          uint64_t set_offset, uint64_t pool_base, Totals* t) {
-  if (model == TIM_MODEL_IC) TIM_TRY(ensure_big(c, g->n));  // the LT long-chain tier needs no slots
+  if (model != TIM_MODEL_LT) TIM_TRY(ensure_big(c, g->n));  // the LT long-chain tier needs no slots
   TIM_TRY(ensure(c, c->list1, count * 8, "deferred-set list"));
   if (model == TIM_MODEL_IC) TIM_TRY(ensure(c, c->list2, count * 8, "deferred-set list"));
   SampleArgs a;
@@ -378,6 +391,10 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   a.g.src = g->src;
   a.g.thr = g->thr;
   a.g.lthr = g->lthr;
+  a.g.toff = g->toff;
+  a.g.tthr = g->tthr;
+  a.g.tset = g->tset;
+  a.g.tmem = g->tmem;
   a.g.n = g->n;
   a.g.m = g->m;
   a.seed = seed;
@@ -451,7 +468,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
     t->covered += acc[tim::kAccCovered];
   }
   t->pool_used += h[tim::kCtrPoolCursor];
-  if (c->prof_on && !c->hub) {
+  if (c->prof_on && !c->hub && model != TIM_MODEL_TRIGGER) {  // the profile covers the IC and LT kernels
     float ms_main = 0.f, ms_big = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms_main, c->pev[0], c->pev[1]));
     HIP_TRY(hipEventElapsedTime(&ms_big, c->pev[1], c->pev[2]));
@@ -465,6 +482,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
     const uint64_t nodes = acc0[tim::kAccNodes], edges = acc0[tim::kAccWidth];
     uint64_t bytes;
     if (model == TIM_MODEL_IC) bytes = 16 * nodes + (g->thr ? 8 : 4) * edges;
+    else if (model == TIM_MODEL_TRIGGER) bytes = kTriggerNodeBytes * nodes;
     else bytes = 20 * nodes;
     if (mode == tim::kModeEmit) bytes += 4 * nodes + 12 * sets;
     p.launches += 1;
@@ -917,7 +935,12 @@ uint64_t round_size(int64_t n, double ell, int i) {
 tim_status check_phase_args(const tim_ctx* c, const tim_graph* g, int model, int k) {
   if (!c) return fail(TIM_EINVAL, "null context");
   if (!check_graph(c, g)) return fail(TIM_EINVAL, "graph does not belong to this context");
-  if (model != TIM_MODEL_IC && model != TIM_MODEL_LT) return fail(TIM_EINVAL, "unknown model %d", model);
+  if (model != TIM_MODEL_IC && model != TIM_MODEL_LT && model != TIM_MODEL_TRIGGER)
+    return fail(TIM_EINVAL, "unknown model %d", model);
+  if (model == TIM_MODEL_TRIGGER && !g->toff)
+    return fail(TIM_EINVAL, "the graph has no triggering distribution (tim_graph_set_triggering)");
+  if (model == TIM_MODEL_TRIGGER && c->hub)
+    return fail(TIM_EINVAL, "the general triggering model runs through tim_run, not in batches or servers");
   if (k < 1 || (int64_t)k > g->n) return fail(TIM_EINVAL, "k=%d outside [1, n=%lld]", k, (long long)g->n);
   return TIM_OK;
 }
@@ -1115,7 +1138,7 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
     const uint64_t ci = round_size(g->n, ell, i);
     Totals t;
     const bool predicted = predict(i, ci);
-    if (!c->hub && !predicted) {
+    if (!c->hub && !predicted && model != TIM_MODEL_TRIGGER) {
       // the rounds of few sets run together (up to kGroupSets sets), a later
       // round with the next one (up to kPairSets); under a budget, the
       // group's lists (20 bytes per set) take at most an eighth of the room
@@ -1733,6 +1756,7 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
       c->grid_ic_wide[mode][wc] = tim::ic_blocks_per_cu(mode, wc != 0, 64);
     }
     c->grid_lt[mode] = tim::lt_lane_blocks_per_cu(mode);
+    c->grid_trig[mode] = tim::trig_blocks_per_cu(mode);
     c->grid_lt_chain[mode] = tim::lt_chain_blocks_per_cu(mode, false);
   }
   for (int wc = 0; wc < 2; ++wc) {
@@ -1852,6 +1876,8 @@ void tim_graph_free(tim_graph* g) {
   if (g->src) (void)hipFree(g->src);
   if (g->thr) (void)hipFree(g->thr);
   if (g->lthr) (void)hipFree(g->lthr);
+  for (void* p : {(void*)g->toff, (void*)g->tthr, (void*)g->tset, (void*)g->tmem})
+    if (p) (void)hipFree(p);
   if (g->out_off) (void)hipFree(g->out_off);
   if (g->out_dst) (void)hipFree(g->out_dst);
   if (g->out_eid) (void)hipFree(g->out_eid);
@@ -1885,6 +1911,76 @@ tim_status tim_graph_set_lt_weights(tim_ctx* c, tim_graph* g, const uint32_t* lt
   }
   if (g->lthr) (void)hipFree(g->lthr);
   g->lthr = d;
+  return TIM_OK;
+}
+
+tim_status tim_graph_set_triggering(tim_ctx* c, tim_graph* g, const int64_t* toff, const uint32_t* tthr,
+                                    const int64_t* tset, const uint32_t* tmem, const int64_t* in_off) {
+  if (!c || !g || g->ctx != c) return fail(TIM_EINVAL, "graph does not belong to this context");
+  if (c->serving) return fail(TIM_EINVAL, "a server runs on this context");
+  HIP_TRY(hipSetDevice(c->device));
+  auto drop = [&]() {
+    for (void** p : {(void**)&g->toff, (void**)&g->tthr, (void**)&g->tset, (void**)&g->tmem}) {
+      if (*p) (void)hipFree(*p);
+      *p = nullptr;
+    }
+  };
+  if (!toff) {
+    HIP_TRY(hipStreamSynchronize(c->stream));
+    drop();
+    return TIM_OK;
+  }
+  if (!tthr || !tset || !tmem || !in_off) return fail(TIM_EINVAL, "null argument");
+  if (in_off[0] != 0 || in_off[g->n] != g->m) return fail(TIM_EINVAL, "in_off does not match the graph");
+  if (toff[0] != 0) return fail(TIM_EINVAL, "toff[0] must be 0");
+  for (int64_t v = 0; v < g->n; ++v)
+    if (toff[v + 1] < toff[v]) return fail(TIM_EINVAL, "toff decreases at node %lld", (long long)v);
+  const int64_t J = toff[g->n];
+  if (J > 0xFFFFFFFFLL) return fail(TIM_EINVAL, "more than 2^32 - 1 outcomes");
+  if (tset[0] != 0) return fail(TIM_EINVAL, "tset[0] must be 0");
+  for (int64_t j = 0; j < J; ++j)
+    if (tset[j + 1] < tset[j]) return fail(TIM_EINVAL, "tset decreases at outcome %lld", (long long)j);
+  const int64_t total = tset[J];
+  for (int64_t v = 0; v < g->n; ++v) {
+    const int64_t d = in_off[v + 1] - in_off[v];
+    for (int64_t j = toff[v]; j < toff[v + 1]; ++j) {
+      if (j > toff[v] && tthr[j] < tthr[j - 1])
+        return fail(TIM_EINVAL, "thresholds of node %lld decrease at outcome %lld", (long long)v, (long long)j);
+      for (int64_t i = tset[j]; i < tset[j + 1]; ++i) {
+        if ((int64_t)tmem[i] >= d)
+          return fail(TIM_EINVAL, "member %lld of outcome %lld is not an in-edge of node %lld", (long long)i,
+                      (long long)j, (long long)v);
+        if (i > tset[j] && tmem[i] <= tmem[i - 1])
+          return fail(TIM_EINVAL, "members of outcome %lld are not strictly increasing", (long long)j);
+      }
+    }
+  }
+  int64_t* d_off = nullptr;
+  uint32_t* d_thr = nullptr;
+  int64_t* d_set = nullptr;
+  uint32_t* d_mem = nullptr;
+  bool ok = hipMalloc(&d_off, (size_t)(g->n + 1) * 8) == hipSuccess &&
+            hipMalloc(&d_thr, (size_t)std::max<int64_t>(J, 1) * 4) == hipSuccess &&
+            hipMalloc(&d_set, (size_t)(J + 1) * 8) == hipSuccess &&
+            hipMalloc(&d_mem, (size_t)std::max<int64_t>(total, 1) * 4) == hipSuccess;
+  if (ok)
+    ok = hipMemcpyAsync(d_off, toff, (size_t)(g->n + 1) * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         (J == 0 || hipMemcpyAsync(d_thr, tthr, (size_t)J * 4, hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+         hipMemcpyAsync(d_set, tset, (size_t)(J + 1) * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         (total == 0 ||
+          hipMemcpyAsync(d_mem, tmem, (size_t)total * 4, hipMemcpyHostToDevice, c->stream) == hipSuccess) &&
+         hipStreamSynchronize(c->stream) == hipSuccess;
+  if (!ok) {
+    for (void* p : {(void*)d_off, (void*)d_thr, (void*)d_set, (void*)d_mem})
+      if (p) (void)hipFree(p);
+    (void)hipGetLastError();
+    return fail(TIM_ENOMEM, "triggering distribution: upload failed");
+  }
+  drop();
+  g->toff = d_off;
+  g->tthr = d_thr;
+  g->tset = d_set;
+  g->tmem = d_mem;
   return TIM_OK;
 }
 
@@ -2077,6 +2173,7 @@ tim_status tim_node_select(tim_ctx* c, const tim_graph* g, int model, uint64_t s
 tim_status tim_autotune(tim_ctx* c, const tim_graph* g, int model, uint64_t sets, tim_tune_result* out) {
   TIM_TRY(check_phase_args(c, g, model, 1));
   if (c->hub || c->serving) return fail(TIM_EINVAL, "context is a batch member or runs a server");
+  if (model == TIM_MODEL_TRIGGER) return fail(TIM_EINVAL, "tim_autotune times the IC and LT samplers only");
   if (sets < 4096 || sets > kMaxLaunchSets) return fail(TIM_EINVAL, "sets must lie in [4096, 2^26]");
   HIP_TRY(hipSetDevice(c->device));
   tim_tune_result r;
@@ -2193,6 +2290,12 @@ tim_status tim_spread_mc(tim_ctx* c, const tim_graph* g, int model, uint64_t see
   a.g.src = g->src;
   a.g.thr = model == TIM_MODEL_IC ? g->thr : nullptr;
   a.g.lthr = model == TIM_MODEL_LT ? g->lthr : nullptr;
+  if (model == TIM_MODEL_TRIGGER) {
+    a.g.toff = g->toff;
+    a.g.tthr = g->tthr;
+    a.g.tset = g->tset;
+    a.g.tmem = g->tmem;
+  }
   a.g.n = g->n;
   a.g.m = g->m;
   a.out_off = gm->out_off;
@@ -2237,6 +2340,8 @@ tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_conc
   for (int i = 0; i < count; ++i) {
     tim_query& q = queries[i];
     q.status = check_run_args(c, q.graph, q.model, q.k, q.eps, q.ell, q.seeds);
+    if (q.status == TIM_OK && q.model == TIM_MODEL_TRIGGER)
+      q.status = fail(TIM_EINVAL, "the general triggering model runs through tim_run, not in batches");
     if (q.status != TIM_OK) return fail(q.status, "query %d: %s", i, g_error.c_str());
   }
   if (count == 0) return TIM_OK;
@@ -2315,6 +2420,8 @@ tim_status tim_server_submit(tim_server* sv, tim_query* q, uint64_t* ticket) {
   if (!sv || !q || !ticket) return fail(TIM_EINVAL, "null argument");
   tim_ctx* c = sv->ctx;
   TIM_TRY(check_run_args(c, q->graph, q->model, q->k, q->eps, q->ell, q->seeds));
+  if (q->model == TIM_MODEL_TRIGGER)
+    return fail(TIM_EINVAL, "the general triggering model runs through tim_run, not in servers");
   if ((uint64_t)q->graph->n > sv->hub->big_stride)
     return fail(TIM_EINVAL, "graph uploaded after the server started is larger than its slots");
   Ticket* t = new Ticket();

@@ -57,6 +57,13 @@ struct GraphView {
   const int32_t* src;   // m rounded up to a multiple of 4, plus 4, zero padded
   const uint32_t* thr;  // same padding, or nullptr for the weighted cascade
   const uint32_t* lthr; // LT cumulative in-weight thresholds (m), or nullptr for 1/indeg
+  // general triggering model: outcomes of v are [toff[v], toff[v+1]) with
+  // cumulative thresholds tthr; outcome j's members (local in-edge indices)
+  // are tmem[tset[j] .. tset[j+1])
+  const int64_t* toff;
+  const uint32_t* tthr;
+  const int64_t* tset;
+  const uint32_t* tmem;
   int64_t n, m;
 };
 
@@ -95,6 +102,8 @@ int ic_seg_lanes();
 int ic_blocks_per_cu(int mode, bool wc, int seg_lanes);
 int ic_tier1_blocks_per_cu(int mode, bool wc);
 int lt_lane_blocks_per_cu(int mode);
+// Occupancy of the general-triggering first tier (one set per wavefront).
+int trig_blocks_per_cu(int mode);
 // Occupancy of the LT long-chain tier (single or batched launches).
 int lt_chain_blocks_per_cu(int mode, bool batch);
 // Largest set the first tier keeps in LDS (IC: its queue for seg_lanes lanes

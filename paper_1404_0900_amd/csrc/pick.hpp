@@ -44,4 +44,24 @@ __device__ __forceinline__ int64_t lt_pick_edge(const GraphView& g, const Key& k
   return ea + lo;
 }
 
+// General triggering model (Section 4.2): the outcome node v draws from its
+// explicit distribution (an index into g.tthr / g.tset), or -1 for the empty
+// triggering set.  The outcomes of v are [toff[v], toff[v+1]) with
+// non-decreasing cumulative thresholds; with x = word 0 of v's draw of kind
+// 3, the first outcome with x <= its threshold, found by binary search.
+__device__ __forceinline__ int64_t trig_pick(const GraphView& g, const Key& key, const SetStream& st, int32_t v) {
+  int64_t lo = g.toff[v];
+  const int64_t end = g.toff[v + 1];
+  if (lo == end) return -1;
+  const uint32_t x = draw(key, st, kKindTrigger, (uint64_t)v).x;
+  if (x > g.tthr[end - 1]) return -1;
+  int64_t hi = end - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (x <= g.tthr[mid]) hi = mid;
+    else lo = mid + 1;
+  }
+  return lo;
+}
+
 }  // namespace tim

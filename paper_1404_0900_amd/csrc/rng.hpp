@@ -14,7 +14,7 @@
 
 namespace tim {
 
-enum : uint32_t { kKindRoot = 0, kKindCoin = 1, kKindPick = 2 };
+enum : uint32_t { kKindRoot = 0, kKindCoin = 1, kKindPick = 2, kKindTrigger = 3 };
 
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
 #pragma unroll

@@ -17,6 +17,9 @@
 // capacity; the last tier is a 512-thread block per set with visited stamps
 // and a queue of n entries in device memory.
 //
+// General triggering (Section 4.2): one set per wavefront over an LDS queue
+// and hash; larger sets go to a block per set with device-memory stamps.
+//
 // LT (at most one live in-edge per node): each lane walks one set's chain,
 // kept in LDS with a 256-bit membership signature in registers; longer chains
 // go to the last tier, one lane per chain without visited marks (Brent's
@@ -1102,6 +1105,237 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
   ic_big_run<MODE, WC>(a, io, blockIdx.x);
 }
 
+// ------------------------------------------------------------------------
+// General triggering model (Section 4.2): every dequeued node v draws its
+// triggering set T(v) from an explicit distribution over subsets of its
+// in-edges (trig_pick), and the unvisited members of T(v) join the set.
+// Tier 0: one set per wavefront, its lanes taking up to 64 queued nodes at a
+// time; the queue (also the stored set) and an open-addressing visited hash
+// live in LDS.  Sets that outgrow them are deferred to the last tier, one
+// 512-thread block per set with visited stamps and a queue in device memory.
+// ------------------------------------------------------------------------
+constexpr int kTrigWaves = 4;   // wavefronts per tier-0 block
+constexpr int kTrigQ = 256;     // largest set tier 0 keeps
+constexpr int kTrigHlog = 9;    // 512 hash slots per set
+
+template <int MODE>
+__device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO& io, BlockAcc* blk) {
+  constexpr int H = 1 << kTrigHlog;
+  __shared__ int32_t s_q[kTrigWaves][kTrigQ];
+  __shared__ uint32_t s_h[kTrigWaves][H];
+  __shared__ uint32_t s_tail[kTrigWaves];
+  const int wv = threadIdx.x / kWave;
+  const int lane = threadIdx.x % kWave;
+  int32_t* q = s_q[wv];
+  uint32_t* h = s_h[wv];
+  const GraphView g = a.g;
+  const Key key = make_key(a.seed);
+  const unsigned long long total = a.count;
+  Acc acc;
+  Reservoir res;
+  res.chunk = chunk_for(total, kTrigWaves, 1);
+  unsigned long long pool_next = 0, pool_end = 0;
+  bool exhausted = false;
+  for (;;) {
+    unsigned long long rel = 0;
+    if (!take(a, io.next_ctr, total, res, !exhausted, lane == 0, 0ull, lane, exhausted, rel)) break;
+    const SetStream st = make_set_stream(a.phase, a.first + rel);
+    const int32_t root = draw_root(key, st, g.n);
+    for (int i = lane; i < H; i += kWave) h[i] = 0u;
+    wave_sync();
+    if (lane == 0) {
+      q[0] = root;
+      s_tail[wv] = 1u;
+      lds_insert<kTrigHlog>(h, (uint32_t)root);
+    }
+    wave_sync();
+    bool hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
+    bool bad = false;
+    unsigned long long wlane = 0;
+    int head = 0;
+    for (;;) {
+      const int tail = __builtin_amdgcn_readfirstlane((int)s_tail[wv]);
+      if (head >= tail || hit || bad) break;
+      const int nb = min(tail - head, kWave);
+      bool lbad = false, lhit = false;
+      if (lane < nb) {
+        const int32_t v = q[head + lane];
+        const int64_t ea = g.off[v];
+        wlane += (unsigned long long)(g.off[v + 1] - ea);
+        const int64_t j = trig_pick(g, key, st, v);
+        if (j >= 0) {
+          const int64_t m1 = g.tset[j + 1];
+          for (int64_t i = g.tset[j]; i < m1; ++i) {
+            const int32_t u = g.src[ea + (int64_t)g.tmem[i]];
+            const int r = lds_insert<kTrigHlog>(h, (uint32_t)u);
+            if (r < 0) {
+              lbad = true;
+              break;
+            }
+            if (r == 1) {
+              const uint32_t pos = atomicAdd(&s_tail[wv], 1u);
+              if (pos < (uint32_t)kTrigQ) q[pos] = u;
+              else lbad = true;
+              if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+            }
+          }
+        }
+      }
+      head += nb;
+      wave_sync();
+      bad = __ballot(lbad) != 0ull;
+      hit = hit || __ballot(lhit) != 0ull;
+    }
+    const unsigned long long width = seg_sum<kWave>(wlane);
+    const uint32_t len = min((uint32_t)__builtin_amdgcn_readfirstlane((int)s_tail[wv]), (uint32_t)kTrigQ);
+    if (bad && !(MODE == kModeCover && hit)) {
+      if (lane == 0) {
+        const unsigned long long pos = atomicAdd(&a.ctr[io.out_len_ctr], 1ull);
+        if (pos < a.count) io.out_list[pos] = rel;
+      }
+    } else if (MODE == kModeEmit) {
+      const uint32_t mine = lane == 0 ? len : 0u;
+      const unsigned long long my_base =
+          pool_place(a, (unsigned long long)a.pool_chunk, mine, len, len, pool_next, pool_end, lane);
+      const unsigned long long base = __shfl(my_base, 0);
+      if (base + len <= a.pool_cap)
+        for (uint32_t i = lane; i < len; i += kWave) a.pool[base + i] = q[i];
+      if (lane == 0) {
+        a.set_start[rel] = a.pool_base + base;
+        a.set_len[rel] = len;
+        if (a.widths) a.widths[rel] = width;
+        if (a.wbuf) a.wbuf[rel] = (uint32_t)width;
+        acc.width += width;
+        acc.nodes += len;
+      }
+    } else if (lane == 0) {
+      acc.width += width;
+      acc.nodes += len;
+      if (MODE == kModeWidth) {
+        a.wbuf[rel] = (uint32_t)width;
+        if (a.sizes) a.sizes[rel] = len;
+      } else if (hit) {
+        acc.covered += 1;
+      }
+    }
+    wave_sync();
+  }
+  flush_acc(a, blk, acc, io.acc, lane);
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kTrigWaves* kWave) void trig_wave_kernel(SampleArgs a, TierIO io) {
+  __shared__ BlockAcc blk;
+  block_acc_init(blk);
+  trig_wave_run<MODE>(a, io, &blk);
+}
+
+// Last tier of the triggering model: one block per deferred set.
+template <int MODE>
+__global__ __launch_bounds__(kBigThreads) void trig_big_kernel(SampleArgs a, TierIO io) {
+  constexpr int T = kBigThreads;
+  __shared__ unsigned long long s_red[T / kWave];
+  __shared__ unsigned long long s_idx, s_base;
+  __shared__ uint32_t s_tail, s_epoch;
+  __shared__ int s_hit;
+  const int slot = blockIdx.x;
+  const int tid = threadIdx.x;
+  const int lane = tid % kWave, wv = tid / kWave;
+  const GraphView g = a.g;
+  const Key key = make_key(a.seed);
+  uint32_t* stamp = a.big_stamp + (size_t)slot * (size_t)a.big_stride;
+  int32_t* queue = a.big_queue + (size_t)slot * (size_t)a.big_stride;
+  const unsigned long long ndef = list_len(a, io.in_len_ctr);
+  Acc acc;
+  for (;;) {
+    if (tid == 0) {
+      s_idx = atomicAdd(&a.ctr[io.next_ctr], 1ull);
+      s_epoch = a.big_epoch[slot] + 1u;
+    }
+    __syncthreads();
+    const unsigned long long idx = s_idx;
+    if (idx >= ndef) break;
+    uint32_t epoch = s_epoch;
+    if (epoch == 0u) {  // stamp counter wrapped: start the slot afresh
+      for (uint64_t i = tid; i < a.big_stride; i += T) stamp[i] = 0u;
+      epoch = 1u;
+    }
+    const unsigned long long rel = io.in_list[idx];
+    const SetStream st = make_set_stream(a.phase, a.first + rel);
+    const int32_t root = draw_root(key, st, g.n);
+    __syncthreads();
+    if (tid == 0) {
+      a.big_epoch[slot] = epoch;
+      stamp[root] = epoch;
+      queue[0] = root;
+      s_tail = 1u;
+      s_hit = (MODE == kModeCover && in_seed(a.seed_bits, root)) ? 1 : 0;
+    }
+    __syncthreads();
+    int64_t head = 0;
+    unsigned long long wloc = 0;
+    for (;;) {
+      const int64_t tail = (int64_t)s_tail;
+      const int hit = s_hit;
+      __syncthreads();  // every thread has read the tail before any appends
+      if (head >= tail || hit) break;
+      const int64_t nb = min<int64_t>(tail - head, (int64_t)T);
+      if (tid < nb) {
+        const int32_t v = queue[head + tid];
+        const int64_t ea = g.off[v];
+        wloc += (unsigned long long)(g.off[v + 1] - ea);
+        const int64_t j = trig_pick(g, key, st, v);
+        if (j >= 0) {
+          const int64_t m1 = g.tset[j + 1];
+          for (int64_t i = g.tset[j]; i < m1; ++i) {
+            const int32_t u = g.src[ea + (int64_t)g.tmem[i]];
+            if (atomicExch(&stamp[u], epoch) != epoch) {
+              const uint32_t pos = atomicAdd(&s_tail, 1u);
+              queue[pos] = u;
+              if (MODE == kModeCover && in_seed(a.seed_bits, u)) s_hit = 1;
+            }
+          }
+        }
+      }
+      head += nb;
+      __syncthreads();
+    }
+    const unsigned long long wsum_w = seg_sum<kWave>(wloc);
+    if (lane == 0) s_red[wv] = wsum_w;
+    __syncthreads();
+    const uint32_t len = s_tail;
+    unsigned long long width = 0;
+    for (int w = 0; w < T / kWave; ++w) width += s_red[w];
+    if (MODE == kModeEmit) {
+      if (tid == 0) {
+        const unsigned long long b = atomicAdd(&a.ctr[kCtrPoolCursor], (unsigned long long)len);
+        s_base = b;
+        a.set_start[rel] = a.pool_base + b;
+        a.set_len[rel] = len;
+        if (a.widths) a.widths[rel] = width;
+        if (a.wbuf) a.wbuf[rel] = (uint32_t)width;
+        acc.width += width;
+        acc.nodes += len;
+      }
+      __syncthreads();
+      const unsigned long long b = s_base;
+      if (b + len <= a.pool_cap)
+        for (uint32_t i = tid; i < len; i += T) a.pool[b + i] = queue[i];
+    } else if (tid == 0) {
+      acc.width += width;
+      acc.nodes += len;
+      if (MODE == kModeWidth) {
+        a.wbuf[rel] = (uint32_t)width;
+        if (a.sizes) a.sizes[rel] = len;
+      } else if (s_hit) {
+        acc.covered += 1;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid == 0) block_flush(a, acc, io.acc);
+}
+
 // LT, chains longer than the first tier's LDS chain: one lane per chain and
 // no visited marks at all.  The walk's pick at a node is a fixed function of
 // (set, node), so the walk is x_{i+1} = f(x_i): it ends where f stops (no
@@ -1515,6 +1749,16 @@ void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, 
 }
 
 template <int MODE>
+void launch_trig(const SampleArgs& a, int grid0, hipStream_t s, hipEvent_t after0) {
+  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
+  const TierIO t2 = {a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2};
+  hipLaunchKernelGGL((trig_wave_kernel<MODE>), dim3(grid0), dim3(kTrigWaves * kWave), 0, s, a, t0);
+  if (after0) (void)hipEventRecord(after0, s);
+  hipLaunchKernelGGL((trig_big_kernel<MODE>), dim3(a.big_slots), dim3(kBigThreads), 0, s, a, t2);
+  if (MODE == kModeWidth || (MODE == kModeEmit && a.wbuf)) launch_kappa_reduce(a, s);
+}
+
+template <int MODE>
 void launch_lt(const SampleArgs& a, int grid0, int grid2, hipStream_t s, hipEvent_t after0) {
   const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
   const TierIO t2 = {a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2};
@@ -1617,8 +1861,17 @@ int lt_lane_blocks_per_cu(int mode) {
   }
 }
 
+int trig_blocks_per_cu(int mode) {
+  switch (mode) {
+    case 0: return blocks_per_cu(trig_wave_kernel<kModeWidth>, kTrigWaves * kWave);
+    case 1: return blocks_per_cu(trig_wave_kernel<kModeEmit>, kTrigWaves * kWave);
+    default: return blocks_per_cu(trig_wave_kernel<kModeCover>, kTrigWaves * kWave);
+  }
+}
+
 uint32_t tier0_set_cap(int model, int seg_lanes) {
   if (model == 1) return (uint32_t)kChain;
+  if (model == 2) return (uint32_t)kTrigQ;
   switch (seg_lanes) {
     case 4: return 64;
     case 8: return 128;
@@ -1690,6 +1943,12 @@ void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int 
       case 3: launch_ic<kModeEmit, true>(a, S, grid0, grid1, s, after_tier0); break;
       case 4: launch_ic<kModeCover, false>(a, S, grid0, grid1, s, after_tier0); break;
       default: launch_ic<kModeCover, true>(a, S, grid0, grid1, s, after_tier0); break;
+    }
+  } else if (model == 2) {
+    switch (mode) {
+      case 0: launch_trig<kModeWidth>(a, grid0, s, after_tier0); break;
+      case 1: launch_trig<kModeEmit>(a, grid0, s, after_tier0); break;
+      default: launch_trig<kModeCover>(a, grid0, s, after_tier0); break;
     }
   } else {
     switch (mode) {

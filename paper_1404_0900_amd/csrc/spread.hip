@@ -3,8 +3,9 @@
 // the mean spread over independent runs.  Run r is the live-edge world of
 // phase 65 and set id r: IC edge e is live iff its coin word (kind 1, group
 // e >> 2, word e & 3) is at most its threshold, and in LT node v's live
-// in-edge is the one its pick draw (kind 2, index v) selects - the same rules
-// the RR-set samplers use (pick.hpp).  A run's spread is the number of nodes
+// in-edge is the one its pick draw (kind 2, index v) selects, and under the
+// general triggering model v's live in-edges are the set its draw of kind 3
+// selects - the same rules the RR-set samplers use (pick.hpp).  A run's spread is the number of nodes
 // reachable from S along live edges, found by a forward BFS over the graph's
 // out-edge lists (built once from the in-CSR and kept with the graph).
 #include "engine.hpp"
@@ -128,6 +129,12 @@ __global__ __launch_bounds__(kThreads) void spread_kernel(SpreadArgs a) {
           const uint4 c = draw(key, st, kKindCoin, (uint64_t)e >> 2);
           const uint32_t words[4] = {c.x, c.y, c.z, c.w};
           live = edge_live<WC>(words[e & 3], WC ? 0u : g.thr[e], din);
+        } else if (MODEL == 2) {
+          // general triggering: e is live iff it belongs to the set v draws
+          const int64_t j = trig_pick(g, key, st, v);
+          live = false;
+          if (j >= 0)
+            for (int64_t i = g.tset[j]; i < g.tset[j + 1]; ++i) live = live || iv + (int64_t)g.tmem[i] == e;
         } else {
           live = lt_pick_edge(g, key, st, v, iv, din) == e;
         }
@@ -162,6 +169,8 @@ void launch_spread(int model, const SpreadArgs& a, hipStream_t s) {
   if (model == 0) {
     if (a.g.thr) hipLaunchKernelGGL((spread_kernel<0, false>), grid, blk, 0, s, a);
     else hipLaunchKernelGGL((spread_kernel<0, true>), grid, blk, 0, s, a);
+  } else if (model == 2) {
+    hipLaunchKernelGGL((spread_kernel<2, false>), grid, blk, 0, s, a);
   } else {
     hipLaunchKernelGGL((spread_kernel<1, false>), grid, blk, 0, s, a);
   }

@@ -162,34 +162,37 @@ def random_triggering(g: Graph, seed: int, max_outcomes: int = 4, max_size: int 
     J = int(toff[-1])
     od = np.repeat(d, nout)  # in-degree of each outcome's node
     size = 1 + (rng.integers(0, 2**31, size=J) % np.minimum(od, max_size))
-    # up to three distinct local indices per outcome (sequential draws skipping the ones taken)
-    r = rng.integers(0, 2**62, size=(J, 3))
-    a = r[:, 0] % od
-    b = r[:, 1] % np.maximum(od - 1, 1)
-    b = np.where(b >= a, b + 1, b)
-    lo_ab, hi_ab = np.minimum(a, b), np.maximum(a, b)
-    c = r[:, 2] % np.maximum(od - 2, 1)
-    c = np.where(c >= lo_ab, c + 1, c)
-    c = np.where(c >= hi_ab, c + 1, c)
-    picks = np.stack([a, b, c], axis=1)
-    keep = np.arange(3)[None, :] < size[:, None]
-    picks = np.where(keep, picks, np.iinfo(np.int64).max)
+    # up to max_size distinct local indices per outcome: draw c-th pick uniformly among the od - c
+    # indices not taken yet (skip past the taken ones in increasing order)
+    big = np.iinfo(np.int64).max
+    picks = np.full((J, max_size), big, dtype=np.int64)
+    r = rng.integers(0, 2**62, size=(J, max_size))
+    for c in range(max_size):
+        x = r[:, c] % np.maximum(od - c, 1)
+        taken = np.sort(picks[:, :c], axis=1)
+        for t in range(c):
+            x = np.where(x >= taken[:, t], x + 1, x)
+        picks[:, c] = np.where(c < size, x, big)
+    keep = np.arange(max_size)[None, :] < size[:, None]
     picks.sort(axis=1)
     tset = np.zeros(J + 1, dtype=np.int64)
     tset[1:] = np.cumsum(size)
     tmem = picks[keep].astype(np.uint32) if J else np.zeros(0, dtype=np.uint32)
-    # cumulative thresholds
-    w = rng.integers(1, 2**16 + 1, size=J).astype(object)
+    # cumulative thresholds (S_j * F * 2^16 < 2^(16 + log2(max_outcomes)) * 2^32: exact in int64 up to 2^14
+    # outcomes per node)
+    assert max_outcomes <= 2**14
+    w = rng.integers(1, 2**16 + 1, size=J).astype(np.int64)
     full = rng.random(g.n) < p_full
-    F = np.where(full, 2**16, rng.integers(int(mass[0] * 2**16), int(mass[1] * 2**16) + 1, size=g.n))
-    tthr = np.zeros(J, dtype=np.uint32)
-    for v in np.flatnonzero(nout):
-        j0, j1 = int(toff[v]), int(toff[v + 1])
-        ws = [int(x) for x in w[j0:j1]]
-        S, acc = sum(ws), 0
-        for j, x in enumerate(ws):
-            acc += x
-            tthr[j0 + j] = max(0, (acc * int(F[v]) * 2**16) // S - 1)
+    F = np.where(full, 2**16, rng.integers(int(mass[0] * 2**16), int(mass[1] * 2**16) + 1, size=g.n)).astype(np.int64)
+    cum = np.cumsum(w)
+    first = np.repeat(toff[:-1], nout)  # first outcome of each outcome's node
+    before = np.where(first > 0, cum[np.maximum(first - 1, 0)], 0)
+    s_j = cum - before
+    S = np.repeat(np.where(nout > 0, cum[np.maximum(toff[1:] - 1, 0)] - np.where(toff[:-1] > 0,
+                                                                                  cum[np.maximum(toff[:-1] - 1, 0)],
+                                                                                  0), 1), nout)
+    Fo = np.repeat(F, nout)
+    tthr = np.maximum((s_j * Fo * 2**16) // S - 1, 0).astype(np.uint32)
     return Triggering(toff, tthr, tset, tmem)
 
 
