@@ -418,6 +418,10 @@ def batch_main(args):
         sequential()
         eng.run_batch(batch)
         log(f"warmup {i + 1}/{args.warmup} done")
+    # the granularity of the batch's device KptEstimation work queue, timed before the steps
+    tune = eng.autotune_batch(batch)
+    log(f"batch autotune: {[int(c) for c in tune.caps]} sets per query and step -> "
+        f"{[round(x, 2) for x in tune.ms_kpt]} ms; kept {int(tune.job_cap)}")
     t_seq, t_bat, identical, info = [], [], True, None
     sets = 0
     for i in range(args.steps):
@@ -431,7 +435,9 @@ def batch_main(args):
         identical = identical and same(seq, bat)
         sets = sum(int(r.sets_total) for _, _, r in bat)
         log(f"step {i + 1}/{args.steps}: sequential {t_seq[-1]:.3f} s, batched {t_bat[-1]:.3f} s "
-            f"({info.rounds} rounds, {info.launches} launches, up to {info.max_jobs} jobs), identical={identical}")
+            f"(device KptEstimation {info.ms_kpt:.1f} ms in {info.kpt_steps} steps / {info.kpt_graph_launches} "
+            f"graph launches; then {info.rounds} rounds, {info.launches} launches, up to {info.max_jobs} jobs), "
+            f"identical={identical}")
     ts, tb = statistics.median(t_seq), statistics.median(t_bat)
 
     # one more batch with per-launch timing, for the roofline of the dominant batched kernel
@@ -462,6 +468,10 @@ def batch_main(args):
         "sequential": {"value": round(64 / ts, 3), "unit": "queries/s", "ms_per_step": round(ts * 1e3, 3)},
         "speedup_vs_sequential": round(ts / tb, 3),
         "identical_outputs": identical,
+        "device_kpt": {"ms": round(info.ms_kpt, 3), "steps": int(info.kpt_steps),
+                       "graph_launches": int(info.kpt_graph_launches), "job_cap": int(info.kpt_job_cap),
+                       "autotune_caps": [int(c) for c in tune.caps],
+                       "autotune_ms": [round(x, 3) for x in tune.ms_kpt]},
         "rounds": int(info.rounds), "launches": int(info.launches), "max_jobs": int(info.max_jobs),
         "rr_sets_per_step": sets,
         "rr_sets_per_s": round(sets / tb, 1),

@@ -413,14 +413,25 @@ typedef struct {
   uint64_t budget_bytes; /* device memory of the batch */
   uint64_t member_budget_bytes; /* each query's share of it */
   double ms_wall;
+  double ms_kpt;         /* tim_run_batch: wall time of the device-driven KptEstimation of all queries */
+  uint64_t kpt_job_cap;  /* tim_run_batch: most sets a query's job held per KptEstimation step */
+  uint64_t kpt_steps;    /* tim_run_batch: device KptEstimation steps run (rounds, launches and jobs above
+                            count the batched RefineKPT and NodeSelection requests) */
+  uint64_t kpt_graph_launches; /* ... and launches of their captured HIP graph */
 } tim_batch_info;
 
 /* Runs `count` independent TIM / TIM+ queries (Sections 3.3 and 4.1) at
- * once, at most max_concurrent at a time (0: all).  Each query runs the
- * steps of tim_run in a host thread of its own with buffers of its own;
- * the RR sets every query needs at the same point (a KptEstimation round,
- * RefineKPT's sets, NodeSelection's sets) are gathered into one GPU launch
- * whose wavefronts move from query to query as their work runs out.  Each
+ * once, at most max_concurrent at a time (0: all).  First, KptEstimation
+ * (Algorithm 2) of every query runs on the device with no host step between
+ * rounds: a device work queue hands each query chunks of its current round
+ * (at most the granularity tim_autotune_batch keeps), persistent multi-query
+ * samplers whose wavefronts move from query to query run them, and a device
+ * kernel adds each chunk to its round and takes the stop test; these steps
+ * are captured in a HIP graph and replayed until every query has stopped.
+ * Then each query runs RefineKPT and NodeSelection in a host thread of its
+ * own with buffers of its own; the RR sets every query needs at the same
+ * point (RefineKPT's sets, NodeSelection's sets) are gathered into one GPU
+ * launch whose wavefronts move from query to query as their work runs out.  Each
  * query's seeds, gains and report values other than times and memory
  * figures are those tim_run gives it alone.  The batch's memory is the
  * context's budget less what it holds (without one: 85% of the free device
@@ -434,6 +445,21 @@ typedef struct {
  * round waits for the queries in flight to join it is 1 ms (environment
  * variable TIM_BATCH_WINDOW_US, read per call). */
 tim_status tim_run_batch(tim_ctx *ctx, tim_query *queries, int count, int max_concurrent, tim_batch_info *info);
+
+/* What tim_autotune_batch measured and chose. */
+typedef struct {
+  uint64_t job_cap;   /* the granularity kept: most sets of one query per device KptEstimation step */
+  uint64_t caps[4];   /* the candidates: 2^16, 2^18, 2^20, 2^22 */
+  double ms_kpt[4];   /* wall time of the batch's device KptEstimation with each (best of 2) */
+} tim_batch_tune;
+
+/* Times the device-driven KptEstimation of tim_run_batch on these queries
+ * (arguments as for tim_run_batch; nothing is written to their outputs)
+ * with each candidate granularity of its work queue - the most sets one
+ * query's job holds per step - and keeps the fastest for ctx's later
+ * batches if it beats the current one by 3% (default 2^20).  Results of
+ * every call do not depend on it.  out (host) may be NULL. */
+tim_status tim_autotune_batch(tim_ctx *ctx, tim_query *queries, int count, tim_batch_tune *out);
 
 /* ---- serving: queries that arrive over time ------------------------------ */
 

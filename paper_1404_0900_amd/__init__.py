@@ -30,7 +30,7 @@ EXPORTED = ("tim_ctx_create", "tim_ctx_destroy", "tim_last_error", "tim_ctx_devi
             "tim_graph_free", "tim_sample_rr", "tim_sample_widths", "tim_sample_cover", "tim_max_coverage",
             "tim_max_coverage_noalloc",
             "tim_kpt_estimate", "tim_refine_kpt", "tim_node_select", "tim_run", "tim_profile_enable",
-            "tim_profile_read", "tim_autotune", "tim_spread_mc", "tim_run_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
+            "tim_profile_read", "tim_autotune", "tim_spread_mc", "tim_run_batch", "tim_autotune_batch", "tim_server_start", "tim_server_submit", "tim_server_wait",
             "tim_server_stop")
 
 U64, I64, U32, I32, DBL, P = (ctypes.c_uint64, ctypes.c_int64, ctypes.c_uint32, ctypes.c_int32, ctypes.c_double,
@@ -99,7 +99,12 @@ class Query(ctypes.Structure):
 
 class BatchInfo(ctypes.Structure):
     _fields_ = [("rounds", U64), ("jobs", U64), ("launches", U64), ("max_jobs", U64), ("workers", U64),
-                ("budget_bytes", U64), ("member_budget_bytes", U64), ("ms_wall", DBL)]
+                ("budget_bytes", U64), ("member_budget_bytes", U64), ("ms_wall", DBL), ("ms_kpt", DBL),
+                ("kpt_job_cap", U64), ("kpt_steps", U64), ("kpt_graph_launches", U64)]
+
+
+class BatchTune(ctypes.Structure):
+    _fields_ = [("job_cap", U64), ("caps", U64 * 4), ("ms_kpt", DBL * 4)]
 
 
 MODE_NAMES = ("widths", "store", "cover")
@@ -149,6 +154,7 @@ def load_library():
                                          ctypes.POINTER(DBL), ctypes.POINTER(U64)]),
         "tim_run_batch": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.c_int, ctypes.c_int,
                                          ctypes.POINTER(BatchInfo)]),
+        "tim_autotune_batch": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.c_int, ctypes.POINTER(BatchTune)]),
         "tim_server_start": (ctypes.c_int, [P, ctypes.c_int, ctypes.POINTER(P)]),
         "tim_server_submit": (ctypes.c_int, [P, ctypes.POINTER(Query), ctypes.POINTER(U64)]),
         "tim_server_wait": (ctypes.c_int, [P, U64, ctypes.POINTER(DBL)]),
@@ -410,6 +416,21 @@ class Engine:
         info = BatchInfo()
         _check(self.lib.tim_run_batch(self.ctx, arr, nq, max_concurrent, ctypes.byref(info)))
         return keep, info
+
+    def autotune_batch(self, queries) -> BatchTune:
+        """Times the batch's device KptEstimation with each work-queue granularity and keeps the fastest."""
+        nq = len(queries)
+        arr = (Query * max(nq, 1))()
+        keep = []
+        for i, q in enumerate(queries):
+            g, model, k, eps, ell, seed = q[:6]
+            flags = q[6] if len(q) > 6 else 0
+            seeds = np.zeros(k, dtype=np.int32)
+            keep.append(seeds)
+            arr[i] = Query(g.handle, model, k, eps, ell, seed, flags, seeds.ctypes.data, None, None, 0)
+        out = BatchTune()
+        _check(self.lib.tim_autotune_batch(self.ctx, arr, nq, ctypes.byref(out)))
+        return out
 
 
 class Server:

@@ -125,6 +125,7 @@ struct tim_ctx {
   Hub* batch = nullptr;
   std::vector<tim_ctx*> members;
   bool serving = false;  // a server runs on this context
+  uint64_t batch_job_cap = 1ull << 20;  // sets a query's job holds per step of the batch's device KptEstimation
   int64_t max_graph_n = 0;  // largest graph uploaded to this context
   hipEvent_t ready_ev = nullptr;
   bool prof_on = false;
@@ -289,6 +290,7 @@ struct Hub {
   hipEvent_t pev[3] = {nullptr, nullptr, nullptr};
   // statistics
   uint64_t rounds = 0, jobs = 0, launches = 0, max_jobs = 0;
+  uint64_t kpt_steps = 0, kpt_graph_launches = 0;  // the device-driven KptEstimation of tim_run_batch
 };
 
 // Blocks a request waits in until its round has run.
@@ -1265,14 +1267,32 @@ tim_status node_select_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t 
   return TIM_OK;
 }
 
+double ell_of(const tim_graph* g, double ell, uint32_t flags) {
+  if (!(flags & TIM_FLAG_ELL_ADJUST)) return ell;
+  return ell * (1.0 + std::log((flags & TIM_FLAG_PLAIN) ? 2.0 : 3.0) / std::log((double)g->n));
+}
+
+// KPT* from the totals of the rounds of a finished KptEstimation (as kpt_estimate_impl computes it).
+void kpt_finish_result(const tim_graph* g, tim_kpt_result* out) {
+  out->kpt_star = 1.0;
+  const int i = out->i_last;
+  if (i < 1) return;
+  const u128 sum = ((u128)out->round_sum_hi[i] << 64) | (u128)out->round_sum_lo[i];
+  const uint64_t ci = out->round_c[i];
+  if ((sum << i) <= ((u128)ci << 53)) return;
+  out->kpt_star = (std::ldexp((double)sum, -53) * (double)g->n) / (2.0 * (double)ci);
+}
+
+// TIM / TIM+; kpt_in (nullable): a KptEstimation already done for this query
+// (the batch runs Algorithm 2 for all its queries on the device first).
 tim_status run_impl(tim_ctx* c, const tim_graph* g, int model, int k, double eps, double ell, uint64_t seed,
-                    uint32_t flags, int32_t* seeds, uint64_t* gains, tim_report* rep) {
+                    uint32_t flags, int32_t* seeds, uint64_t* gains, tim_report* rep,
+                    const tim_kpt_result* kpt_in = nullptr) {
   tim_report local;
   tim_report* r = rep ? rep : &local;
   memset(r, 0, sizeof(*r));
   const bool plain = (flags & TIM_FLAG_PLAIN) != 0;
-  double ell_used = ell;
-  if (flags & TIM_FLAG_ELL_ADJUST) ell_used = ell * (1.0 + std::log(plain ? 2.0 : 3.0) / std::log((double)g->n));
+  const double ell_used = ell_of(g, ell, flags);
   r->ell_used = ell_used;
   hipEvent_t t0, t1;
   HIP_TRY(hipEventCreate(&t0));
@@ -1286,8 +1306,16 @@ tim_status run_impl(tim_ctx* c, const tim_graph* g, int model, int k, double eps
     (void)hipEventRecord(t0, c->stream);
   };
   (void)hipEventRecord(t0, c->stream);
-  tim_status st =
-      kpt_estimate_impl(c, g, model, seed, k, ell_used, !plain, &r->kpt, &r->sets_total, &r->width_total);
+  tim_status st = TIM_OK;
+  if (kpt_in) {
+    r->kpt = *kpt_in;
+    for (int i = 1; i <= r->kpt.i_last; ++i) {
+      r->sets_total += r->kpt.round_c[i];
+      r->width_total += r->kpt.round_width[i];
+    }
+  } else {
+    st = kpt_estimate_impl(c, g, model, seed, k, ell_used, !plain, &r->kpt, &r->sets_total, &r->width_total);
+  }
   if (st == TIM_OK) lap(&r->ms_kpt);
   // mean set size of the stopping round sizes the node pools
   const int il = r->kpt.i_last;
@@ -1536,13 +1564,14 @@ tim_status hub_member(Hub* h, const tim_ctx* parent, tim_ctx** out) {
 }
 
 void batch_worker(Hub* h, tim_ctx* c, tim_query* qs, int nq, std::atomic<int>* next,
-                  std::vector<std::string>* errs) {
+                  std::vector<std::string>* errs, const std::vector<tim_kpt_result>* kpts) {
   (void)hipSetDevice(c->device);
   for (;;) {
     const int i = next->fetch_add(1);
     if (i >= nq) break;
     tim_query& q = qs[i];
-    q.status = run_impl(c, q.graph, q.model, q.k, q.eps, q.ell, q.seed, q.flags, q.seeds, q.gains, q.report);
+    q.status = run_impl(c, q.graph, q.model, q.k, q.eps, q.ell, q.seed, q.flags, q.seeds, q.gains, q.report,
+                        kpts ? &(*kpts)[(size_t)i] : nullptr);
     if (q.status != TIM_OK) (*errs)[(size_t)i] = g_error;
   }
   c->stored.valid = false;
@@ -1633,6 +1662,7 @@ tim_status hub_prepare(Hub* h, tim_ctx* parent, int64_t maxn, int workers) {
   h->stop = false;
   h->alive = workers;
   h->rounds = h->jobs = h->launches = h->max_jobs = 0;
+  h->kpt_steps = h->kpt_graph_launches = 0;
   return TIM_OK;
 }
 
@@ -1652,6 +1682,163 @@ void hub_destroy(tim_ctx* parent) {
   if (h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
   parent->batch = nullptr;
+}
+
+// ---- batches: Algorithm 2 of every query on the device ----
+//
+// tim_run_batch first runs KptEstimation for all its queries without the
+// host between rounds: per class of queries (model, thresholds), up to 64 at
+// a time, a step hands each query a chunk of its current round (kpt_jobs),
+// the batched samplers run the chunks (their wavefronts move from query to
+// query), and kpt_advance adds the chunks' totals to their rounds and takes
+// Algorithm 2's stop test where a round is complete.  kKptGraphSteps steps
+// are captured as one HIP graph, replayed until no query is left; the host
+// reads one flag per replay.  The queries' RefineKPT and NodeSelection then
+// run as before (worker threads, the hub batching their sampling requests);
+// R' of RefineKPT is generated again from its keys.
+constexpr int kKptGraphSteps = 4;
+
+// Sets in all per step: bounded by the batch's memory (20 bytes per set).
+uint64_t kpt_step_cap(uint64_t limit) {
+  return std::max<uint64_t>(1ull << 16, std::min<uint64_t>(1ull << 23, limit / 4 / 20));
+}
+
+tim_status batch_kpt_group(tim_ctx* c, Hub* h, tim_query* qs, const std::vector<int>& idx, int model, bool wc,
+                           uint64_t job_cap, std::vector<tim_kpt_result>* out) {
+  const int nq = (int)idx.size();
+  std::vector<tim::KptQuery> hq((size_t)nq);
+  std::vector<int> live;  // queries with at least one round
+  for (int j = 0; j < nq; ++j) {
+    const tim_query& q = qs[idx[(size_t)j]];
+    const tim_graph* g = q.graph;
+    tim_kpt_result& r = (*out)[(size_t)idx[(size_t)j]];
+    memset(&r, 0, sizeof(r));
+    const int imax = rounds_of(g->n);
+    r.i_max = imax;
+    r.i_last = imax;
+    r.c_last = imax >= 1 ? round_size(g->n, ell_of(g, q.ell, q.flags), imax) : 0;
+    r.kpt_star = 1.0;
+    tim::KptQuery& d = hq[(size_t)j];
+    memset(&d, 0, sizeof(d));
+    d.g.off = g->off;
+    d.g.src = g->src;
+    d.g.thr = g->thr;
+    d.g.lthr = g->lthr;
+    d.g.n = g->n;
+    d.g.m = g->m;
+    d.seed = q.seed;
+    d.k = q.k;
+    d.imax = imax;
+    d.round = imax >= 1 ? 1 : 0;
+    d.i_last = imax;
+    for (int i = 1; i <= imax && i < tim::kKptMaxRounds; ++i) d.c[i] = round_size(g->n, ell_of(g, q.ell, q.flags), i);
+  }
+  const uint64_t step_cap = kpt_step_cap(h->limit > h->big_bytes ? h->limit - h->big_bytes : 0);
+  TIM_TRY(ensure(c, c->wbuf, step_cap * 4, "width buffer"));
+  TIM_TRY(ensure(c, c->list1, step_cap * 8, "deferred-set list"));
+  if (model == TIM_MODEL_IC) TIM_TRY(ensure(c, c->list2, step_cap * 8, "deferred-set list"));
+  const size_t qbytes = ((size_t)nq * sizeof(tim::KptQuery) + 255) & ~(size_t)255;
+  const size_t jbytes = ((size_t)nq * sizeof(SampleArgs) + 255) & ~(size_t)255;
+  const size_t cbytes = (size_t)nq * tim::kCtrCount * 8;
+  TIM_TRY(ensure(c, c->jobs, qbytes + jbytes + cbytes + 256, "batch KptEstimation state"));
+  char* base = static_cast<char*>(c->jobs.p);
+  tim::KptStepArgs a;
+  memset(&a, 0, sizeof(a));
+  a.q = reinterpret_cast<tim::KptQuery*>(base);
+  a.nq = nq;
+  a.jobs = reinterpret_cast<SampleArgs*>(base + qbytes);
+  a.ctr = reinterpret_cast<unsigned long long*>(base + qbytes + jbytes);
+  a.active = reinterpret_cast<unsigned int*>(base + qbytes + jbytes + cbytes);
+  a.wbuf = c->wbuf.as<uint32_t>();
+  a.list1 = c->list1.as<uint64_t>();
+  a.list2 = model == TIM_MODEL_IC ? c->list2.as<uint64_t>() : nullptr;
+  a.step_cap = step_cap;
+  a.job_cap = std::max<uint64_t>(1, job_cap);
+  a.big_stamp = h->big_stamp;
+  a.big_queue = h->big_queue;
+  a.big_epoch = h->big_epoch;
+  a.big_slots = h->big_slots;
+  a.big_stride = h->big_stride;
+  HIP_TRY(hipMemcpyAsync(a.q, hq.data(), (size_t)nq * sizeof(tim::KptQuery), hipMemcpyHostToDevice, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+
+  // the steps, captured once as a graph
+  const tim::JobTable tab{a.jobs, nq, 0};
+  const int mode = tim::kModeWidth;
+  const uint64_t grid0 = (uint64_t)h->grid0[model][mode][wc ? 1 : 0] * (uint64_t)h->num_cu;
+  const uint64_t grid1 =
+      (uint64_t)(model == TIM_MODEL_IC ? h->grid1[mode][wc ? 1 : 0] : h->grid_chain[mode]) * (uint64_t)h->num_cu;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  HIP_TRY(hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+  for (int st = 0; st < kKptGraphSteps; ++st) {
+    tim::launch_kpt_jobs(a, h->stream);
+    tim::launch_clear_counters_batch(tab, h->stream);
+    tim::launch_sample_batch(model, mode, wc, tab, (int)grid0, (int)grid1, h->big_slots, step_cap, h->stream, nullptr);
+    tim::launch_kpt_advance(a, h->stream);
+  }
+  const hipError_t ce = hipStreamEndCapture(h->stream, &graph);
+  if (ce != hipSuccess) return fail(TIM_EDEVICE, "capture of the KptEstimation steps: %s", hipGetErrorString(ce));
+  struct GraphScope {
+    hipGraph_t g;
+    hipGraphExec_t e;
+    ~GraphScope() {
+      if (e) (void)hipGraphExecDestroy(e);
+      if (g) (void)hipGraphDestroy(g);
+    }
+  } scope{graph, nullptr};
+  HIP_TRY(hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0));
+  scope.e = exec;
+  unsigned int* active_host = reinterpret_cast<unsigned int*>(c->ctr_host);
+  for (int launches = 0;; ++launches) {
+    if (launches > 1 << 16) return fail(TIM_EDEVICE, "batch KptEstimation did not finish");
+    HIP_TRY(hipGraphLaunch(exec, h->stream));
+    HIP_TRY(hipMemcpyAsync(active_host, a.active, 4, hipMemcpyDeviceToHost, h->stream));
+    HIP_TRY(hipStreamSynchronize(h->stream));
+    h->kpt_steps += kKptGraphSteps;
+    h->kpt_graph_launches += 1;
+    if (*active_host == 0u) break;
+  }
+  HIP_TRY(hipMemcpyAsync(hq.data(), a.q, (size_t)nq * sizeof(tim::KptQuery), hipMemcpyDeviceToHost, h->stream));
+  HIP_TRY(hipStreamSynchronize(h->stream));
+  for (int j = 0; j < nq; ++j) {
+    const tim::KptQuery& d = hq[(size_t)j];
+    if (d.err) return fail(TIM_EDEVICE, "deferred-set list overflow");
+    tim_kpt_result& r = (*out)[(size_t)idx[(size_t)j]];
+    if (d.imax < 1) continue;
+    r.i_last = d.i_last;
+    r.c_last = d.c[d.i_last];
+    for (int i = 1; i <= d.i_last; ++i) {
+      r.round_c[i] = d.c[i];
+      r.round_sum_lo[i] = d.r_lo[i];
+      r.round_sum_hi[i] = d.r_hi[i];
+      r.round_width[i] = d.r_width[i];
+      r.round_nodes[i] = d.r_nodes[i];
+    }
+    kpt_finish_result(qs[idx[(size_t)j]].graph, &r);
+  }
+  return TIM_OK;
+}
+
+// Algorithm 2 for every query of a batch on the device, by classes of up to 64.
+tim_status batch_kpt(tim_ctx* c, Hub* h, tim_query* qs, int count, uint64_t job_cap,
+                     std::vector<tim_kpt_result>* out) {
+  out->assign((size_t)count, tim_kpt_result());
+  std::vector<int> cls[2][2];
+  for (int i = 0; i < count; ++i) {
+    const tim_query& q = qs[i];
+    const bool wc = q.model != TIM_MODEL_IC || q.graph->thr == nullptr;
+    cls[q.model][wc ? 1 : 0].push_back(i);
+  }
+  for (int model = 0; model < 2; ++model)
+    for (int wc = 0; wc < 2; ++wc)
+      for (size_t lo = 0; lo < cls[model][wc].size(); lo += tim::kMaxBatchJobs) {
+        const size_t hi = std::min(cls[model][wc].size(), lo + (size_t)tim::kMaxBatchJobs);
+        std::vector<int> idx(cls[model][wc].begin() + (long)lo, cls[model][wc].begin() + (long)hi);
+        TIM_TRY(batch_kpt_group(c, h, qs, idx, model, wc != 0, job_cap, out));
+      }
+  for (DevBuf* b : {&c->list1, &c->list2, &c->wbuf, &c->jobs}) release(c, *b);
+  return TIM_OK;
 }
 
 // ---- serving: queries that arrive over time ----
@@ -2360,12 +2547,16 @@ tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_conc
   int64_t maxn = 2;
   for (int i = 0; i < count; ++i) maxn = std::max<int64_t>(maxn, queries[i].graph->n);
   TIM_TRY(hub_prepare(&hub, c, maxn, workers));
+  // Algorithm 2 of every query on the device, then the rest of each query in its worker
+  std::vector<tim_kpt_result> kpts;
+  TIM_TRY(batch_kpt(c, &hub, queries, count, c->batch_job_cap, &kpts));
+  const double ms_kpt = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
   std::atomic<int> next{0};
   std::vector<std::string> errs((size_t)count);
   std::thread sched(hub_scheduler, &hub);
   std::vector<std::thread> pool;
   for (int w = 0; w < workers; ++w)
-    pool.emplace_back(batch_worker, &hub, c->members[(size_t)w], queries, count, &next, &errs);
+    pool.emplace_back(batch_worker, &hub, c->members[(size_t)w], queries, count, &next, &errs, &kpts);
   for (std::thread& t : pool) t.join();
   {
     std::lock_guard<std::mutex> lk(hub.mu);
@@ -2382,9 +2573,63 @@ tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_conc
     info->budget_bytes = hub.limit;
     info->member_budget_bytes = hub.member_budget;
     info->ms_wall = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    info->ms_kpt = ms_kpt;
+    info->kpt_job_cap = c->batch_job_cap;
+    info->kpt_steps = hub.kpt_steps;
+    info->kpt_graph_launches = hub.kpt_graph_launches;
   }
   for (int i = 0; i < count; ++i)
     if (queries[i].status != TIM_OK) return fail(queries[i].status, "query %d: %s", i, errs[(size_t)i].c_str());
+  return TIM_OK;
+}
+
+tim_status tim_autotune_batch(tim_ctx* c, tim_query* queries, int count, tim_batch_tune* out) {
+  if (!c || count < 1 || !queries) return fail(TIM_EINVAL, "null argument or no queries");
+  if (c->hub) return fail(TIM_EINVAL, "context is a batch member");
+  if (c->serving) return fail(TIM_EINVAL, "a server runs on this context");
+  for (int i = 0; i < count; ++i) {
+    const tim_query& q = queries[i];
+    TIM_TRY(check_run_args(c, q.graph, q.model, q.k, q.eps, q.ell, q.seeds));
+    if (q.model == TIM_MODEL_TRIGGER)
+      return fail(TIM_EINVAL, "the general triggering model runs through tim_run, not in batches");
+  }
+  HIP_TRY(hipSetDevice(c->device));
+  if (!c->batch) {
+    c->batch = new Hub();
+    const tim_status st = hub_setup(c->batch, c);
+    if (st != TIM_OK) {
+      hub_destroy(c);
+      return st;
+    }
+  }
+  Hub& hub = *c->batch;
+  int64_t maxn = 2;
+  for (int i = 0; i < count; ++i) maxn = std::max<int64_t>(maxn, queries[i].graph->n);
+  TIM_TRY(hub_prepare(&hub, c, maxn, 1));
+  tim_batch_tune r;
+  memset(&r, 0, sizeof(r));
+  const uint64_t caps[4] = {1ull << 16, 1ull << 18, 1ull << 20, 1ull << 22};
+  std::vector<tim_kpt_result> kpts;
+  int best = -1;
+  for (int j = 0; j < 4; ++j) {
+    r.caps[j] = caps[j];
+    TIM_TRY(batch_kpt(c, &hub, queries, count, caps[j], &kpts));  // untimed
+    double t = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {
+      const auto t0 = std::chrono::steady_clock::now();
+      TIM_TRY(batch_kpt(c, &hub, queries, count, caps[j], &kpts));
+      t = std::min(t, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+    r.ms_kpt[j] = t;
+    if (best < 0 || t < r.ms_kpt[best]) best = j;
+  }
+  // keep the current granularity unless another is 3% faster
+  double cur = 1e300;
+  for (int j = 0; j < 4; ++j)
+    if (caps[j] == c->batch_job_cap) cur = r.ms_kpt[j];
+  if (r.ms_kpt[best] < 0.97 * cur) c->batch_job_cap = caps[best];
+  r.job_cap = c->batch_job_cap;
+  if (out) *out = r;
   return TIM_OK;
 }
 

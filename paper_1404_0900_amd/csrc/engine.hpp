@@ -133,6 +133,48 @@ void launch_clear_counters_batch(const JobTable& t, hipStream_t s);
 void launch_sample_batch(int model, int mode, bool wc, const JobTable& t, int grid0, int grid1, int slots,
                          uint64_t max_count, hipStream_t s, hipEvent_t after_tier0);
 
+// ---- device-driven KptEstimation for a batch of queries (sample.hip) ----
+// Algorithm 2 for up to kMaxBatchJobs queries of one (model, thresholds)
+// class, with the round loop on the device: each step hands every query a
+// chunk of its current round (a device work queue of set-id ranges, at most
+// job_cap sets per query and step_cap in all), runs the batched samplers on
+// those chunks, and adds each chunk's totals to its round; a round whose sets
+// are all done takes the stop test S * 2^i > c_i * 2^53 and the query moves
+// to round i + 1 or stops.  The steps need no host synchronisation, so a
+// run of them is captured in one HIP graph.
+constexpr int kKptMaxRounds = 64;
+struct KptQuery {
+  GraphView g;
+  uint64_t seed;
+  int32_t k, imax;
+  int32_t round;  // current round (1-based); 0 once stopped
+  int32_t i_last;  // round that stopped (imax if none did)
+  int32_t err;     // a deferred-set list overflowed
+  int32_t pad;
+  uint64_t pos;    // next set id of the current round
+  unsigned long long sum_lo, sum_hi, width, nodes;  // totals of the current round so far
+  uint64_t c[kKptMaxRounds];
+  unsigned long long r_lo[kKptMaxRounds], r_hi[kKptMaxRounds], r_width[kKptMaxRounds], r_nodes[kKptMaxRounds];
+};
+struct KptStepArgs {
+  KptQuery* q;
+  int nq;
+  SampleArgs* jobs;            // nq job descriptors (rewritten every step)
+  unsigned long long* ctr;     // nq * kCtrCount counters
+  uint32_t* wbuf;              // step_cap widths
+  uint64_t* list1;             // step_cap deferred ids
+  uint64_t* list2;             // step_cap deferred ids (IC)
+  uint64_t step_cap, job_cap;  // sets per step in all / per query
+  unsigned int* active;        // queries not yet stopped after the last step
+  uint32_t* big_stamp;
+  int32_t* big_queue;
+  uint32_t* big_epoch;
+  int big_slots;
+  uint64_t big_stride;
+};
+void launch_kpt_jobs(const KptStepArgs& a, hipStream_t s);
+void launch_kpt_advance(const KptStepArgs& a, hipStream_t s);
+
 // ---- spread.hip ----
 // Forward Monte-Carlo runs [first, first+runs) of phase 65 from a seed set.
 struct SpreadArgs {

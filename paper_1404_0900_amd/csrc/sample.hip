@@ -1683,6 +1683,88 @@ __global__ void clear_counters_batch_kernel(JobTable t) {
   for (int i = threadIdx.x; i < kCtrCount; i += blockDim.x) ctr[i] = 0ull;
 }
 
+// ---- device-driven KptEstimation (Algorithm 2) for a batch ----
+// One thread hands out this step's chunks: every query still estimating gets
+// the next sets of its current round, up to job_cap, while the step's
+// step_cap sets last; queries with nothing this step get an empty job.
+__global__ void kpt_jobs_kernel(KptStepArgs a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  uint64_t used = 0;
+  for (int j = 0; j < a.nq; ++j) {
+    const KptQuery& q = a.q[j];
+    SampleArgs s = SampleArgs();
+    s.g = q.g;
+    s.seed = q.seed;
+    s.k = q.k;
+    s.ctr = a.ctr + (size_t)j * kCtrCount;
+    s.big_stamp = a.big_stamp;
+    s.big_queue = a.big_queue;
+    s.big_epoch = a.big_epoch;
+    s.big_slots = a.big_slots;
+    s.big_stride = a.big_stride;
+    s.wbuf = a.wbuf + used;
+    s.list1 = a.list1 + used;
+    s.list2 = a.list2 ? a.list2 + used : nullptr;
+    if (q.round > 0 && !q.err) {
+      const uint64_t left = q.c[q.round] - q.pos;
+      uint64_t take = left < a.job_cap ? left : a.job_cap;
+      take = take < a.step_cap - used ? take : a.step_cap - used;
+      s.phase = (uint32_t)q.round;
+      s.first = q.pos;
+      s.count = take;
+      used += take;
+    }
+    a.jobs[j] = s;
+  }
+}
+
+// One thread per query: adds the step's totals of its chunk to its round,
+// and a round whose sets are all done takes the stop test of Algorithm 2.
+__global__ void kpt_advance_kernel(KptStepArgs a) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= a.nq) return;
+  KptQuery& q = a.q[j];
+  const SampleArgs& s = a.jobs[j];
+  if (q.round > 0 && s.count > 0) {
+    const unsigned long long* h = s.ctr;
+    if (h[kCtrList1] > s.count || h[kCtrList2] > s.count) q.err = 1;
+    u128 sum = ((u128)q.sum_hi << 64) | (u128)q.sum_lo;
+    for (int tier = 0; tier < 3; ++tier) {
+      const unsigned long long* acc = h + kCtrAcc + kAccStride * tier;
+      sum += ((u128)acc[kAccKappaHi] << 64) | (u128)acc[kAccKappaLo];
+      q.width += acc[kAccWidth];
+      q.nodes += acc[kAccNodes];
+    }
+    q.sum_lo = (unsigned long long)sum;
+    q.sum_hi = (unsigned long long)(sum >> 64);
+    q.pos += s.count;
+    const int i = q.round;
+    if (q.pos == q.c[i]) {
+      q.r_lo[i] = q.sum_lo;
+      q.r_hi[i] = q.sum_hi;
+      q.r_width[i] = q.width;
+      q.r_nodes[i] = q.nodes;
+      // sum / c_i > 2^-i with sum = S * 2^-53: S * 2^i > c_i * 2^53 (exact)
+      if ((sum << i) > ((u128)q.c[i] << 53)) {
+        q.i_last = i;
+        q.round = 0;
+      } else if (i >= q.imax) {
+        q.i_last = q.imax;
+        q.round = 0;
+      } else {
+        q.round = i + 1;
+        q.pos = 0;
+        q.sum_lo = q.sum_hi = q.width = q.nodes = 0;
+      }
+    }
+  }
+  if (q.round > 0 && !q.err) atomicAdd(a.active, 1u);
+}
+
+__global__ void kpt_clear_active_kernel(unsigned int* active) {
+  if (threadIdx.x == 0) *active = 0u;
+}
+
 template <typename K>
 int blocks_per_cu(K kernel, int threads) {
   int nb = 0;
@@ -1903,6 +1985,15 @@ int batch_blocks_per_cu(int model, int mode, bool wc, int tier) {
     case 10: return blocks_per_cu((BatchKernels<kModeCover, false>::seg1), kSegThreads);
     default: return blocks_per_cu((BatchKernels<kModeCover, true>::seg1), kSegThreads);
   }
+}
+
+void launch_kpt_jobs(const KptStepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(kpt_jobs_kernel, dim3(1), dim3(64), 0, s, a);
+}
+
+void launch_kpt_advance(const KptStepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(kpt_clear_active_kernel, dim3(1), dim3(64), 0, s, a.active);
+  hipLaunchKernelGGL(kpt_advance_kernel, dim3((unsigned)((a.nq + 63) / 64)), dim3(64), 0, s, a);
 }
 
 void launch_clear_counters_batch(const JobTable& t, hipStream_t s) {

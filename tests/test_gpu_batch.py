@@ -17,8 +17,9 @@ import synth
 pytestmark = pytest.mark.gpu
 IC, LT = 0, 1
 
-KEYS = ("ell_used", "lambda", "i_max", "i_last", "c_last", "kpt_star", "round_sums", "theta", "ns_nodes", "ns_width",
-        "ns_covered", "eps_prime", "lambda_prime", "theta_prime", "covered_prime", "kpt_prime", "kpt_plus")
+KEYS = ("ell_used", "lambda", "i_max", "i_last", "c_last", "kpt_star", "round_sums", "round_c", "round_width",
+        "round_nodes", "theta", "ns_nodes", "ns_width", "ns_covered", "eps_prime", "lambda_prime", "theta_prime",
+        "covered_prime", "kpt_prime", "kpt_plus")
 
 
 def _say(*a):
@@ -82,6 +83,21 @@ def test_batch_equals_queries_alone(eng, mixed):
     _say(f"batch: rounds={info.rounds} jobs={info.jobs} launches={info.launches} max_jobs={info.max_jobs} "
          f"wall={info.ms_wall:.1f} ms")
     assert info.rounds > 0 and info.jobs >= len(up) and info.max_jobs > 1
+    for (q, *_), got, want in zip(up, res, alone):
+        _same(got, want, q["name"])
+
+
+def test_batch_device_kpt_granularity_keeps_results(eng, mixed):
+    """The batch's KptEstimation runs on the device in chunks of at most the work-queue granularity; the
+    autotuner times each candidate (2^16 .. 2^22 sets per query and step) and the results stay those of
+    every query alone, whichever it keeps."""
+    up, alone = mixed
+    batch = _as_batch(up)
+    tune = eng.autotune_batch(batch)
+    _say(f"batch autotune: caps {list(tune.caps)} ms {[round(x, 2) for x in tune.ms_kpt]} kept {tune.job_cap}")
+    assert tune.job_cap in list(tune.caps) and all(x > 0 for x in tune.ms_kpt)
+    res, info = eng.run_batch(batch)
+    assert info.kpt_job_cap == tune.job_cap and info.kpt_steps > 0 and info.kpt_graph_launches > 0
     for (q, *_), got, want in zip(up, res, alone):
         _same(got, want, q["name"])
 
