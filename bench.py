@@ -523,7 +523,9 @@ def serve_main(args):
         done = max(r[0] + r[4] / 1e3 for r in res)
         point = {"rate_per_s": rate, "queries": count, "completed_per_s": round(count / (done - first), 3),
                  "p50_ms": round(float(np.percentile(lat, 50)), 3), "p99_ms": round(float(np.percentile(lat, 99)), 3),
-                 "rounds": int(info.rounds), "max_jobs": int(info.max_jobs)}
+                 "rounds": int(info.rounds), "max_jobs": int(info.max_jobs),
+                 "rr_pool_gb": round(info.rr_pool_bytes / 1e9, 3), "rr_peak_gb": round(info.rr_peak_bytes / 1e9, 3),
+                 "held_queries": int(info.held_queries), "held_ms": round(info.held_ms, 3)}
         sweep.append(point)
         last = (qs, res)
         log(f"rate {rate:g}/s: {point}")

@@ -411,13 +411,17 @@ typedef struct {
   uint64_t max_jobs;     /* largest round */
   uint64_t workers;      /* queries run at once */
   uint64_t budget_bytes; /* device memory of the batch */
-  uint64_t member_budget_bytes; /* each query's share of it */
+  uint64_t member_budget_bytes; /* each query's share of it outside NodeSelection */
   double ms_wall;
   double ms_kpt;         /* tim_run_batch: wall time of the device-driven KptEstimation of all queries */
   uint64_t kpt_job_cap;  /* tim_run_batch: most sets a query's job held per KptEstimation step */
   uint64_t kpt_steps;    /* tim_run_batch: device KptEstimation steps run (rounds, launches and jobs above
                             count the batched RefineKPT and NodeSelection requests) */
   uint64_t kpt_graph_launches; /* ... and launches of their captured HIP graph */
+  uint64_t rr_pool_bytes;  /* RR pool granted to NodeSelection by the bytes of each query's theta sets */
+  uint64_t rr_peak_bytes;  /* most of it granted at once */
+  uint64_t held_queries;   /* NodeSelections that waited for memory */
+  double held_ms;          /* their waiting time in all */
 } tim_batch_info;
 
 /* Runs `count` independent TIM / TIM+ queries (Sections 3.3 and 4.1) at

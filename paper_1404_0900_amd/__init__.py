@@ -100,7 +100,8 @@ class Query(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("rounds", U64), ("jobs", U64), ("launches", U64), ("max_jobs", U64), ("workers", U64),
                 ("budget_bytes", U64), ("member_budget_bytes", U64), ("ms_wall", DBL), ("ms_kpt", DBL),
-                ("kpt_job_cap", U64), ("kpt_steps", U64), ("kpt_graph_launches", U64)]
+                ("kpt_job_cap", U64), ("kpt_steps", U64), ("kpt_graph_launches", U64),
+                ("rr_pool_bytes", U64), ("rr_peak_bytes", U64), ("held_queries", U64), ("held_ms", DBL)]
 
 
 class BatchTune(ctypes.Structure):

@@ -120,6 +120,7 @@ struct tim_ctx {
   // batch member: its sampling launches go to the hub
   Hub* hub = nullptr;
   const tim_ctx* parent = nullptr;  // whose graphs it may use
+  uint64_t share = 0;               // its budget outside NodeSelection (the rest comes from the hub's RR pool)
   // batches run on this context: the hub and its member contexts, kept
   // (with their buffers) from one tim_run_batch call to the next
   Hub* batch = nullptr;
@@ -291,7 +292,56 @@ struct Hub {
   // statistics
   uint64_t rounds = 0, jobs = 0, launches = 0, max_jobs = 0;
   uint64_t kpt_steps = 0, kpt_graph_launches = 0;  // the device-driven KptEstimation of tim_run_batch
+  // RR pool: device memory granted to NodeSelection by the bytes its theta sets need
+  std::mutex mem_mu;
+  std::condition_variable mem_cv;
+  uint64_t rr_total = 0, rr_free = 0, rr_peak = 0;
+  uint64_t next_ticket = 0, serving_ticket = 0;  // grants are served in request order
+  uint64_t held = 0;                             // grants that had to wait for memory
+  double held_ms = 0.0;
 };
+
+// NodeSelection of a batch member (Algorithm 1 over theta sets) is admitted
+// by the device memory its collection needs: theta * E|R| * 4 bytes for the
+// node pool plus the per-set offsets and the inverted index (resident_bytes,
+// from the mean size of the last KptEstimation round).  The grant comes from
+// the hub's RR pool, in request order; a request that does not fit waits
+// until earlier grants are returned.  One larger than the whole pool gets
+// the whole pool and runs its collection in regenerated chunks (A10).  The
+// member's budget is its share plus the grant while NodeSelection runs.
+void release_transients(tim_ctx* c);
+
+uint64_t hub_admit(tim_ctx* c, uint64_t need) {
+  Hub* h = c->hub;
+  const uint64_t grant = std::min(need, h->rr_total);
+  const auto t0 = std::chrono::steady_clock::now();
+  std::unique_lock<std::mutex> lk(h->mem_mu);
+  const uint64_t ticket = h->next_ticket++;
+  bool waited = false;
+  while (!(h->serving_ticket == ticket && h->rr_free >= grant)) {
+    waited = true;
+    h->mem_cv.wait(lk);
+  }
+  h->serving_ticket += 1;
+  h->rr_free -= grant;
+  h->rr_peak = std::max(h->rr_peak, h->rr_total - h->rr_free);
+  if (waited) {
+    h->held += 1;
+    h->held_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+  }
+  c->budget = c->share + grant;
+  h->mem_cv.notify_all();  // the next ticket may fit too
+  return grant;
+}
+
+void hub_return(tim_ctx* c, uint64_t grant) {
+  Hub* h = c->hub;
+  release_transients(c);  // back within its share
+  c->budget = c->share;
+  std::lock_guard<std::mutex> lk(h->mem_mu);
+  h->rr_free += grant;
+  h->mem_cv.notify_all();
+}
 
 // Blocks a request waits in until its round has run.
 void hub_submit(Hub* h, Pending* p) {
@@ -1183,8 +1233,17 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
           ~KappaScope() { c->emit_kappa_k = 0; }
         } scope{c};
         c->emit_kappa_k = k;
-        TIM_TRY(emit_sets(c, g, model, seed, (uint32_t)i, 0, ci, expect, nullptr, &t));
-        stored = true;
+        const tim_status es = emit_sets(c, g, model, seed, (uint32_t)i, 0, ci, expect, nullptr, &t);
+        if (es == TIM_OK) {
+          stored = true;
+        } else if (es == TIM_EBUDGET) {
+          // the round's sets came out larger than estimated: sum its widths instead (RefineKPT
+          // generates R' again from its keys, with the same sets)
+          release_transients(c);
+          t = Totals();
+        } else {
+          return es;
+        }
       }
     }
     if (!stored)
@@ -1336,9 +1395,12 @@ tim_status run_impl(tim_ctx* c, const tim_graph* g, int model, int k, double eps
   if (st == TIM_OK) {
     r->lambda = lambda_eq4(g->n, k, eps, ell_used);
     const uint64_t theta = (uint64_t)std::ceil(r->lambda / lb);
+    const uint64_t expect = (uint64_t)(mean_nodes * 1.25 * (double)theta) + 4096;
     SelectTimes times;
-    st = node_select_impl(c, g, model, seed, k, theta, (uint64_t)(mean_nodes * 1.25 * (double)theta) + 4096, seeds,
-                          gains, &r->select, &times);
+    uint64_t grant = 0;
+    if (c->hub) grant = hub_admit(c, resident_bytes(c, g->n, model, theta, expect, k) + theta * 8);
+    st = node_select_impl(c, g, model, seed, k, theta, expect, seeds, gains, &r->select, &times);
+    if (c->hub) hub_return(c, grant);
     if (st == TIM_OK) {
       r->ms_select_sample = times.sample;
       r->ms_select_index = 0.0;
@@ -1642,8 +1704,32 @@ tim_status hub_prepare(Hub* h, tim_ctx* parent, int64_t maxn, int workers) {
     h->big_slots = slots;
     h->big_bytes = (uint64_t)slots * per + (uint64_t)slots * 4;
   }
-  h->member_budget = (limit - std::min(limit, h->big_bytes)) / (uint64_t)workers;
-  if (h->member_budget < (1u << 20)) return fail(TIM_EBUDGET, "budget too small for %d queries at once", workers);
+  // half of what is left after the slots is shared equally among the queries running at once (their
+  // KptEstimation and RefineKPT work space), the other half is the RR pool granted to NodeSelection
+  const uint64_t rest = limit - std::min(limit, h->big_bytes);
+  // a share holds at least the node-pool slices of one small stored-set launch (any wavefront of a
+  // batched launch may reserve one in any job), the greedy's per-node arrays for the largest graph
+  // and the lists of small launches
+  uint64_t slices = 0;
+  for (int model = 0; model < 2; ++model) {
+    const uint64_t cap = tim::tier0_set_cap(model, 8);
+    slices = std::max<uint64_t>(slices, h->emit_waves[model] * 5 * cap * 4);
+  }
+  const uint64_t min_share = 2 * slices + 17 * (uint64_t)maxn + (8u << 20);
+  h->member_budget = std::max<uint64_t>(rest / 2 / (uint64_t)workers, min_share);
+  if (h->member_budget * (uint64_t)workers >= rest)
+    return fail(TIM_EBUDGET, "budget too small for %d queries at once (%llu bytes each and an RR pool)", workers,
+                (unsigned long long)min_share);
+  h->rr_total = rest - h->member_budget * (uint64_t)workers;
+  if (const char* cap = getenv("TIM_RR_POOL_BYTES")) {  // a smaller RR pool than the budget allows
+    const uint64_t v = strtoull(cap, nullptr, 10);
+    if (v >= (1u << 20)) h->rr_total = std::min(h->rr_total, v);
+  }
+  h->rr_free = h->rr_total;
+  h->rr_peak = 0;
+  h->next_ticket = h->serving_ticket = 0;
+  h->held = 0;
+  h->held_ms = 0.0;
   while ((int)parent->members.size() < workers) {
     tim_ctx* m = nullptr;
     TIM_TRY(hub_member(h, parent, &m));
@@ -1652,6 +1738,7 @@ tim_status hub_prepare(Hub* h, tim_ctx* parent, int64_t maxn, int workers) {
   for (int w = 0; w < workers; ++w) {
     tim_ctx* m = parent->members[(size_t)w];
     m->budget = h->member_budget;
+    m->share = h->member_budget;
     m->resident_limit = parent->resident_limit;
     if (m->held > m->budget) release_transients(m);
   }
@@ -2577,6 +2664,10 @@ tim_status tim_run_batch(tim_ctx* c, tim_query* queries, int count, int max_conc
     info->kpt_job_cap = c->batch_job_cap;
     info->kpt_steps = hub.kpt_steps;
     info->kpt_graph_launches = hub.kpt_graph_launches;
+    info->rr_pool_bytes = hub.rr_total;
+    info->rr_peak_bytes = hub.rr_peak;
+    info->held_queries = hub.held;
+    info->held_ms = hub.held_ms;
   }
   for (int i = 0; i < count; ++i)
     if (queries[i].status != TIM_OK) return fail(queries[i].status, "query %d: %s", i, errs[(size_t)i].c_str());
@@ -2725,6 +2816,10 @@ tim_status tim_server_stop(tim_server* sv, tim_batch_info* info) {
     info->workers = (uint64_t)sv->slots;
     info->budget_bytes = h->limit;
     info->member_budget_bytes = h->member_budget;
+    info->rr_pool_bytes = h->rr_total;
+    info->rr_peak_bytes = h->rr_peak;
+    info->held_queries = h->held;
+    info->held_ms = h->held_ms;
   }
   sv->ctx->serving = false;
   for (Ticket* t : sv->tickets) delete t;

@@ -87,3 +87,49 @@ def test_server_rejects_bad_queries_and_other_calls(setup):
             e.run_batch([(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"])])
         t = srv.submit(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"])
         srv.wait(t)
+
+
+def test_served_queries_equal_the_oracle():
+    """Queries served over time on small resident graphs against the CPU oracle directly."""
+    import oracle
+
+    import paper_1404_0900_amd as tim
+    graphs = synth.serve_graphs(scale=0.02)  # 2K, 20K, 80K and 200K nodes, average degree 16
+    qs = synth.serve_queries(10, 300.0, 21, k_max=12, eps_choices=(0.5,))
+    with tim.Engine(0) as e:
+        dgs = [e.upload(g) for g in graphs]
+        with e.serve(slots=4) as srv:
+            tickets = [srv.submit(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"]) for q in qs]
+            results = [srv.wait(t) for t in tickets]
+            srv.stop()
+    for i, (q, (seeds, gains, rep, _)) in enumerate(zip(qs, results)):
+        g = graphs[q["graph"]]
+        _say(f"served vs oracle: query {i} n={g.n} model={q['model']} k={q['k']}")
+        want = oracle.tim_run(g, q["model"], q["k"], q["eps"], q["ell"], q["seed"])
+        r = tim.report_dict(rep, q["k"])
+        assert np.array_equal(seeds, want["seeds"]) and np.array_equal(gains, want["gains"]), i
+        for key in KEYS:
+            assert r[key] == want[key], (i, key)
+
+
+def test_admission_by_theta_bytes_holds_queries_and_keeps_results(setup, monkeypatch):
+    """An RR pool of 8 MB (TIM_RR_POOL_BYTES) under a 512 MB budget fits few collections at once:
+    NodeSelections wait for memory in request order (none is refused; one larger than the pool gets the
+    whole pool and regenerates its collection in chunks), the pool is never over-granted, and every
+    result stays that of the query alone."""
+    import paper_1404_0900_amd as tim
+    _, _, qs, alone = setup
+    graphs = synth.serve_graphs(scale=0.005)
+    monkeypatch.setenv("TIM_RR_POOL_BYTES", str(8 << 20))
+    with tim.Engine(0, budget_bytes=512 << 20) as e:
+        dgs = [e.upload(g) for g in graphs]
+        with e.serve(slots=8) as srv:
+            tickets = [srv.submit(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"]) for q in qs]
+            results = [srv.wait(t) for t in tickets]
+            info = srv.stop()
+    _say(f"admission: pool {info.rr_pool_bytes >> 20} MB, peak {info.rr_peak_bytes >> 20} MB, "
+         f"{info.held_queries} held for {info.held_ms:.1f} ms")
+    assert info.rr_pool_bytes == 8 << 20 and 0 < info.rr_peak_bytes <= info.rr_pool_bytes
+    assert info.held_queries > 0
+    for i, (got, want) in enumerate(zip(results, alone)):
+        _same(got, want, i)
