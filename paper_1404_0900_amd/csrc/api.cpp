@@ -336,7 +336,8 @@ uint64_t hub_admit(tim_ctx* c, uint64_t need) {
 
 void hub_return(tim_ctx* c, uint64_t grant) {
   Hub* h = c->hub;
-  release_transients(c);  // back within its share
+  // back within its share; buffers that fit in it stay for the next query (a free waits for the device)
+  if (c->held > c->share) release_transients(c);
   c->budget = c->share;
   std::lock_guard<std::mutex> lk(h->mem_mu);
   h->rr_free += grant;
