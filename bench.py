@@ -12,7 +12,11 @@ Prints one JSON line: RR sets generated per second over the timed steps
 generating them again, as Algorithm 3 prescribes, so they count once), edges
 examined per second, TIM+ seconds per k, the roofline of the dominant sampler
 kernel (algorithmic bytes over its event-timed duration), and the CPU oracle
-timed on the host on one TIM+ run of the same graph (k = 50).
+timed on the host on one TIM+ run of the same graph (k = 50), whose result the
+last timed k = 50 run must equal ("parity").  Outside the timed steps it also
+reports LT (1/indeg and random in-weights), the general triggering model, and
+("batched") the 64-query mixed workload below as one batch against the same
+queries one by one (--no-batch skips it).
 
 --workload batch64: 64 independent TIM+ queries, each on a Chung-Lu graph of
 its own (n log-uniform in [10^4, 2*10^6], average degree uniform in [4, 40];
@@ -109,6 +113,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain leg of the default line")
     ap.add_argument("--workload", choices=("timplus", "batch64", "serve", "sweep"), default="timplus")
     ap.add_argument("--mc-runs", type=int, default=10_000, help="forward Monte-Carlo runs per seed set (sweep)")
     ap.add_argument("--rates", type=str, default="1,5,20,50,200", help="arrival rates per second (serve)")
@@ -292,6 +297,14 @@ def main():
         line["parity"] = parity_with_oracle(tim, last[50], r, 50)
         log(f"parity of the last timed k=50 run with the oracle: {line['parity']}")
     eng.close()
+    if not args.no_batch:
+        # batched vs plain queries/s on the 64-query mixed workload (its own graphs; outside the timed steps)
+        b = batch_measure(2, 1)
+        line["batched"] = {"metric": "TIM+ queries/s, 64 mixed queries, batched vs one by one",
+                           "queries_per_s": b["queries_per_s"], "plain_queries_per_s": b["sequential"]["value"],
+                           "speedup": b["speedup_vs_sequential"], "identical_outputs": b["identical_outputs"],
+                           "device_kpt_ms": b["device_kpt"]["ms"], "job_cap": b["device_kpt"]["job_cap"],
+                           "workload": b["config"]["workload"], "steps": 2}
     print(json.dumps(line), flush=True)
 
 
@@ -387,6 +400,30 @@ def batch_kernel_name(model, mode):
 
 
 def batch_main(args):
+    res = batch_measure(args.steps, args.warmup)
+    line = {
+        "metric": "TIM+ queries/s, 64 mixed queries batched on 1 GPU (vs the same queries run one by one)",
+        "value": res["queries_per_s"],
+        "unit": "queries/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": res["ms_per_batch"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u32/u64 integer, f64 kappa",
+        "data": "synthetic (64 seeded directed Chung-Lu graphs, alpha=2.1)",
+        "config": res.pop("config"),
+    }
+    line.update(res)
+    print(json.dumps(line), flush=True)
+
+
+def batch_measure(steps, warmup):
+    """The 64-query batched workload: the queries one by one (tim_run) and as one batch (tim_run_batch),
+    `steps` times each after `warmup` untimed rounds; medians, identity of the outputs, and the batch's
+    device KptEstimation figures."""
     import statistics
 
     import numpy as np
@@ -414,17 +451,17 @@ def batch_main(args):
                 return False
         return True
 
-    for i in range(args.warmup):
+    for i in range(warmup):
         sequential()
         eng.run_batch(batch)
-        log(f"warmup {i + 1}/{args.warmup} done")
+        log(f"batch warmup {i + 1}/{warmup} done")
     # the granularity of the batch's device KptEstimation work queue, timed before the steps
     tune = eng.autotune_batch(batch)
     log(f"batch autotune: {[int(c) for c in tune.caps]} sets per query and step -> "
         f"{[round(x, 2) for x in tune.ms_kpt]} ms; kept {int(tune.job_cap)}")
     t_seq, t_bat, identical, info = [], [], True, None
     sets = 0
-    for i in range(args.steps):
+    for i in range(steps):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         seq = sequential()
@@ -434,7 +471,7 @@ def batch_main(args):
         t_bat.append(time.perf_counter() - t0)
         identical = identical and same(seq, bat)
         sets = sum(int(r.sets_total) for _, _, r in bat)
-        log(f"step {i + 1}/{args.steps}: sequential {t_seq[-1]:.3f} s, batched {t_bat[-1]:.3f} s "
+        log(f"batch step {i + 1}/{steps}: sequential {t_seq[-1]:.3f} s, batched {t_bat[-1]:.3f} s "
             f"(device KptEstimation {info.ms_kpt:.1f} ms in {info.kpt_steps} steps / {info.kpt_graph_launches} "
             f"graph launches; then {info.rounds} rounds, {info.launches} launches, up to {info.max_jobs} jobs), "
             f"identical={identical}")
@@ -448,19 +485,9 @@ def batch_main(args):
     roofline = dominant_roofline(prof, batch_kernel_name)
 
     slow = sorted(((r.ms_total, q["name"]) for (_, _, r), q in zip(seq, queries)), reverse=True)[:5]
-    line = {
-        "metric": "TIM+ queries/s, 64 mixed queries batched on 1 GPU (vs the same queries run one by one)",
-        "value": round(64 / tb, 3),
-        "unit": "queries/s",
-        "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": round(tb * 1e3, 3),
-        "higher_is_better": True,
-        "scaling": "weak",
-        "vs_baseline": None,
-        "dtype": "u32/u64 integer, f64 kappa",
-        "data": "synthetic (64 seeded directed Chung-Lu graphs, alpha=2.1)",
+    out = {
+        "queries_per_s": round(64 / tb, 3),
+        "ms_per_batch": round(tb * 1e3, 3),
         "config": {"workload": "batch64_chunglu_ic_trivalency_lt", "queries": 64, "n_range": [10_000, 2_000_000],
                    "avg_degree_range": [4, 40], "ic_p": list(synth.TRIVALENCY_P), "k_range": [1, 50],
                    "eps": [0.1, 0.2, 0.5], "ell": 1.0, "seeds": "1000+j",
@@ -479,7 +506,7 @@ def batch_main(args):
         "roofline": roofline,
     }
     eng.close()
-    print(json.dumps(line), flush=True)
+    return out
 
 
 def serve_main(args):

@@ -17,6 +17,9 @@ namespace tim {
 enum : uint32_t { kKindRoot = 0, kKindCoin = 1, kKindPick = 2, kKindTrigger = 3 };
 
 __device__ __forceinline__ uint4 philox10(uint4 c, uint32_t k0, uint32_t k1) {
+  k0 = __builtin_amdgcn_readfirstlane(k0);
+  k1 = __builtin_amdgcn_readfirstlane(k1);
+  asm volatile("" : "+s"(k0), "+s"(k1));
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     // one 32x32->64 product per multiplier: a single v_mad_u64_u32 each
