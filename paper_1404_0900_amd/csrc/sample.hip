@@ -483,8 +483,6 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   uint32_t* h = s_h[kHash ? seg : 0];
   const GraphView g = a.g;
   const Key key = make_key(a.seed);
-  const uint32_t* off32 = nullptr;  // unused: offsets are read as int64 and narrowed
-  (void)off32;
   const unsigned long long total = io.in_list ? list_len(a, io.in_len_ctr) : a.count;
   if (first_only && io.in_list) {
     const unsigned long long wave = (unsigned long long)blockIdx.x * (kSegThreads / kWave) + threadIdx.x / kWave;
@@ -510,43 +508,8 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   uint32_t wlane = 0;
 
   for (;;) {
-    // ---- A: idle segments take their next set
-    {
-      int32_t root = 0;
-      const bool want = !has && !exhausted;
-      if (take_set(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
-        st = make_set_stream(a.phase, a.first + rel);
-        if (kHash) {
-          uint4* h4 = reinterpret_cast<uint4*>(h);
-          for (int i = sl; i < H / 4; i += S) h4[i] = make_uint4(0u, 0u, 0u, 0u);
-          wave_sync();
-        }
-        if (is_leader) {
-          q[0] = root;
-          if (kHash) {
-            s_tail[seg] = 1u;
-            lds_insert<(kHash ? HLOG : 1)>(h, (uint32_t)root);
-          }
-        }
-        tail_r = 1;
-        if (!kHash) {  // the segment's lanes clear the words (the root is the same in all of them)
-          const uint32_t wd = sig2_word(root);
-          for (int i = sl; i < kSigWords; i += S) s_sig[seg][i] = (uint32_t)i == wd ? sig2_bit(root) : 0ull;
-        }
-        has = true;
-        hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
-        bad = false;
-        head = 0;
-        G = 0;
-        done_items = 0;
-        gsum = 0;
-        wlane = 0;
-      }
-    }
-    if (__ballot(has) == 0) break;
-    wave_sync();
-
-    // ---- B: segments whose batch is done finish the set or load the next batch
+    // ---- A: segments whose set is complete finish it (or defer it), so that
+    // they take their next set in this same iteration
     bool fin = false, defer_now = false;
     uint32_t fin_len = 0, fin_width = 0;
     if (has && (done_items >= G || hit || bad)) {
@@ -571,28 +534,6 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
               if (hit) acc.covered += 1;
             }
           }
-        }
-      } else {
-        const int nb = min(tail - head, S);
-        ea = 0;
-        d = 0;
-        ng = 0;
-        if (sl < nb) {
-          const int32_t v = q[head + sl];
-          ea = (uint32_t)g.off[v];
-          const uint32_t eb = (uint32_t)g.off[v + 1];
-          d = eb - ea;
-          ng = d ? ((eb - 1u) >> 2) - (ea >> 2) + 1u : 0u;
-        }
-        wlane += d;
-        head += nb;
-        incl = seg_incl_scan<S>(ng, sl);
-        G = seg_last<S>(incl, ng);
-        done_items = 0;
-        gsum += G;
-        if (gsum > (uint32_t)GMAX) {  // too wide for this tier: hand it on
-          bad = true;
-          done_items = G;
         }
       }
     }
@@ -637,8 +578,72 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
         }
       }
     }
+    wave_sync();
 
-    // ---- C: segments with work process R*S groups of their batch (R per lane)
+    // ---- B: idle segments take their next set
+    {
+      int32_t root = 0;
+      const bool want = !has && !exhausted;
+      if (take_set(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
+        st = make_set_stream(a.phase, a.first + rel);
+        if (kHash) {
+          uint4* h4 = reinterpret_cast<uint4*>(h);
+          for (int i = sl; i < H / 4; i += S) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+          wave_sync();
+        }
+        if (is_leader) {
+          q[0] = root;
+          if (kHash) {
+            s_tail[seg] = 1u;
+            lds_insert<(kHash ? HLOG : 1)>(h, (uint32_t)root);
+          }
+        }
+        tail_r = 1;
+        if (!kHash) {  // the segment's lanes clear the words (the root is the same in all of them)
+          const uint32_t wd = sig2_word(root);
+          for (int i = sl; i < kSigWords; i += S) s_sig[seg][i] = (uint32_t)i == wd ? sig2_bit(root) : 0ull;
+        }
+        has = true;
+        hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
+        bad = false;
+        head = 0;
+        G = 0;
+        done_items = 0;
+        gsum = 0;
+        wlane = 0;
+      }
+    }
+    if (__ballot(has) == 0) break;
+    wave_sync();
+
+    // ---- C: segments whose batch is done load the next batch of queued nodes
+    // (a set still held here has queued nodes left: it was not finished above)
+    if (has && done_items >= G && !hit && !bad) {
+      const int tail = kHash ? (int)s_tail[seg] : tail_r;
+      const int nb = min(tail - head, S);
+      ea = 0;
+      d = 0;
+      ng = 0;
+      if (sl < nb) {
+        const int32_t v = q[head + sl];
+        ea = (uint32_t)g.off[v];
+        const uint32_t eb = (uint32_t)g.off[v + 1];
+        d = eb - ea;
+        ng = d ? ((eb - 1u) >> 2) - (ea >> 2) + 1u : 0u;
+      }
+      wlane += d;
+      head += nb;
+      incl = seg_incl_scan<S>(ng, sl);
+      G = seg_last<S>(incl, ng);
+      done_items = 0;
+      gsum += G;
+      if (gsum > (uint32_t)GMAX) {  // too wide for this tier: hand it on
+        bad = true;
+        done_items = G;
+      }
+    }
+
+    // ---- D: segments with work process R*S groups of their batch (R per lane)
     bool lhit = false, lbad = false;
     if (has && done_items < G) {
       int32_t sv[4 * R];
