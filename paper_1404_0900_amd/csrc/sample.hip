@@ -45,6 +45,7 @@ constexpr int kLtWaves = 2;        // wavefronts per block, LT lane-level pass
 constexpr int kChain = 64;         // LT chain length held in LDS
 constexpr int kBigThreads = 512;   // IC last-tier block size
 constexpr int kSegGroups = 1;      // 4-edge groups a lane decides per step (IC tiers 0 and 1)
+constexpr int kSegPasses = 2;      // batches of queued nodes a segment may take per iteration (IC tiers 0 and 1)
 constexpr uint64_t kKappaBlocks = 1024;  // largest grid of the kappa pass (four per CU)
 
 typedef unsigned __int128 u128;
@@ -616,154 +617,164 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
     if (__ballot(has) == 0) break;
     wave_sync();
 
-    // ---- C: segments whose batch is done load the next batch of queued nodes
-    // (a set still held here has queued nodes left: it was not finished above)
-    if (has && done_items >= G && !hit && !bad) {
-      const int tail = kHash ? (int)s_tail[seg] : tail_r;
-      const int nb = min(tail - head, S);
-      ea = 0;
-      d = 0;
-      ng = 0;
-      if (sl < nb) {
-        const int32_t v = q[head + sl];
-        ea = (uint32_t)g.off[v];
-        const uint32_t eb = (uint32_t)g.off[v + 1];
-        d = eb - ea;
-        ng = d ? ((eb - 1u) >> 2) - (ea >> 2) + 1u : 0u;
+    // C and D run up to kSegPasses times per iteration, so that the sets'
+    // finishing and taking above are paid once per two batches; a second pass
+    // runs only while some segment still has groups or queued nodes.
+    for (int pass = 0; pass < kSegPasses; ++pass) {
+      if (pass > 0) {
+        const int tl = kHash ? (int)s_tail[seg] : tail_r;
+        if (__ballot(has && !hit && !bad && (done_items < G || head < tl)) == 0ull) break;
       }
-      wlane += d;
-      head += nb;
-      incl = seg_incl_scan<S>(ng, sl);
-      G = seg_last<S>(incl, ng);
-      done_items = 0;
-      gsum += G;
-      if (gsum > (uint32_t)GMAX) {  // too wide for this tier: hand it on
-        bad = true;
-        done_items = G;
-      }
-    }
 
-    // ---- D: segments with work process R*S groups of their batch (R per lane)
-    bool lhit = false, lbad = false;
-    if (has && done_items < G) {
-      int32_t sv[4 * R];
-      bool live[4 * R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        const uint32_t item = done_items + (uint32_t)(r * S + sl);
-        int owner = 0;
-#pragma unroll
-        for (int step = S / 2; step > 0; step >>= 1) {
-          const uint32_t c = __shfl(incl, owner + step - 1, S);
-          if (c <= item) owner += step;
+      // ---- C: segments whose batch is done load the next batch of queued nodes
+      // (a set still held here that is not complete has queued nodes left)
+      if (has && done_items >= G && !hit && !bad) {
+        const int tail = kHash ? (int)s_tail[seg] : tail_r;
+        const int nb = min(tail - head, S);
+        ea = 0;
+        d = 0;
+        ng = 0;
+        if (sl < nb) {
+          const int32_t v = q[head + sl];
+          ea = (uint32_t)g.off[v];
+          const uint32_t eb = (uint32_t)g.off[v + 1];
+          d = eb - ea;
+          ng = d ? ((eb - 1u) >> 2) - (ea >> 2) + 1u : 0u;
         }
-        owner = min(owner, S - 1);
-        const uint32_t oa = __shfl(ea, owner, S);
-        const uint32_t od = __shfl(d, owner, S);
-        const uint32_t oex = __shfl(incl - ng, owner, S);
-#pragma unroll
-        for (int w = 0; w < 4; ++w) {
-          sv[4 * r + w] = 0;
-          live[4 * r + w] = false;
+        wlane += d;
+        head += nb;
+        incl = seg_incl_scan<S>(ng, sl);
+        G = seg_last<S>(incl, ng);
+        done_items = 0;
+        gsum += G;
+        if (gsum > (uint32_t)GMAX) {  // too wide for this tier: hand it on
+          bad = true;
+          done_items = G;
         }
-        if (item < G) {
-          const uint32_t grp = (oa >> 2) + (item - oex);
-          const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
-          uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
-          if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
-          const uint4 x = draw(key, st, kKindCoin, (uint64_t)grp);
-          sv[4 * r + 0] = s4.x;
-          sv[4 * r + 1] = s4.y;
-          sv[4 * r + 2] = s4.z;
-          sv[4 * r + 3] = s4.w;
-          const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
-          const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
-          const uint32_t e0 = grp << 2;
+      }
+
+      // ---- D: segments with work process R*S groups of their batch (R per lane)
+      bool lhit = false, lbad = false;
+      if (has && done_items < G) {
+        int32_t sv[4 * R];
+        bool live[4 * R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          const uint32_t item = done_items + (uint32_t)(r * S + sl);
+          int owner = 0;
+#pragma unroll
+          for (int step = S / 2; step > 0; step >>= 1) {
+            const uint32_t c = __shfl(incl, owner + step - 1, S);
+            if (c <= item) owner += step;
+          }
+          owner = min(owner, S - 1);
+          const uint32_t oa = __shfl(ea, owner, S);
+          const uint32_t od = __shfl(d, owner, S);
+          const uint32_t oex = __shfl(incl - ng, owner, S);
 #pragma unroll
           for (int w = 0; w < 4; ++w) {
-            const uint32_t e = e0 + (uint32_t)w;
-            live[4 * r + w] = e - oa < od && edge_live<WC>(xv[w], tv[w], od);
+            sv[4 * r + w] = 0;
+            live[4 * r + w] = false;
+          }
+          if (item < G) {
+            const uint32_t grp = (oa >> 2) + (item - oex);
+            const int4 s4 = reinterpret_cast<const int4*>(g.src)[grp];
+            uint4 t4 = make_uint4(0u, 0u, 0u, 0u);
+            if (!WC) t4 = reinterpret_cast<const uint4*>(g.thr)[grp];
+            const uint4 x = draw(key, st, kKindCoin, (uint64_t)grp);
+            sv[4 * r + 0] = s4.x;
+            sv[4 * r + 1] = s4.y;
+            sv[4 * r + 2] = s4.z;
+            sv[4 * r + 3] = s4.w;
+            const uint32_t xv[4] = {x.x, x.y, x.z, x.w};
+            const uint32_t tv[4] = {t4.x, t4.y, t4.z, t4.w};
+            const uint32_t e0 = grp << 2;
+#pragma unroll
+            for (int w = 0; w < 4; ++w) {
+              const uint32_t e = e0 + (uint32_t)w;
+              live[4 * r + w] = e - oa < od && edge_live<WC>(xv[w], tv[w], od);
+            }
           }
         }
-      }
-      bool any_live = false;
+        bool any_live = false;
 #pragma unroll
-      for (int w = 0; w < 4 * R; ++w) any_live |= live[w];
-      if (kHash) {
+        for (int w = 0; w < 4 * R; ++w) any_live |= live[w];
+        if (kHash) {
 #pragma unroll
-        for (int w = 0; w < 4 * R; ++w) {
-          if (!live[w]) continue;
-          const int32_t u = sv[w];
-          const int r = lds_insert<(kHash ? HLOG : 1)>(h, (uint32_t)u);
-          if (r < 0) {
+          for (int w = 0; w < 4 * R; ++w) {
+            if (!live[w]) continue;
+            const int32_t u = sv[w];
+            const int r = lds_insert<(kHash ? HLOG : 1)>(h, (uint32_t)u);
+            if (r < 0) {
+              lbad = true;
+            } else if (r == 1) {
+              const uint32_t pos = atomicAdd(&s_tail[seg], 1u);
+              if (pos < (uint32_t)Q) q[pos] = u;
+              else lbad = true;
+              if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+            }
+          }
+        } else if (seg_bits<S>(__ballot(any_live), sw) != 0ull) {
+          // Every live source sets its signature bit in the set's LDS signature
+          // with an atomic OR.  One that finds the bit clear is new (every queued
+          // node's bit is set, and of several sources sharing a bit in this step
+          // only the first sees it clear): those are appended at once.  The rest
+          // are looked up in the queue one at a time, after the appends.
+          bool fast[4 * R];
+          uint32_t nfast = 0;
+#pragma unroll
+          for (int w = 0; w < 4 * R; ++w) {
+            fast[w] = false;
+            if (live[w]) {
+              const unsigned long long b = sig2_bit(sv[w]);
+              fast[w] = (atomicOr(&s_sig[seg][sig2_word(sv[w])], b) & b) == 0ull;
+            }
+            nfast += fast[w] ? 1u : 0u;
+          }
+          const uint32_t fincl = seg_incl_scan<S>(nfast, sl);
+          const uint32_t ftot = seg_last<S>(fincl, nfast);
+          if (tail_r + (int)ftot > Q) {
             lbad = true;
-          } else if (r == 1) {
-            const uint32_t pos = atomicAdd(&s_tail[seg], 1u);
-            if (pos < (uint32_t)Q) q[pos] = u;
-            else lbad = true;
-            if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
-          }
-        }
-      } else if (seg_bits<S>(__ballot(any_live), sw) != 0ull) {
-        // Every live source sets its signature bit in the set's LDS signature
-        // with an atomic OR.  One that finds the bit clear is new (every queued
-        // node's bit is set, and of several sources sharing a bit in this step
-        // only the first sees it clear): those are appended at once.  The rest
-        // are looked up in the queue one at a time, after the appends.
-        bool fast[4 * R];
-        uint32_t nfast = 0;
+          } else {
+            int pos = tail_r + (int)(fincl - nfast);
 #pragma unroll
-        for (int w = 0; w < 4 * R; ++w) {
-          fast[w] = false;
-          if (live[w]) {
-            const unsigned long long b = sig2_bit(sv[w]);
-            fast[w] = (atomicOr(&s_sig[seg][sig2_word(sv[w])], b) & b) == 0ull;
-          }
-          nfast += fast[w] ? 1u : 0u;
-        }
-        const uint32_t fincl = seg_incl_scan<S>(nfast, sl);
-        const uint32_t ftot = seg_last<S>(fincl, nfast);
-        if (tail_r + (int)ftot > Q) {
-          lbad = true;
-        } else {
-          int pos = tail_r + (int)(fincl - nfast);
+            for (int w = 0; w < 4 * R; ++w) {
+              if (!fast[w]) continue;
+              q[pos++] = sv[w];
+              if (MODE == kModeCover && in_seed(a.seed_bits, sv[w])) lhit = true;
+            }
+            tail_r += (int)ftot;
+            wave_sync();
 #pragma unroll
-          for (int w = 0; w < 4 * R; ++w) {
-            if (!fast[w]) continue;
-            q[pos++] = sv[w];
-            if (MODE == kModeCover && in_seed(a.seed_bits, sv[w])) lhit = true;
-          }
-          tail_r += (int)ftot;
-          wave_sync();
-#pragma unroll
-          for (int w = 0; w < 4 * R; ++w) {
-            uint64_t m = seg_bits<S>(__ballot(live[w] && !fast[w]), sw);
-            while (m) {
-              const int src_lane = __ffsll((unsigned long long)m) - 1;
-              m &= m - 1ull;
-              const int32_t u = __shfl(sv[w], src_lane, S);
-              bool found = false;
-              for (int i = sl; i < tail_r; i += S) found |= q[i] == u;
-              if (seg_bits<S>(__ballot(found), sw) == 0ull) {
-                if (tail_r < Q) {
-                  if (is_leader) q[tail_r] = u;
-                  ++tail_r;
-                  wave_sync();
-                  if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
-                } else {
-                  lbad = true;
+            for (int w = 0; w < 4 * R; ++w) {
+              uint64_t m = seg_bits<S>(__ballot(live[w] && !fast[w]), sw);
+              while (m) {
+                const int src_lane = __ffsll((unsigned long long)m) - 1;
+                m &= m - 1ull;
+                const int32_t u = __shfl(sv[w], src_lane, S);
+                bool found = false;
+                for (int i = sl; i < tail_r; i += S) found |= q[i] == u;
+                if (seg_bits<S>(__ballot(found), sw) == 0ull) {
+                  if (tail_r < Q) {
+                    if (is_leader) q[tail_r] = u;
+                    ++tail_r;
+                    wave_sync();
+                    if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+                  } else {
+                    lbad = true;
+                  }
                 }
               }
             }
           }
         }
+        done_items += (uint32_t)(R * S);
       }
-      done_items += (uint32_t)(R * S);
+      wave_sync();
+      const uint64_t hm = __ballot(lhit), bm = __ballot(lbad);
+      hit = hit || seg_bits<S>(hm, sw) != 0ull;
+      bad = bad || seg_bits<S>(bm, sw) != 0ull;
     }
-    wave_sync();
-    const uint64_t hm = __ballot(lhit), bm = __ballot(lbad);
-    hit = hit || seg_bits<S>(hm, sw) != 0ull;
-    bad = bad || seg_bits<S>(bm, sw) != 0ull;
   }
   flush_acc(a, blk, acc, io.acc, lane);
 }
