@@ -210,14 +210,14 @@ struct Sig256 {
     w3 |= wd == 3u ? b : 0ull;
   }
 };
-// A set signature of kSigWords 64-bit words: word index and bit of node u.
-// The top bits of the hash pick the word, the 6 bits below them the bit.
-constexpr int kSigWordBits = 4;
+// A set signature of kSigWords 32-bit words (1024 bits): word index and bit
+// of node u.  The top bits of a multiplicative hash pick the word, the 5 bits
+// below them the bit.
+constexpr int kSigWordBits = 5;
 constexpr int kSigWords = 1 << kSigWordBits;
-__device__ __forceinline__ uint32_t sig2_word(int32_t u) { return ((uint32_t)u * 0x9E3779B1u) >> (32 - kSigWordBits); }
-__device__ __forceinline__ uint64_t sig2_bit(int32_t u) {
-  return 1ull << ((((uint32_t)u * 0x9E3779B1u) >> (26 - kSigWordBits)) & 63u);
-}
+__device__ __forceinline__ uint32_t sig_hash(int32_t u) { return (uint32_t)u * 0x9E3779B1u; }
+__device__ __forceinline__ uint32_t sig_word(uint32_t h) { return h >> (32 - kSigWordBits); }
+__device__ __forceinline__ uint32_t sig_bit(uint32_t h) { return 1u << ((h >> (27 - kSigWordBits)) & 31u); }
 
 struct Acc {
   u128 kappa = 0;
@@ -471,7 +471,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   __shared__ int32_t s_q[NSEG][Q];
   __shared__ uint32_t s_h[kHash ? NSEG : 1][H];
   __shared__ uint32_t s_tail[kHash ? NSEG : 1];
-  __shared__ __align__(16) unsigned long long s_sig[kHash ? 1 : NSEG][kSigWords];  // signature of each set's queued nodes
+  __shared__ __align__(16) uint32_t s_sig[kHash ? 1 : NSEG][kSigWords];  // signature of each set's queued nodes
   const int lane = threadIdx.x % kWave;
   const int sl = threadIdx.x % S;       // lane within the segment
   const int seg = threadIdx.x / S;      // segment within the block
@@ -601,8 +601,13 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
         }
         tail_r = 1;
         if (!kHash) {  // the segment's lanes clear the words (the root is the same in all of them)
-          const uint32_t wd = sig2_word(root);
-          for (int i = sl; i < kSigWords; i += S) s_sig[seg][i] = (uint32_t)i == wd ? sig2_bit(root) : 0ull;
+          const uint32_t hr = sig_hash(root), wd = sig_word(hr), bt = sig_bit(hr);
+          uint4* s4 = reinterpret_cast<uint4*>(s_sig[seg]);
+          for (int i = sl; i < kSigWords / 4; i += S) {
+            const uint32_t w0 = 4u * (uint32_t)i;
+            s4[i] = make_uint4(wd == w0 ? bt : 0u, wd == w0 + 1u ? bt : 0u, wd == w0 + 2u ? bt : 0u,
+                               wd == w0 + 3u ? bt : 0u);
+          }
         }
         has = true;
         hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
@@ -726,8 +731,8 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
           for (int w = 0; w < 4 * R; ++w) {
             fast[w] = false;
             if (live[w]) {
-              const unsigned long long b = sig2_bit(sv[w]);
-              fast[w] = (atomicOr(&s_sig[seg][sig2_word(sv[w])], b) & b) == 0ull;
+              const uint32_t hv = sig_hash(sv[w]), b = sig_bit(hv);
+              fast[w] = (atomicOr(&s_sig[seg][sig_word(hv)], b) & b) == 0u;
             }
             nfast += fast[w] ? 1u : 0u;
           }
