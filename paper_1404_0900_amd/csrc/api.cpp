@@ -138,6 +138,7 @@ struct tim_graph {
   tim_ctx* ctx = nullptr;
   int64_t n = 0, m = 0;
   int64_t* off = nullptr;
+  uint32_t* off32 = nullptr;  // the offsets in 32 bits (m < 2^32): one 8-byte read gives a node's in-list range
   int32_t* src = nullptr;
   uint32_t* thr = nullptr;
   uint32_t* lthr = nullptr;  // LT cumulative in-weight thresholds, or nullptr (1/indeg)
@@ -441,6 +442,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
   SampleArgs a;
   memset(&a, 0, sizeof(a));
   a.g.off = g->off;
+  a.g.off32 = g->off32;
   a.g.src = g->src;
   a.g.thr = g->thr;
   a.g.lthr = g->lthr;
@@ -1059,6 +1061,7 @@ tim_status sample_rounds(tim_ctx* c, const tim_graph* g, int model, uint64_t see
     SampleArgs& a = jobs[(size_t)r];
     memset(&a, 0, sizeof(a));
     a.g.off = g->off;
+    a.g.off32 = g->off32;
     a.g.src = g->src;
     a.g.thr = g->thr;
     a.g.lthr = g->lthr;
@@ -1809,6 +1812,7 @@ tim_status batch_kpt_group(tim_ctx* c, Hub* h, tim_query* qs, const std::vector<
     tim::KptQuery& d = hq[(size_t)j];
     memset(&d, 0, sizeof(d));
     d.g.off = g->off;
+    d.g.off32 = g->off32;
     d.g.src = g->src;
     d.g.thr = g->thr;
     d.g.lthr = g->lthr;
@@ -2126,10 +2130,14 @@ tim_status tim_graph_upload(tim_ctx* c, int64_t n, int64_t m, const int64_t* in_
   g->n = n;
   g->m = m;
   const size_t mpad = (size_t)((m + 3) / 4 * 4 + 4);
-  bool ok = hipMalloc(&g->off, (size_t)(n + 1) * 8) == hipSuccess && hipMalloc(&g->src, mpad * 4) == hipSuccess &&
+  std::vector<uint32_t> off32((size_t)n + 1);
+  for (int64_t v = 0; v <= n; ++v) off32[(size_t)v] = (uint32_t)in_off[v];  // m < 2^32
+  bool ok = hipMalloc(&g->off, (size_t)(n + 1) * 8) == hipSuccess &&
+            hipMalloc(&g->off32, (size_t)(n + 1) * 4) == hipSuccess && hipMalloc(&g->src, mpad * 4) == hipSuccess &&
             (!ic_thr || hipMalloc(&g->thr, mpad * 4) == hipSuccess);
   if (ok) {
     ok = hipMemcpyAsync(g->off, in_off, (size_t)(n + 1) * 8, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
+         hipMemcpyAsync(g->off32, off32.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, c->stream) == hipSuccess &&
          hipMemsetAsync(g->src, 0, mpad * 4, c->stream) == hipSuccess &&
          hipMemcpyAsync(g->src, in_src, (size_t)m * 4, hipMemcpyHostToDevice, c->stream) == hipSuccess;
     if (ok && ic_thr)
@@ -2148,6 +2156,7 @@ tim_status tim_graph_upload(tim_ctx* c, int64_t n, int64_t m, const int64_t* in_
 void tim_graph_free(tim_graph* g) {
   if (!g) return;
   if (g->off) (void)hipFree(g->off);
+  if (g->off32) (void)hipFree(g->off32);
   if (g->src) (void)hipFree(g->src);
   if (g->thr) (void)hipFree(g->thr);
   if (g->lthr) (void)hipFree(g->lthr);
@@ -2562,6 +2571,7 @@ tim_status tim_spread_mc(tim_ctx* c, const tim_graph* g, int model, uint64_t see
   tim::SpreadArgs a;
   memset(&a, 0, sizeof(a));
   a.g.off = g->off;
+  a.g.off32 = g->off32;
   a.g.src = g->src;
   a.g.thr = model == TIM_MODEL_IC ? g->thr : nullptr;
   a.g.lthr = model == TIM_MODEL_LT ? g->lthr : nullptr;

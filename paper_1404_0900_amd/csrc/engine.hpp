@@ -54,6 +54,7 @@ constexpr uint32_t kPoolChunk = 2048;
 
 struct GraphView {
   const int64_t* off;   // n+1
+  const uint32_t* off32;  // the same offsets in 32 bits (m < 2^32), for the IC first tiers
   const int32_t* src;   // m rounded up to a multiple of 4, plus 4, zero padded
   const uint32_t* thr;  // same padding, or nullptr for the weighted cascade
   const uint32_t* lthr; // LT cumulative in-weight thresholds (m), or nullptr for 1/indeg
