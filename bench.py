@@ -55,6 +55,9 @@ import hashlib
 KS = (1, 10, 50)
 EPS, ELL, SEED = 0.2, 1.0, 2
 HBM_PEAK_GBS = 8000.0
+# Algorithmic bytes per RR entry of the inverted index and greedy: the entry read by the counts pass, read and
+# written by the scatter, and read by the cover pass that decrements the counts of a chosen node's sets (4 B each).
+GREEDY_BYTES_PER_ENTRY = 20
 SEG_GROUPS = 1  # 4-edge groups per lane and step of the IC segment kernels (kSegGroups)
 MODES = ("widths", "store", "cover")
 # HBM bytes per launch of the first-tier IC kernels that can be the dominant
@@ -64,13 +67,9 @@ MODES = ("widths", "store", "cover")
 # picks on this graph.  Valid only for the kernel sources they were taken on.
 TRAFFIC = {
     "ic_seg_kernel<1, true, 8, 128, 0, 512, 1> (store)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3318178006, "write_bytes": 556814720},
-    "ic_seg_kernel<1, true, 16, 128, 8, 512, 1> (store)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3273551591, "write_bytes": 437677184},
+        "sources_sha256_16": "8ecdd29b5ccc5a0b", "taken": "2026-12-03", "fetch_bytes": 2906779407, "write_bytes": 573834816},
     "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3070146813, "write_bytes": 90828587},
-    "ic_seg_kernel<0, true, 16, 128, 8, 512, 1> (widths)": {
-        "sources_sha256_16": "625d0537e6a9cbd0", "taken": "2026-12-03", "fetch_bytes": 3060404808, "write_bytes": 69464651},
+        "sources_sha256_16": "8ecdd29b5ccc5a0b", "taken": "2026-12-03", "fetch_bytes": 2638582694, "write_bytes": 100931445},
 }
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/pick.hpp", "paper_1404_0900_amd/csrc/engine.hpp")
@@ -171,12 +170,16 @@ def main():
     torch.cuda.synchronize()
     eng.profile(True)
     sets = width = 0
+    greedy_entries = greedy_argmax_bytes = 0  # RR entries the greedy runs index, and their argmax passes' bytes
     per_k = {k: 0.0 for k in KS}
     t0 = time.perf_counter()
     for i in range(args.steps):
         for k, dt, rep in step():
             sets += rep.sets_total
             width += rep.width_total
+            # two greedy runs per query: RefineKPT's on R' (the last KptEstimation round) and NodeSelection's
+            greedy_entries += int(rep.kpt.round_nodes[rep.kpt.i_last]) + int(rep.select.nodes)
+            greedy_argmax_bytes += 2 * k * 4 * g.n
             per_k[k] += dt
             phases[str(k)] = {"kpt_ms": round(rep.ms_kpt, 3), "refine_ms": round(rep.ms_refine, 3),
                               "select_sample_ms": round(rep.ms_select_sample, 3),
@@ -209,6 +212,16 @@ def main():
     sampler_ms += sum(prof.ic_wide[b].kernel_ms + prof.ic_wide[b].large_ms for b in (0, 1, 2))
     sampler_ms += sum(prof.grouped[a].kernel_ms + prof.grouped[a].large_ms for a in (0, 1))
     by_phase = sampler_by_mode(prof, 0)
+    roofline_widths = kernel_roofline(prof, 0, 0, name_of, traffic_of)
+    ig_ms = prof.index_ms + prof.greedy_ms
+    ig_bytes = GREEDY_BYTES_PER_ENTRY * greedy_entries + greedy_argmax_bytes
+    ig_gbs = ig_bytes / (ig_ms * 1e-3) / 1e9 if ig_ms > 0 else 0.0
+    roofline_index_greedy = {
+        "bound": "hbm", "achieved": round(ig_gbs, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+        "frac": round(ig_gbs / HBM_PEAK_GBS, 5), "traffic": None,
+        "kernels": "inverted index (counts, scan, scatter) and greedy (argmax, cover) of every query",
+        "entries_per_step": greedy_entries // args.steps, "bytes_per_entry": GREEDY_BYTES_PER_ENTRY,
+        "argmax_bytes_per_step": greedy_argmax_bytes // args.steps, "gpu_ms_per_step": round(ig_ms / args.steps, 3)}
 
     line = {
         "metric": "RR sets/s (IC, 1 GPU, TIM+ on 1M-node Chung-Lu, k in {1,10,50})",
@@ -233,6 +246,8 @@ def main():
         "index_greedy_gpu_ms_per_step": round((prof.index_ms + prof.greedy_ms) / args.steps, 3),
         "sampler_by_phase": by_phase,
         "roofline": roofline,
+        "roofline_widths": roofline_widths,
+        "roofline_index_greedy": roofline_index_greedy,
         "autotune": None if args.no_autotune else {
             "seg_lanes": int(tune.seg_lanes), "slice_cap": int(tune.slice_cap),
             "ms_width_4_8_16_32_64": [round(x, 3) for x in tune.ms_width],
@@ -380,7 +395,14 @@ def dominant_roofline(prof, name_of, traffic_of=lambda model, mode: None):
             kp = prof.sampler[model][mode]
             if kp.launches and (best is None or kp.kernel_ms > best[2].kernel_ms):
                 best = (model, mode, kp)
-    model, mode, kp = best
+    return kernel_roofline(prof, best[0], best[1], name_of, traffic_of)
+
+
+def kernel_roofline(prof, model, mode, name_of, traffic_of=lambda model, mode: None):
+    """Roofline object of one first-tier sampler kernel (algorithmic bytes over its event time), or None."""
+    kp = prof.sampler[model][mode]
+    if not kp.launches:
+        return None
     achieved = kp.bytes / (kp.kernel_ms * 1e-3) / 1e9
     return {
         "bound": "hbm", "achieved": round(achieved, 2), "peak": HBM_PEAK_GBS, "unit": "GB/s",
