@@ -116,6 +116,7 @@ struct tim_ctx {
   int big_slots = 0;
   int64_t big_n = -1;
   DevBuf rr_off, rr_nodes, sizes, cnt, fill, inv_off, inv_sets, covered, selected, best, scan_tmp, seed_bits;
+  DevBuf bucket;  // the greedy's counting sort by node range (tim::bucket_workspace_bytes)
   hipEvent_t ev[2] = {nullptr, nullptr};
   // batch member: its sampling launches go to the hub
   Hub* hub = nullptr;
@@ -622,6 +623,15 @@ tim_status sample_store(tim_ctx* c, const tim_graph* g, int model, uint64_t seed
 // Greedy maximum coverage over a collection in device memory, in CSR layout
 // (set_off) or in the node-pool layout of an emit launch (set_start/set_len).
 // k = 1 needs only the coverage counts; larger k builds the inverted index.
+// TIM_GREEDY_BUCKETS=0 keeps the greedy's counts and index on per-entry device atomics.
+bool greedy_buckets() {
+  static const bool on = [] {
+    const char* e = getenv("TIM_GREEDY_BUCKETS");
+    return !(e && e[0] == '0');
+  }();
+  return on;
+}
+
 tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off, const uint64_t* set_start,
                   const uint32_t* set_len, const int32_t* nodes, uint64_t total, int k, int32_t* seeds,
                   uint64_t* gains) {
@@ -656,6 +666,12 @@ tim_status greedy(tim_ctx* c, int64_t n, uint64_t nsets, const int64_t* set_off,
   a.covered = c->covered.as<uint8_t>();
   a.selected = c->selected.as<uint8_t>();
   a.best = c->best.as<unsigned long long>();
+  // the counting sort by node range where its workspace fits the budget, else per-entry device atomics
+  // (under a budget only while it takes at most half of it, so that later allocations of the run keep room)
+  const size_t wb = greedy_buckets() ? tim::bucket_workspace_bytes(n, total, index) : 0;
+  if (wb && nsets && (!c->budget || c->held - c->bucket.bytes + wb <= c->budget / 2) &&
+      ensure(c, c->bucket, wb, "greedy workspace") == TIM_OK)
+    a.bkt = c->bucket.p;
   if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
   if (index) tim::launch_index(a, c->stream);
   else tim::launch_counts(a, c->stream);
@@ -703,12 +719,12 @@ struct CollectionStats {
 };
 
 DevBuf* const* transient_bufs(tim_ctx* c, size_t* n) {
-  static thread_local DevBuf* bufs[17];
+  static thread_local DevBuf* bufs[18];
   DevBuf* list[] = {&c->list1,  &c->list2,   &c->wbuf,    &c->pool,     &c->set_start, &c->set_len,
                     &c->rr_off, &c->rr_nodes, &c->sizes,  &c->cnt,      &c->fill,      &c->inv_off,
-                    &c->inv_sets, &c->covered, &c->selected, &c->best, &c->scan_tmp};
-  for (size_t i = 0; i < 17; ++i) bufs[i] = list[i];
-  *n = 17;
+                    &c->inv_sets, &c->covered, &c->selected, &c->best, &c->scan_tmp, &c->bucket};
+  for (size_t i = 0; i < 18; ++i) bufs[i] = list[i];
+  *n = 18;
   return bufs;
 }
 
@@ -2072,7 +2088,7 @@ void tim_ctx_destroy(tim_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   DevBuf* bufs[] = {&c->list1, &c->list2, &c->wbuf, &c->pool, &c->set_start, &c->set_len, &c->big_stamp, &c->big_queue, &c->big_epoch,
                     &c->rr_off, &c->rr_nodes, &c->sizes, &c->cnt, &c->fill, &c->inv_off, &c->inv_sets, &c->covered,
-                    &c->selected, &c->best, &c->scan_tmp, &c->seed_bits, &c->jobs};
+                    &c->selected, &c->best, &c->scan_tmp, &c->bucket, &c->seed_bits, &c->jobs};
   for (DevBuf* b : bufs) release(c, *b);
   if (c->ctr) (void)hipFree(c->ctr);
   if (c->ctr_host) (void)hipHostFree(c->ctr_host);

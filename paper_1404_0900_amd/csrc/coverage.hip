@@ -370,6 +370,178 @@ __global__ __launch_bounds__(kThreads) void scatter_kernel(V sets, uint64_t nset
   }
 }
 
+// ---- counting sort of the entries by node range ----
+//
+// The counts pass above adds one device atomic per distinct node of every
+// tile, about two for every three entries on the large collections, and
+// device atomics to scattered addresses top out far below the memory's
+// bandwidth.  With a workspace, the index is built instead by a counting sort
+// in two levels: the entries are first moved into buckets of 2^shift
+// consecutive node ids (one atomic per bucket and tile of sets), then each
+// chunk of a bucket counts its nodes, and places its sets, in LDS, with one
+// device atomic per distinct node and chunk (none for a bucket of one chunk).
+// Counts and index are those of the direct passes: only the order of the sets
+// within a node's list differs, and no step of the greedy depends on it.
+constexpr int kBucketShiftMin = 10, kBucketShiftMax = 13;
+constexpr int kBucketMax = 8192;             // buckets (LDS counters per tile of sets)
+constexpr uint32_t kBucketChunk = 1u << 16;  // entries per block of the per-bucket passes
+
+// bcnt[b] += entries of the collection in bucket b.
+template <class V>
+__global__ __launch_bounds__(kThreads) void bucket_hist_kernel(V sets, uint64_t nsets, int shift, int nb,
+                                                               uint32_t* bcnt) {
+  constexpr int TS = kHistTileSets;
+  __shared__ int64_t s_start[TS];
+  __shared__ int64_t s_pre[TS + 1];
+  __shared__ uint32_t s_wtot[kThreads / 64];
+  __shared__ uint32_t h[kBucketMax];
+  for (uint64_t s0 = (uint64_t)blockIdx.x * TS; s0 < nsets; s0 += (uint64_t)gridDim.x * TS) {
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < TS && s0 + threadIdx.x < nsets) {
+      start = sets.start(s0 + threadIdx.x);
+      len = sets.len(s0 + threadIdx.x);
+    }
+    for (int i = threadIdx.x; i < nb; i += kThreads) h[i] = 0u;
+    tile_prefix<TS>(len, start, s_start, s_pre, s_wtot);
+    const int64_t tot = s_pre[TS];
+    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+      const int j = tile_set_of(s_pre, TS, e);
+      const uint32_t u = (uint32_t)sets.nodes[s_start[j] + (e - s_pre[j])];
+      atomicAdd(&h[u >> shift], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kThreads)
+      if (h[i]) atomicAdd(&bcnt[i], h[i]);
+    __syncthreads();
+  }
+}
+
+// Chunks of kBucketChunk entries per bucket: cstart[b] is bucket b's first
+// chunk, cstart[nb] their number, cb[c] the bucket of chunk c.
+__global__ __launch_bounds__(kThreads) void bucket_chunks_kernel(const int64_t* boff, int nb, uint32_t* cstart,
+                                                                 uint32_t* cb) {
+  __shared__ unsigned long long red[kThreads / 64];
+  unsigned long long carry = 0;
+  for (int base = 0; base < nb; base += kThreads) {
+    const int b = base + (int)threadIdx.x;
+    const unsigned long long len = b < nb ? (unsigned long long)(boff[b + 1] - boff[b]) : 0ull;
+    const unsigned long long ch = (len + kBucketChunk - 1) / kBucketChunk;
+    unsigned long long total;
+    const unsigned long long ex = block_excl_scan(ch, red, &total);
+    if (b < nb) {
+      const uint32_t c0 = (uint32_t)(carry + ex);
+      cstart[b] = c0;
+      for (uint32_t j = 0; j < (uint32_t)ch; ++j) cb[c0 + j] = (uint32_t)b;
+    }
+    carry += total;
+  }
+  if (threadIdx.x == 0) cstart[nb] = (uint32_t)carry;
+}
+
+// Moves every entry (and, for the index, its set id) into its bucket.
+template <class V, bool INDEX>
+__global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(V sets, uint64_t nsets, int shift, int nb,
+                                                                  const int64_t* boff, uint32_t* bfill, uint32_t* bu,
+                                                                  uint32_t* bs) {
+  constexpr int TS = kHistTileSets;
+  __shared__ int64_t s_start[TS];
+  __shared__ int64_t s_pre[TS + 1];
+  __shared__ uint32_t s_wtot[kThreads / 64];
+  __shared__ uint32_t h[kBucketMax];  // the tile's entries per bucket, then their next position
+  for (uint64_t s0 = (uint64_t)blockIdx.x * TS; s0 < nsets; s0 += (uint64_t)gridDim.x * TS) {
+    uint32_t len = 0;
+    int64_t start = 0;
+    if (threadIdx.x < TS && s0 + threadIdx.x < nsets) {
+      start = sets.start(s0 + threadIdx.x);
+      len = sets.len(s0 + threadIdx.x);
+    }
+    for (int i = threadIdx.x; i < nb; i += kThreads) h[i] = 0u;
+    tile_prefix<TS>(len, start, s_start, s_pre, s_wtot);
+    const int64_t tot = s_pre[TS];
+    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+      const int j = tile_set_of(s_pre, TS, e);
+      const uint32_t u = (uint32_t)sets.nodes[s_start[j] + (e - s_pre[j])];
+      atomicAdd(&h[u >> shift], 1u);
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < nb; i += kThreads)
+      if (h[i]) h[i] = (uint32_t)boff[i] + atomicAdd(&bfill[i], h[i]);
+    __syncthreads();
+    for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
+      const int j = tile_set_of(s_pre, TS, e);
+      const uint32_t u = (uint32_t)sets.nodes[s_start[j] + (e - s_pre[j])];
+      const uint32_t pos = atomicAdd(&h[u >> shift], 1u);
+      bu[pos] = u;
+      if (INDEX) bs[pos] = (uint32_t)(s0 + (uint64_t)j);
+    }
+    __syncthreads();
+  }
+}
+
+// The bucket, first entry and end of chunk blockIdx.x; false past the last chunk.
+__device__ __forceinline__ bool chunk_of(const int64_t* boff, const uint32_t* cstart, const uint32_t* cb, int nb,
+                                         uint32_t& b, int64_t& e0, int64_t& e1, bool& alone) {
+  const uint32_t c = blockIdx.x;
+  if (c >= cstart[nb]) return false;
+  b = cb[c];
+  e0 = boff[b] + (int64_t)(c - cstart[b]) * kBucketChunk;
+  e1 = min(e0 + (int64_t)kBucketChunk, boff[b + 1]);
+  alone = cstart[b + 1] - cstart[b] == 1u;
+  return true;
+}
+
+// cnt of the chunk's node range: stored where the chunk is its bucket's only
+// one, else added with one atomic per node present.
+__global__ __launch_bounds__(kThreads) void bucket_count_kernel(const uint32_t* bu, const int64_t* boff,
+                                                                const uint32_t* cstart, const uint32_t* cb, int nb,
+                                                                int shift, int64_t n, uint32_t* cnt) {
+  __shared__ uint32_t lc[1 << kBucketShiftMax];
+  uint32_t b;
+  int64_t e0, e1;
+  bool alone;
+  if (!chunk_of(boff, cstart, cb, nb, b, e0, e1, alone)) return;
+  const int range = 1 << shift;
+  const uint32_t base = b << shift;
+  for (int i = threadIdx.x; i < range; i += kThreads) lc[i] = 0u;
+  __syncthreads();
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) atomicAdd(&lc[bu[e] - base], 1u);
+  __syncthreads();
+  for (int i = threadIdx.x; i < range && (int64_t)base + i < n; i += kThreads) {
+    if (alone) cnt[base + i] = lc[i];
+    else if (lc[i]) atomicAdd(&cnt[base + i], lc[i]);
+  }
+}
+
+// inv_sets of the chunk's nodes: positions from inv_off, plus a base per node
+// taken from fill where the bucket has several chunks.
+__global__ __launch_bounds__(kThreads) void bucket_index_kernel(const uint32_t* bu, const uint32_t* bs,
+                                                                const int64_t* boff, const uint32_t* cstart,
+                                                                const uint32_t* cb, int nb, int shift, int64_t n,
+                                                                const int64_t* inv_off, uint32_t* fill,
+                                                                uint32_t* inv_sets) {
+  __shared__ uint32_t lc[1 << kBucketShiftMax];  // the chunk's entries per node, then their next position
+  uint32_t b;
+  int64_t e0, e1;
+  bool alone;
+  if (!chunk_of(boff, cstart, cb, nb, b, e0, e1, alone)) return;
+  const int range = 1 << shift;
+  const uint32_t base = b << shift;
+  for (int i = threadIdx.x; i < range; i += kThreads) lc[i] = 0u;
+  __syncthreads();
+  if (!alone) {
+    for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) atomicAdd(&lc[bu[e] - base], 1u);
+    __syncthreads();
+    for (int i = threadIdx.x; i < range && (int64_t)base + i < n; i += kThreads)
+      if (lc[i]) lc[i] = atomicAdd(&fill[base + i], lc[i]);
+    __syncthreads();
+  }
+  for (int64_t e = e0 + threadIdx.x; e < e1; e += kThreads) {
+    const uint32_t u = bu[e];
+    inv_sets[inv_off[u] + atomicAdd(&lc[u - base], 1u)] = bs[e];
+  }
+}
+
 // Key of node u: 0 if selected, else count<<32 | (0xFFFFFFFF - u), so the
 // maximum key is the largest count with the lowest id; unselected keys > 0.
 // Few blocks, 4 nodes per thread and load: one atomicMax per block.
@@ -532,10 +704,101 @@ unsigned tile_grid(uint64_t items, uint64_t per_tile) {
 
 }  // namespace
 
+// ---- the counting sort's workspace ----
+namespace {
+
+int bucket_shift(int64_t n) {
+  int shift = kBucketShiftMin;
+  while (shift <= kBucketShiftMax && ((n + (1ll << shift) - 1) >> shift) > kBucketMax) ++shift;
+  return shift;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct BucketLayout {
+  int shift = 0, nb = 0;
+  uint64_t max_chunks = 0;
+  size_t bcnt = 0, bfill = 0, boff = 0, cstart = 0, cb = 0, temp = 0, bu = 0, bs = 0, bytes = 0;
+};
+
+// Offsets of the workspace's arrays; bytes == 0 where the collection does not
+// fit the counting sort (node ids beyond its ranges, 2^32 entries or more).
+BucketLayout bucket_layout(int64_t n, uint64_t total, bool index) {
+  BucketLayout L;
+  L.shift = bucket_shift(n);
+  if (L.shift > kBucketShiftMax || total >= 0xFFFFFFFFull || n < 1) return L;
+  L.nb = (int)((n + (1ll << L.shift) - 1) >> L.shift);
+  L.max_chunks = (uint64_t)L.nb + total / kBucketChunk + 1;
+  size_t at = 0;
+  L.bcnt = at;
+  at += align256((size_t)L.nb * 4);
+  L.bfill = at;
+  at += align256((size_t)L.nb * 4);
+  L.boff = at;
+  at += align256((size_t)(L.nb + 1) * 8);
+  L.cstart = at;
+  at += align256((size_t)(L.nb + 1) * 4);
+  L.cb = at;
+  at += align256((size_t)L.max_chunks * 4);
+  L.temp = at;
+  at += align256(scan_temp_bytes((uint64_t)L.nb));
+  L.bu = at;
+  at += align256((size_t)total * 4);
+  L.bs = at;
+  if (index) at += align256((size_t)total * 4);
+  L.bytes = at;
+  return L;
+}
+
+template <class T>
+T* at_offset(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+// Sorts the entries into buckets and counts them (cnt zeroed first); with
+// `index`, leaves the set ids beside them for bucket_index_kernel.
+template <class V>
+void bucket_counts(const GreedyArgs& a, V sets, const BucketLayout& L, bool index, hipStream_t s) {
+  uint32_t* bcnt = at_offset<uint32_t>(a.bkt, L.bcnt);
+  int64_t* boff = at_offset<int64_t>(a.bkt, L.boff);
+  uint32_t* cstart = at_offset<uint32_t>(a.bkt, L.cstart);
+  uint32_t* cb = at_offset<uint32_t>(a.bkt, L.cb);
+  uint32_t* bu = at_offset<uint32_t>(a.bkt, L.bu);
+  uint32_t* bs = index ? at_offset<uint32_t>(a.bkt, L.bs) : nullptr;
+  // bcnt and bfill are adjacent: one clear
+  hipLaunchKernelGGL(zero_u32, dim3(grid_for((uint64_t)(L.bfill - L.bcnt) / 4 + (uint64_t)L.nb, 64)), dim3(kThreads),
+                     0, s, bcnt, (uint64_t)(L.bfill - L.bcnt) / 4 + (uint64_t)L.nb);
+  const unsigned grid = tile_grid(a.nsets, kHistTileSets);
+  hipLaunchKernelGGL(bucket_hist_kernel<V>, dim3(grid), dim3(kThreads), 0, s, sets, a.nsets, L.shift, L.nb, bcnt);
+  launch_scan_u32_to_i64(bcnt, boff, (uint64_t)L.nb, at_offset<void>(a.bkt, L.temp), s);
+  hipLaunchKernelGGL(bucket_chunks_kernel, dim3(1), dim3(kThreads), 0, s, boff, L.nb, cstart, cb);
+  uint32_t* bfill = at_offset<uint32_t>(a.bkt, L.bfill);
+  if (index)
+    hipLaunchKernelGGL((bucket_scatter_kernel<V, true>), dim3(grid), dim3(kThreads), 0, s, sets, a.nsets, L.shift,
+                       L.nb, boff, bfill, bu, bs);
+  else
+    hipLaunchKernelGGL((bucket_scatter_kernel<V, false>), dim3(grid), dim3(kThreads), 0, s, sets, a.nsets, L.shift,
+                       L.nb, boff, bfill, bu, bs);
+  hipLaunchKernelGGL(bucket_count_kernel, dim3((unsigned)L.max_chunks), dim3(kThreads), 0, s, bu, boff, cstart, cb,
+                     L.nb, L.shift, a.n, a.cnt);
+}
+
+}  // namespace
+
+size_t bucket_workspace_bytes(int64_t n, uint64_t total, bool index) { return bucket_layout(n, total, index).bytes; }
+
 void launch_counts(const GreedyArgs& a, hipStream_t s) {
   const uint64_t n = (uint64_t)a.n;
   hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.cnt, n);
   if (!a.nsets) return;
+  if (a.bkt && a.total) {
+    const BucketLayout L = bucket_layout(a.n, a.total, false);
+    if (L.bytes) {
+      if (a.set_off) bucket_counts(a, csr_of(a), L, false, s);
+      else bucket_counts(a, pool_of(a), L, false, s);
+      return;
+    }
+  }
   if (a.set_off) {
     if (a.total)
       hipLaunchKernelGGL(hist_flat_kernel, dim3(tile_grid(a.total, kTileEntries)), dim3(kThreads), 0, s, a.nodes,
@@ -548,6 +811,21 @@ void launch_counts(const GreedyArgs& a, hipStream_t s) {
 
 void launch_index(const GreedyArgs& a, hipStream_t s) {
   const uint64_t n = (uint64_t)a.n;
+  if (a.bkt && a.nsets && a.total) {
+    const BucketLayout L = bucket_layout(a.n, a.total, true);
+    if (L.bytes) {
+      hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.cnt, n);
+      if (a.set_off) bucket_counts(a, csr_of(a), L, true, s);
+      else bucket_counts(a, pool_of(a), L, true, s);
+      hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.fill, n);
+      launch_scan_u32_to_i64(a.cnt, a.inv_off, n, a.scan_temp, s);
+      hipLaunchKernelGGL(bucket_index_kernel, dim3((unsigned)L.max_chunks), dim3(kThreads), 0, s,
+                         at_offset<uint32_t>(a.bkt, L.bu), at_offset<uint32_t>(a.bkt, L.bs),
+                         at_offset<int64_t>(a.bkt, L.boff), at_offset<uint32_t>(a.bkt, L.cstart),
+                         at_offset<uint32_t>(a.bkt, L.cb), L.nb, L.shift, a.n, a.inv_off, a.fill, a.inv_sets);
+      return;
+    }
+  }
   launch_counts(a, s);
   hipLaunchKernelGGL(zero_u32, dim3(grid_for(n, 4096)), dim3(kThreads), 0, s, a.fill, n);
   launch_scan_u32_to_i64(a.cnt, a.inv_off, n, a.scan_temp, s);

@@ -226,7 +226,11 @@ struct GreedyArgs {
   uint8_t* selected;   // n
   unsigned long long* best;  // k packed (count, ~id) keys
   void* scan_temp;
+  void* bkt;           // optional: bucket_workspace_bytes(n, total, index) for the counting sort by node range
 };
+// Workspace of the counting sort by node range that launch_counts and
+// launch_index use when GreedyArgs.bkt is set; 0 where it does not apply.
+size_t bucket_workspace_bytes(int64_t n, uint64_t total, bool index);
 // Coverage counts only (the greedy of k = 1 needs no index).
 void launch_counts(const GreedyArgs& a, hipStream_t s);
 void launch_index(const GreedyArgs& a, hipStream_t s);

@@ -210,6 +210,7 @@ void launch_spread(int, const SpreadArgs& a, hipStream_t s) {
 }
 
 size_t scan_temp_bytes(uint64_t len) { return (len / 4096 + 2) * 8; }
+size_t bucket_workspace_bytes(int64_t n, uint64_t total, bool index) { return 256 + (size_t)n / 64 + total * (index ? 8 : 4); }
 void launch_scan_u32_to_i64(const uint32_t* in, int64_t* out, uint64_t len, void*, hipStream_t s) {
   stub_submit(s, [=] {
     int64_t acc = 0;
