@@ -382,7 +382,9 @@ __global__ __launch_bounds__(kThreads) void scatter_kernel(V sets, uint64_t nset
 // device atomic per distinct node and chunk (none for a bucket of one chunk).
 // Counts and index are those of the direct passes: only the order of the sets
 // within a node's list differs, and no step of the greedy depends on it.
-constexpr int kBucketShiftMin = 10, kBucketShiftMax = 13;
+// Buckets of 8192 nodes (32 KB of LDS counters per chunk): the fewer the
+// buckets, the longer the runs each tile of sets writes into one bucket.
+constexpr int kBucketShiftMin = 13, kBucketShiftMax = 13;
 constexpr int kBucketMax = 8192;             // buckets (LDS counters per tile of sets)
 constexpr uint32_t kBucketChunk = 1u << 16;  // entries per block of the per-bucket passes
 
