@@ -44,9 +44,6 @@ constexpr int kSegThreads = 256;   // block size of the IC segment kernels
 constexpr int kLtWaves = 2;        // wavefronts per block, LT lane-level pass
 constexpr int kChain = 64;         // LT chain length held in LDS
 constexpr int kBigThreads = 512;   // IC last-tier block size
-// A pair of 32-bit words at 4-byte alignment (one 8-byte read).
-typedef uint2 uint2_a4 __attribute__((aligned(4)));
-
 constexpr int kSegGroups = 1;      // 4-edge groups a lane decides per step (IC tiers 0 and 1)
 constexpr int kSegPasses = 2;      // batches of queued nodes a segment may take per iteration (IC tiers 0 and 1)
 constexpr uint64_t kKappaBlocks = 1024;  // largest grid of the kappa pass (four per CU)
@@ -644,9 +641,8 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
         ng = 0;
         if (sl < nb) {
           const int32_t v = q[head + sl];
-          const uint2 oe = *reinterpret_cast<const uint2_a4*>(g.off32 + v);  // off[v], off[v+1]
-          ea = oe.x;
-          const uint32_t eb = oe.y;
+          ea = g.off32[v];  // with off32[v + 1]: one 8-byte load
+          const uint32_t eb = g.off32[v + 1];
           d = eb - ea;
           ng = d ? ((eb - 1u) >> 2) - (ea >> 2) + 1u : 0u;
         }
