@@ -105,6 +105,7 @@ struct tim_ctx {
   int grid_lt[3] = {};
   int grid_lt_chain[3] = {};
   int grid_trig[3] = {};          // general-triggering first tier
+  int grid_trig1[3] = {};         // general-triggering one-set-per-wavefront tier
   int grid_rounds[2][2] = {};     // multi-job launches of KptEstimation rounds: tier 0 per [model][wc]
   int grid_batch1[2] = {};        // their IC tier 1, per wc
   int grid_batch_chain = 0;       // their LT long-chain tier
@@ -379,7 +380,7 @@ uint64_t sample_grid(const tim_ctx* c, int model, int mode, bool wc, uint64_t co
                      : lanes == c->seg_lanes ? c->grid_ic[mode][wc ? 1 : 0]
                                              : c->grid_ic_wide[mode][wc ? 1 : 0];
   const uint64_t waves_per_block = model == TIM_MODEL_LT ? 2 : 4;
-  uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)lanes) : model == TIM_MODEL_LT ? 128 : 4;
+  uint64_t sets_per_block = model == TIM_MODEL_IC ? 4 * (64 / (uint64_t)lanes) : model == TIM_MODEL_LT ? 128 : 16;
   if (mode == tim::kModeEmit && c->emit_wave_sets)
     sets_per_block = std::max<uint64_t>(sets_per_block, waves_per_block * c->emit_wave_sets);
   uint64_t grid = (uint64_t)per_cu * (uint64_t)c->num_cu;
@@ -439,7 +440,7 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
                          uint64_t set_offset, uint64_t pool_base, Totals* t) {
   if (model != TIM_MODEL_LT) TIM_TRY(ensure_big(c, g->n));  // the LT long-chain tier needs no slots
   TIM_TRY(ensure(c, c->list1, count * 8, "deferred-set list"));
-  if (model == TIM_MODEL_IC) TIM_TRY(ensure(c, c->list2, count * 8, "deferred-set list"));
+  if (model != TIM_MODEL_LT) TIM_TRY(ensure(c, c->list2, count * 8, "deferred-set list"));
   SampleArgs a;
   memset(&a, 0, sizeof(a));
   a.g.off = g->off;
@@ -500,9 +501,10 @@ tim_status sample_launch(tim_ctx* c, const tim_graph* g, int model, int mode, ui
     h = req.h;
   } else {
     const uint64_t grid0 = sample_grid(c, model, mode, wc, count, nullptr);
-    const uint64_t grid1 =
-        (uint64_t)(model == TIM_MODEL_IC ? c->grid_ic64[mode][wc ? 1 : 0] : c->grid_lt_chain[mode]) *
-        (uint64_t)c->num_cu;
+    const uint64_t grid1 = (uint64_t)(model == TIM_MODEL_IC        ? c->grid_ic64[mode][wc ? 1 : 0]
+                                      : model == TIM_MODEL_TRIGGER ? c->grid_trig1[mode]
+                                                                   : c->grid_lt_chain[mode]) *
+                           (uint64_t)c->num_cu;
     tim::launch_clear_counters(c->ctr, c->stream);
     if (c->prof_on) HIP_TRY(hipEventRecord(c->pev[0], c->stream));
     tim::launch_sample(model, mode, a, launch_lanes(c, model, mode, count), (int)grid0, (int)grid1, c->stream,
@@ -2052,6 +2054,7 @@ tim_status tim_ctx_create(int device, void* stream, uint64_t hbm_budget_bytes, t
     }
     c->grid_lt[mode] = tim::lt_lane_blocks_per_cu(mode);
     c->grid_trig[mode] = tim::trig_blocks_per_cu(mode);
+    c->grid_trig1[mode] = tim::trig_tier1_blocks_per_cu(mode);
     c->grid_lt_chain[mode] = tim::lt_chain_blocks_per_cu(mode, false);
   }
   for (int wc = 0; wc < 2; ++wc) {

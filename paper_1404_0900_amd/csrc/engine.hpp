@@ -104,7 +104,8 @@ int ic_blocks_per_cu(int mode, bool wc, int seg_lanes);
 int ic_tier1_blocks_per_cu(int mode, bool wc);
 int lt_lane_blocks_per_cu(int mode);
 // Occupancy of the general-triggering first tier (one set per wavefront).
-int trig_blocks_per_cu(int mode);
+int trig_blocks_per_cu(int mode);         // tier 0 of the triggering model
+int trig_tier1_blocks_per_cu(int mode);   // its one-set-per-wavefront tier
 // Occupancy of the LT long-chain tier (single or batched launches).
 int lt_chain_blocks_per_cu(int mode, bool batch);
 // Largest set the first tier keeps in LDS (IC: its queue for seg_lanes lanes

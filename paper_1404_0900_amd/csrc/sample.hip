@@ -1130,14 +1130,20 @@ __global__ __launch_bounds__(kBigThreads) void ic_big_kernel(SampleArgs a, TierI
 // General triggering model (Section 4.2): every dequeued node v draws its
 // triggering set T(v) from an explicit distribution over subsets of its
 // in-edges (trig_pick), and the unvisited members of T(v) join the set.
-// Tier 0: one set per wavefront, its lanes taking up to 64 queued nodes at a
-// time; the queue (also the stored set) and an open-addressing visited hash
-// live in LDS.  Sets that outgrow them are deferred to the last tier, one
-// 512-thread block per set with visited stamps and a queue in device memory.
+// Tier 0: 16 lanes per set, four sets per wavefront, each lane taking one
+// queued node of its set per step; per set a queue of 128 nodes (also the
+// stored set) and an open-addressing visited hash of 256 slots in LDS.
+// Tier 1: one set per wavefront, its lanes taking up to 64 queued nodes at a
+// time, with a queue of 1024 and a hash of 2048.  Sets that outgrow a tier are
+// deferred to the next; the last is one 512-thread block per set with visited
+// stamps and a queue in device memory.
 // ------------------------------------------------------------------------
-constexpr int kTrigWaves = 4;   // wavefronts per tier-0 block
-constexpr int kTrigQ = 256;     // largest set tier 0 keeps
-constexpr int kTrigHlog = 9;    // 512 hash slots per set
+constexpr int kTrigSegLanes = 16;  // lanes per set in tier 0
+constexpr int kTrigSegQ = 128;     // largest set tier 0 keeps
+constexpr int kTrigSegHlog = 8;    // 256 hash slots per set in tier 0
+constexpr int kTrigWaves = 4;      // wavefronts per tier-1 block
+constexpr int kTrigQ = 1024;       // largest set tier 1 keeps
+constexpr int kTrigHlog = 11;      // 2048 hash slots per set in tier 1
 
 template <int MODE>
 __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO& io, BlockAcc* blk) {
@@ -1151,15 +1157,16 @@ __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO&
   uint32_t* h = s_h[wv];
   const GraphView g = a.g;
   const Key key = make_key(a.seed);
-  const unsigned long long total = a.count;
+  const unsigned long long total = io.in_list ? list_len(a, io.in_len_ctr) : a.count;
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kTrigWaves, 1);
   unsigned long long pool_next = 0, pool_end = 0;
   bool exhausted = false;
   for (;;) {
-    unsigned long long rel = 0;
-    if (!take(a, io.next_ctr, total, res, !exhausted, lane == 0, 0ull, lane, exhausted, rel)) break;
+    unsigned long long item = 0;
+    if (!take(a, io.next_ctr, total, res, !exhausted, lane == 0, 0ull, lane, exhausted, item)) break;
+    const unsigned long long rel = io.in_list ? io.in_list[item] : item;
     const SetStream st = make_set_stream(a.phase, a.first + rel);
     const int32_t root = draw_root(key, st, g.n);
     for (int i = lane; i < H; i += kWave) h[i] = 0u;
@@ -1216,8 +1223,9 @@ __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO&
       }
     } else if (MODE == kModeEmit) {
       const uint32_t mine = lane == 0 ? len : 0u;
-      const unsigned long long my_base =
-          pool_place(a, (unsigned long long)a.pool_chunk, mine, len, len, pool_next, pool_end, lane);
+      // tier 0 reserves slices; the deferral tiers (few sets) exactly what they store
+      const unsigned long long slice = io.acc == 0 ? (unsigned long long)a.pool_chunk : 0ull;
+      const unsigned long long my_base = pool_place(a, slice, mine, len, len, pool_next, pool_end, lane);
       const unsigned long long base = __shfl(my_base, 0);
       if (base + len <= a.pool_cap)
         for (uint32_t i = lane; i < len; i += kWave) a.pool[base + i] = q[i];
@@ -1242,6 +1250,169 @@ __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO&
     wave_sync();
   }
   flush_acc(a, blk, acc, io.acc, lane);
+}
+
+// Tier 0 of the triggering model (see above).
+template <int MODE>
+__global__ __launch_bounds__(kSegThreads) void trig_seg_kernel(SampleArgs a, TierIO io) {
+  constexpr int S = kTrigSegLanes, Q = kTrigSegQ, H = 1 << kTrigSegHlog;
+  constexpr int NSEG = kSegThreads / S;
+  __shared__ int32_t s_q[NSEG][Q];
+  __shared__ __align__(16) uint32_t s_h[NSEG][H];
+  __shared__ uint32_t s_tail[NSEG];
+  __shared__ BlockAcc blk;
+  block_acc_init(blk);
+  const int lane = threadIdx.x % kWave;
+  const int sl = threadIdx.x % S;   // lane within the segment
+  const int seg = threadIdx.x / S;  // segment within the block
+  const int sw = lane / S;          // segment within the wavefront
+  const int leader = sw * S;
+  const bool is_leader = sl == 0;
+  const uint64_t below_leader = leader ? (~0ull >> (64 - leader)) : 0ull;
+  const uint64_t below = lane ? (~0ull >> (64 - lane)) : 0ull;
+  int32_t* q = s_q[seg];
+  uint32_t* h = s_h[seg];
+  uint32_t* tailp = &s_tail[seg];
+  const GraphView g = a.g;
+  const Key key = make_key(a.seed);
+  const unsigned long long total = a.count;
+  Acc acc;
+  Reservoir res;
+  res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
+  RootBuffer rb;
+  unsigned long long pool_next = 0, pool_end = 0;
+  // segment state (the same in every lane of a segment)
+  bool has = false, exhausted = false, hit = false, bad = false;
+  unsigned long long rel = 0;
+  SetStream st = make_set_stream(a.phase, a.first);
+  int head = 0;
+  unsigned long long wlane = 0;  // lane: in-degrees of the nodes it took
+  for (;;) {
+    // ---- A: sets whose queued nodes are all done are finished (or deferred)
+    bool fin = false, defer_now = false;
+    uint32_t fin_len = 0;
+    unsigned long long fin_width = 0;
+    if (has) {
+      const int tail = (int)*tailp;
+      if (bad || hit || head >= tail) {
+        fin_width = seg_sum<S>(wlane);
+        has = false;
+        fin_len = (uint32_t)min(tail, Q);
+        if (bad && !(MODE == kModeCover && hit)) {
+          defer_now = true;
+        } else {
+          fin = true;
+          if (is_leader && MODE != kModeEmit) {
+            acc.width += fin_width;
+            acc.nodes += fin_len;
+            if (MODE == kModeWidth) {
+              a.wbuf[rel] = (uint32_t)fin_width;
+              if (a.sizes) a.sizes[rel] = fin_len;
+            } else if (hit) {
+              acc.covered += 1;
+            }
+          }
+        }
+      }
+    }
+    {
+      const bool dl = defer_now && is_leader;
+      const uint64_t dm = __ballot(dl);
+      if (dm) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&a.ctr[io.out_len_ctr], (unsigned long long)__popcll(dm));
+        base = __shfl(base, 0);
+        if (dl) {
+          const unsigned long long pos = base + (unsigned long long)__popcll(dm & below);
+          if (pos < a.count) io.out_list[pos] = rel;
+        }
+      }
+    }
+    if (MODE == kModeEmit) {
+      const uint32_t mine = (fin && is_leader) ? fin_len : 0u;
+      const uint64_t fm = __ballot(mine != 0u);
+      if (fm) {
+        const uint32_t winc = seg_incl_scan<kWave>(mine, lane);
+        const uint32_t tot = (uint32_t)__builtin_amdgcn_readlane((int)winc, kWave - 1);
+        const unsigned long long my_base =
+            pool_place(a, (unsigned long long)a.pool_chunk, mine, winc, tot, pool_next, pool_end, lane);
+        const unsigned long long base = __shfl(my_base, leader);
+        if (fin) {
+          if (base + fin_len <= a.pool_cap)
+            for (uint32_t i = sl; i < fin_len; i += S) a.pool[base + i] = q[i];
+          if (is_leader) {
+            a.set_start[rel] = a.pool_base + base;
+            a.set_len[rel] = fin_len;
+            if (a.widths) a.widths[rel] = fin_width;
+            if (a.wbuf) a.wbuf[rel] = (uint32_t)fin_width;
+            acc.width += fin_width;
+            acc.nodes += fin_len;
+          }
+        }
+      }
+    }
+    wave_sync();
+
+    // ---- B: idle segments take their next set
+    {
+      int32_t root = 0;
+      const bool want = !has && !exhausted;
+      if (take_set(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
+        st = make_set_stream(a.phase, a.first + rel);
+        uint4* h4 = reinterpret_cast<uint4*>(h);
+        for (int i = sl; i < H / 4; i += S) h4[i] = make_uint4(0u, 0u, 0u, 0u);
+        wave_sync();
+        if (is_leader) {
+          q[0] = root;
+          *tailp = 1u;
+          lds_insert<kTrigSegHlog>(h, (uint32_t)root);
+        }
+        has = true;
+        hit = (MODE == kModeCover) && in_seed(a.seed_bits, root);
+        bad = false;
+        head = 0;
+        wlane = 0;
+      }
+    }
+    if (__ballot(has) == 0) break;
+    wave_sync();
+
+    // ---- C: each set's next queued nodes, one per lane: T(v) by trig_pick
+    bool lbad = false, lhit = false;
+    if (has && !hit && !bad) {
+      const int tail = (int)*tailp;
+      const int nb = min(tail - head, S);
+      if (sl < nb) {
+        const int32_t v = q[head + sl];
+        const int64_t ea = g.off[v];
+        wlane += (unsigned long long)(g.off[v + 1] - ea);
+        const int64_t j = trig_pick(g, key, st, v);
+        if (j >= 0) {
+          const int64_t m1 = g.tset[j + 1];
+          for (int64_t i = g.tset[j]; i < m1; ++i) {
+            const int32_t u = g.src[ea + (int64_t)g.tmem[i]];
+            const int r = lds_insert<kTrigSegHlog>(h, (uint32_t)u);
+            if (r < 0) {
+              lbad = true;
+              break;
+            }
+            if (r == 1) {
+              const uint32_t pos = atomicAdd(tailp, 1u);
+              if (pos < (uint32_t)Q) q[pos] = u;
+              else lbad = true;
+              if (MODE == kModeCover && in_seed(a.seed_bits, u)) lhit = true;
+            }
+          }
+        }
+      }
+      head += nb;
+    }
+    wave_sync();
+    const uint64_t hm = __ballot(lhit), bm = __ballot(lbad);
+    hit = hit || seg_bits<S>(hm, sw) != 0ull;
+    bad = bad || seg_bits<S>(bm, sw) != 0ull;
+  }
+  flush_acc(a, &blk, acc, io.acc, lane);
 }
 
 template <int MODE>
@@ -1852,11 +2023,13 @@ void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, 
 }
 
 template <int MODE>
-void launch_trig(const SampleArgs& a, int grid0, hipStream_t s, hipEvent_t after0) {
+void launch_trig(const SampleArgs& a, int grid0, int grid1, hipStream_t s, hipEvent_t after0) {
   const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
-  const TierIO t2 = {a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2};
-  hipLaunchKernelGGL((trig_wave_kernel<MODE>), dim3(grid0), dim3(kTrigWaves * kWave), 0, s, a, t0);
+  const TierIO t1 = {a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1};
+  const TierIO t2 = {a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2};
+  hipLaunchKernelGGL((trig_seg_kernel<MODE>), dim3(grid0), dim3(kSegThreads), 0, s, a, t0);
   if (after0) (void)hipEventRecord(after0, s);
+  hipLaunchKernelGGL((trig_wave_kernel<MODE>), dim3(grid1), dim3(kTrigWaves * kWave), 0, s, a, t1);
   hipLaunchKernelGGL((trig_big_kernel<MODE>), dim3(a.big_slots), dim3(kBigThreads), 0, s, a, t2);
   if (MODE == kModeWidth || (MODE == kModeEmit && a.wbuf)) launch_kappa_reduce(a, s);
 }
@@ -1966,6 +2139,14 @@ int lt_lane_blocks_per_cu(int mode) {
 
 int trig_blocks_per_cu(int mode) {
   switch (mode) {
+    case 0: return blocks_per_cu(trig_seg_kernel<kModeWidth>, kSegThreads);
+    case 1: return blocks_per_cu(trig_seg_kernel<kModeEmit>, kSegThreads);
+    default: return blocks_per_cu(trig_seg_kernel<kModeCover>, kSegThreads);
+  }
+}
+
+int trig_tier1_blocks_per_cu(int mode) {
+  switch (mode) {
     case 0: return blocks_per_cu(trig_wave_kernel<kModeWidth>, kTrigWaves * kWave);
     case 1: return blocks_per_cu(trig_wave_kernel<kModeEmit>, kTrigWaves * kWave);
     default: return blocks_per_cu(trig_wave_kernel<kModeCover>, kTrigWaves * kWave);
@@ -1974,7 +2155,7 @@ int trig_blocks_per_cu(int mode) {
 
 uint32_t tier0_set_cap(int model, int seg_lanes) {
   if (model == 1) return (uint32_t)kChain;
-  if (model == 2) return (uint32_t)kTrigQ;
+  if (model == 2) return (uint32_t)kTrigSegQ;
   switch (seg_lanes) {
     case 4: return 64;
     case 8: return 128;
@@ -2058,9 +2239,9 @@ void launch_sample(int model, int mode, const SampleArgs& a, int seg_lanes, int 
     }
   } else if (model == 2) {
     switch (mode) {
-      case 0: launch_trig<kModeWidth>(a, grid0, s, after_tier0); break;
-      case 1: launch_trig<kModeEmit>(a, grid0, s, after_tier0); break;
-      default: launch_trig<kModeCover>(a, grid0, s, after_tier0); break;
+      case 0: launch_trig<kModeWidth>(a, grid0, grid1, s, after_tier0); break;
+      case 1: launch_trig<kModeEmit>(a, grid0, grid1, s, after_tier0); break;
+      default: launch_trig<kModeCover>(a, grid0, grid1, s, after_tier0); break;
     }
   } else {
     switch (mode) {

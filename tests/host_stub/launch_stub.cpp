@@ -107,6 +107,7 @@ int ic_blocks_per_cu(int, bool, int) { return 4; }
 int ic_tier1_blocks_per_cu(int, bool) { return 2; }
 int lt_lane_blocks_per_cu(int) { return 4; }
 int trig_blocks_per_cu(int) { return 4; }
+int trig_tier1_blocks_per_cu(int) { return 4; }
 int lt_chain_blocks_per_cu(int, bool) { return 2; }
 uint32_t tier0_set_cap(int model, int seg_lanes) {
   if (model == 1) return 64;
