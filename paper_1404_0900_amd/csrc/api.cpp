@@ -203,13 +203,17 @@ tim_graph const* check_graph(const tim_ctx* c, const tim_graph* g) {
 // (batch members use the hub's slots).
 tim_status ensure_big(tim_ctx* c, int64_t n) {
   if (c->hub) return TIM_OK;
-  if (c->big_n == n) return TIM_OK;
+  // slots sized for a larger graph serve a smaller one (stamps are epochs, never cleared between sets)
+  if (c->big_slots > 0 && c->big_n >= n) return TIM_OK;
   release(c, c->big_stamp);
   release(c, c->big_queue);
   release(c, c->big_epoch);
   c->big_n = -1;
-  // one slot per CU where memory allows (8 bytes per node per slot); at
-  // most a quarter of the budget, or of the free device memory without one
+  // one slot per CU where memory allows (8 bytes per node per slot), up to
+  // four while they take at most a sixteenth of it (four blocks per CU share
+  // the last tier's sets among them: supercritical graphs give that tier many
+  // sets); at most a quarter of the budget, or of the free device memory
+  // without one
   const uint64_t per = (uint64_t)n * 8;
   uint64_t room = 0;
   if (c->budget) {
@@ -219,7 +223,8 @@ tim_status ensure_big(tim_ctx* c, int64_t n) {
     HIP_TRY(hipMemGetInfo(&free_b, &total_b));
     room = free_b / 4;
   }
-  const int slots = (int)std::min<uint64_t>((uint64_t)std::max(c->num_cu, 64), room / per);
+  const int slots = (int)std::max(std::min<uint64_t>((uint64_t)std::max(c->num_cu, 64), room / per),
+                                  std::min<uint64_t>((uint64_t)std::max(4 * c->num_cu, 64), room / 4 / per));
   if (slots < 1)
     return fail(TIM_EBUDGET, "budget too small for the large-set pass (needs %llu bytes)",
                 (unsigned long long)per * 4);
@@ -1712,9 +1717,11 @@ tim_status hub_prepare(Hub* h, tim_ctx* parent, int64_t maxn, int workers) {
   h->limit = limit;
   maxn = std::max<int64_t>(maxn, 2);
   const uint64_t per = (uint64_t)maxn * 8;
-  const int slots = (int)std::min<uint64_t>((uint64_t)std::max(h->num_cu, 64), limit / 4 / per);
+  // as ensure_big: one slot per CU, up to four while they take at most a sixteenth of the limit
+  const int slots = (int)std::max(std::min<uint64_t>((uint64_t)std::max(h->num_cu, 64), limit / 4 / per),
+                                  std::min<uint64_t>((uint64_t)std::max(4 * h->num_cu, 64), limit / 16 / per));
   if (slots < 1) return fail(TIM_EBUDGET, "budget too small for the large-set pass of the batch");
-  if (h->big_stride < (uint64_t)maxn || h->big_slots != slots) {
+  if (h->big_stride < (uint64_t)maxn || h->big_slots == 0) {
     hub_free_slots(h);
     HIP_TRY(hipMalloc(&h->big_stamp, (size_t)slots * (size_t)maxn * 4));
     HIP_TRY(hipMalloc(&h->big_queue, (size_t)slots * (size_t)maxn * 4));
