@@ -50,18 +50,22 @@ def _upload(eng, g, trig):
 def _cases():
     cfg1 = synth.config_graph("cfg1")
     small = synth.chung_lu(2000, 16000, 2.1, 31)
+    giant = synth.chung_lu(8000, 120000, 2.1, 72)
     return [("cfg1 mass 0.3-0.8", cfg1, synth.random_triggering(cfg1, 61)),
-            # total probability 1 and up to 5 members per outcome: a giant reverse-reachable component, so
-            # some sets outgrow the first tier's 256 nodes and finish in the block tier
+            # total probability 1 and up to 5 members per outcome: sets of up to about 400 nodes, so
+            # some outgrow the first tier's 128 nodes and finish in the one-set-per-wavefront tier
             ("cfg1 mass 1", cfg1, synth.random_triggering(cfg1, 62, max_outcomes=3, max_size=5, p_full=1.0)),
-            ("dense 2K", small, synth.random_triggering(small, 63, max_outcomes=6, max_size=3, p_full=0.5))]
+            ("dense 2K", small, synth.random_triggering(small, 63, max_outcomes=6, max_size=3, p_full=0.5)),
+            # a giant reverse-reachable component: most sets have about 3000 nodes and finish in the block
+            # tier after passing through the other two
+            ("giant 8K", giant, synth.random_triggering(giant, 72, max_outcomes=2, max_size=6, p_full=1.0))]
 
 
-@pytest.mark.parametrize("case", range(3))
+@pytest.mark.parametrize("case", range(4))
 def test_trigger_sets_widths_kappa_and_cover(eng, case):
     name, g, trig = _cases()[case]
     dg = _upload(eng, g, trig)
-    count, first = 12000, 5
+    count, first = (3000 if case == 3 else 12000), 5
     _say(f"triggering sets: {name}")
     so, nodes, widths, st = eng.sample_rr(dg, TRIG, 17, 64, first, count)
     so, nd = _sorted_sets(so.cpu().numpy(), nodes.cpu().numpy())
@@ -71,7 +75,9 @@ def test_trigger_sets_widths_kappa_and_cover(eng, case):
     sizes = np.diff(wso)
     _say(f"  set sizes mean {sizes.mean():.2f} max {sizes.max()}, deferred {st.deferred}")
     if case == 1:
-        assert sizes.max() > 256 and st.deferred > 0  # the block tier took part
+        assert sizes.max() > 128 and st.deferred > 0  # the second tier took part
+    if case == 3:
+        assert sizes.max() > 1024 and sizes.min() <= 128 and st.deferred > 0  # every tier took part
     w, sz, wst = eng.sample_widths(dg, TRIG, 17, 64, first, count, 7)
     assert np.array_equal(w.cpu().numpy().astype(np.uint64), ww)
     assert np.array_equal(sz.cpu().numpy(), sizes.astype(np.int32))
