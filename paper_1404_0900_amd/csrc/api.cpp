@@ -1721,7 +1721,8 @@ tim_status hub_prepare(Hub* h, tim_ctx* parent, int64_t maxn, int workers) {
   const int slots = (int)std::max(std::min<uint64_t>((uint64_t)std::max(h->num_cu, 64), limit / 4 / per),
                                   std::min<uint64_t>((uint64_t)std::max(4 * h->num_cu, 64), limit / 16 / per));
   if (slots < 1) return fail(TIM_EBUDGET, "budget too small for the large-set pass of the batch");
-  if (h->big_stride < (uint64_t)maxn || h->big_slots == 0) {
+  // kept from an earlier batch unless too small for its graphs, or too large for this limit
+  if (h->big_stride < (uint64_t)maxn || h->big_slots == 0 || h->big_bytes > limit / 4) {
     hub_free_slots(h);
     HIP_TRY(hipMalloc(&h->big_stamp, (size_t)slots * (size_t)maxn * 4));
     HIP_TRY(hipMalloc(&h->big_queue, (size_t)slots * (size_t)maxn * 4));
