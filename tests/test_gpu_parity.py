@@ -221,6 +221,31 @@ def test_max_coverage_random_collections(eng):
         assert np.array_equal(seeds, ws) and np.array_equal(gains, wg), trial
 
 
+@pytest.mark.parametrize("n", [20000, 5000])
+def test_max_coverage_many_chunks_per_bucket(eng, n):
+    # The counts and index are built by a counting sort over buckets of 8192 consecutive node ids, each
+    # bucket counted in chunks of 65536 entries: sets drawn mostly from a few low ids put hundreds of
+    # thousands of entries into the first bucket (many chunks, merged by device atomics) beside buckets of
+    # one chunk (stored directly) and a last bucket shorter than 8192 ids.
+    import torch
+    rng = np.random.default_rng(11 + n)
+    nsets = 60000
+    sizes = rng.integers(1, 12, size=nsets)
+    sets = []
+    for sz in sizes:
+        hot = rng.choice(64, size=min(int(sz), 64), replace=False)
+        cold = rng.choice(n, size=int(sz), replace=False)
+        sets.append(np.unique(np.where(rng.random(int(sz)) < 0.7, hot[: int(sz)], cold)))
+    off = np.zeros(nsets + 1, dtype=np.int64)
+    off[1:] = np.cumsum([len(x) for x in sets])
+    nodes = np.concatenate(sets).astype(np.int32)
+    assert np.sum(nodes < 8192) > 4 * 65536
+    for k in (1, 10):
+        seeds, gains = eng.max_coverage(n, _dev(off, torch.int64), _dev(nodes, torch.int32), k)
+        ws, wg = oracle.greedy(n, off, nodes, k)
+        assert np.array_equal(seeds, ws) and np.array_equal(gains, wg), k
+
+
 @pytest.mark.parametrize("k", [1, 2, 5])
 def test_max_coverage_empty_collection(eng, k):
     # no sets: every gain is 0 and the tie rule takes the lowest unselected ids
