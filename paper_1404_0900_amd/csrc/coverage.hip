@@ -180,9 +180,11 @@ constexpr int kHistTileSets = 256;  // sets per tile of the counts pass (at most
 static_assert(kTileSets <= kThreads && kHistTileSets <= kThreads, "a tile's sets are carried one per thread");
 constexpr int kTileEntries = 2048;  // entries per tile (flat histogram)
 
-__device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert) {
+// lg: the table's size in use, 2^lg <= kAgg slots.
+__device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert, int lg = kAggLog) {
   const uint32_t key = u + 1u;
-  uint32_t pos = (u * 0x9E3779B1u) >> (32 - kAggLog);
+  const uint32_t mask = (1u << lg) - 1u;
+  uint32_t pos = (u * 0x9E3779B1u) >> (32 - lg);
   for (int i = 0; i < kAggProbes; ++i) {
     const uint32_t cur = keys[pos];
     if (cur == key) return (int)pos;
@@ -191,15 +193,16 @@ __device__ __forceinline__ int agg_slot(uint32_t* keys, uint32_t u, bool insert)
       const uint32_t old = atomicCAS(&keys[pos], 0u, key);
       if (old == 0u || old == key) return (int)pos;
     }
-    pos = (pos + 1u) & (kAgg - 1u);
+    pos = (pos + 1u) & mask;
   }
   return -1;
 }
 
-__device__ __forceinline__ void agg_clear(uint32_t* a, uint32_t* b) {
+// Clears the first `slots` (a multiple of 4) slots of a table.
+__device__ __forceinline__ void agg_clear(uint32_t* a, uint32_t* b, int slots = kAgg) {
   uint4* a4 = reinterpret_cast<uint4*>(a);
   uint4* b4 = reinterpret_cast<uint4*>(b);
-  for (int i = threadIdx.x; i < kAgg / 4; i += blockDim.x) {
+  for (int i = threadIdx.x; i < slots / 4; i += blockDim.x) {
     a4[i] = make_uint4(0u, 0u, 0u, 0u);
     if (b) b4[i] = make_uint4(0u, 0u, 0u, 0u);
   }
@@ -259,26 +262,36 @@ constexpr int64_t kAggMin = 1;
 
 // Adds (sign +1) or subtracts the memberships of the tile's listed sets (prefix
 // from tile_prefix) to cnt, skipping node `skip`.
+// The table in use for a tile of `tot` entries: at least twice as many slots
+// as entries (256 to kAgg), so that a tile of few entries, as most tiles of
+// the cover pass are, clears and scans few slots.
+__device__ __forceinline__ int agg_log_for(int64_t tot) {
+  int lg = 8;
+  while (lg < kAggLog && (int64_t(1) << lg) < 2 * tot) ++lg;
+  return lg;
+}
+
 template <bool kAdd, int TS = kTileSets>
 __device__ __forceinline__ void tile_apply(const int32_t* nodes, TileShared<TS>& t, int64_t skip, uint32_t* cnt) {
   const int64_t tot = t.pre[TS];
   const bool agg = tot >= kAggMin;
+  const int lg = agg_log_for(tot);
   if (agg) {
-    agg_clear(t.key, t.cnt);
+    agg_clear(t.key, t.cnt, 1 << lg);
     __syncthreads();
   }
   for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
     const int j = tile_set_of(t.pre, TS, e);
     const int32_t u = nodes[t.start[j] + (e - t.pre[j])];
     if (u == skip) continue;
-    const int slot = agg ? agg_slot(t.key, (uint32_t)u, true) : -1;
+    const int slot = agg ? agg_slot(t.key, (uint32_t)u, true, lg) : -1;
     if (slot >= 0) atomicAdd(&t.cnt[slot], 1u);
     else if (kAdd) atomicAdd(&cnt[u], 1u);
     else atomicSub(&cnt[u], 1u);
   }
   if (agg) {
     __syncthreads();
-    for (int i = threadIdx.x; i < kAgg; i += kThreads) {
+    for (int i = threadIdx.x; i < (1 << lg); i += kThreads) {
       if (t.key[i]) {
         if (kAdd) atomicAdd(&cnt[t.key[i] - 1u], t.cnt[i]);
         else atomicSub(&cnt[t.key[i] - 1u], t.cnt[i]);
