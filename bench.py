@@ -387,6 +387,16 @@ def sampler_by_mode(prof, model):
     return out
 
 
+def profiled_kernel_ms(prof):
+    """Kernel time a tim_profile holds: every IC and LT sampler launch (all tiers), the index builds
+    and the greedy runs. Of a sequential run it is the GPU's busy time, which no batching can beat
+    unless its launches themselves run faster."""
+    ms = sum(prof.sampler[a][b].kernel_ms + prof.sampler[a][b].large_ms for a in (0, 1) for b in (0, 1, 2))
+    ms += sum(prof.ic_wide[b].kernel_ms + prof.ic_wide[b].large_ms for b in (0, 1, 2))
+    ms += sum(prof.grouped[a].kernel_ms + prof.grouped[a].large_ms for a in (0, 1))
+    return ms + prof.index_ms + prof.greedy_ms
+
+
 def dominant_roofline(prof, name_of, traffic_of=lambda model, mode: None):
     """Roofline object of the sampler kernel with the most event time in a profile."""
     best = None
@@ -499,6 +509,11 @@ def batch_measure(steps, warmup):
             f"identical={identical}")
     ts, tb = statistics.median(t_seq), statistics.median(t_bat)
 
+    # the queries one by one once more with per-launch timing: the GPU's busy time of the sequential run
+    eng.profile(True)
+    sequential()
+    seq_kernel_ms = profiled_kernel_ms(eng.read_profile())
+    eng.profile(False)
     # one more batch with per-launch timing, for the roofline of the dominant batched kernel
     eng.profile(True)
     eng.run_batch(batch)
@@ -514,7 +529,8 @@ def batch_measure(steps, warmup):
                    "avg_degree_range": [4, 40], "ic_p": list(synth.TRIVALENCY_P), "k_range": [1, 50],
                    "eps": [0.1, 0.2, 0.5], "ell": 1.0, "seeds": "1000+j",
                    "edges_total": int(sum(g.m for g, _ in graphs))},
-        "sequential": {"value": round(64 / ts, 3), "unit": "queries/s", "ms_per_step": round(ts * 1e3, 3)},
+        "sequential": {"value": round(64 / ts, 3), "unit": "queries/s", "ms_per_step": round(ts * 1e3, 3),
+                       "kernel_ms": round(seq_kernel_ms, 3)},
         "speedup_vs_sequential": round(ts / tb, 3),
         "identical_outputs": identical,
         "device_kpt": {"ms": round(info.ms_kpt, 3), "steps": int(info.kpt_steps),
@@ -590,6 +606,13 @@ def serve_main(args):
             rep.select.theta == r[3].select.theta and rep.refine.kpt_plus == r[3].refine.kpt_plus
     plain = time.perf_counter() - t0
     log(f"plain: {len(qs)} queries one by one in {plain:.3f} s, identical={identical}")
+    # once more with per-launch timing: the GPU's busy time of the plain run
+    eng.profile(True)
+    for q in qs:
+        eng.run(dgs[q["graph"]], q["model"], q["k"], q["eps"], q["ell"], q["seed"])
+    plain_kernel_s = profiled_kernel_ms(eng.read_profile()) * 1e-3
+    eng.profile(False)
+    log(f"plain: kernel time {plain_kernel_s:.3f} s")
     top = sweep[-1]
     line = {
         "metric": "served TIM+ queries/s at 200 Poisson arrivals/s (1 GPU, continuous batching), p50/p99 latency",
@@ -610,7 +633,9 @@ def serve_main(args):
         "p50_ms": top["p50_ms"],
         "p99_ms": top["p99_ms"],
         "sweep": sweep,
-        "plain": {"value": round(len(qs) / plain, 3), "unit": "queries/s", "queries": len(qs)},
+        "plain": {"value": round(len(qs) / plain, 3), "unit": "queries/s", "queries": len(qs),
+                  "seconds": round(plain, 3), "kernel_s": round(plain_kernel_s, 3),
+                  "kernel_bound_queries_per_s": round(len(qs) / plain_kernel_s, 3)},
         "identical_outputs": identical,
     }
     eng.close()

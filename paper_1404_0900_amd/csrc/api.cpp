@@ -1249,7 +1249,7 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
         continue;
       }
     }
-    bool stored = false;
+    bool stored = false, counted = false;  // counted: the emit summed the round's widths and kappa
     if (predicted) {
       const uint64_t expect = (uint64_t)((double)prev_nodes / (double)prev_c * 1.25 * (double)ci) + 4096;
       uint64_t room = 0;
@@ -1262,7 +1262,13 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
         c->emit_kappa_k = k;
         const tim_status es = emit_sets(c, g, model, seed, (uint32_t)i, 0, ci, expect, nullptr, &t);
         if (es == TIM_OK) {
-          stored = true;
+          // the sets may have come out larger than estimated: their actual size decides whether
+          // RefineKPT's index fits beside them (if not, RefineKPT generates R' again)
+          uint64_t room2 = 0;
+          TIM_TRY(collection_room(c, &room2));
+          stored = resident_bytes(c, g->n, model, ci, t.nodes, k) <= room2;
+          counted = true;
+          if (!stored) release_transients(c);
         } else if (es == TIM_EBUDGET) {
           // the round's sets came out larger than estimated: sum its widths instead (RefineKPT
           // generates R' again from its keys, with the same sets)
@@ -1273,7 +1279,7 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
         }
       }
     }
-    if (!stored)
+    if (!counted)
       TIM_TRY(sample_counts(c, g, model, tim::kModeWidth, seed, (uint32_t)i, 0, ci, k, nullptr, nullptr, &t));
     if (finish(i, ci, t, stored)) break;
     ++i;
@@ -1289,15 +1295,21 @@ tim_status refine_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed,
   // the node pool when KptEstimation kept them, else generated again
   CollectionStats cs;
   const tim_ctx::Stored& kept = c->stored;
+  bool done = false;
   if (c_last > 0 && kept.valid && kept.graph == g && kept.model == model && kept.seed == seed &&
       kept.phase == (uint32_t)i_last && kept.count == c_last) {
-    TIM_TRY(greedy(c, g->n, c_last, nullptr, c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
-                   c->pool.as<int32_t>(), kept.nodes, k, s_prime, nullptr));
-  } else if (c_last > 0) {
+    const tim_status gs = greedy(c, g->n, c_last, nullptr, c->set_start.as<uint64_t>(), c->set_len.as<uint32_t>(),
+                                 c->pool.as<int32_t>(), kept.nodes, k, s_prime, nullptr);
+    if (gs != TIM_OK && gs != TIM_EBUDGET && gs != TIM_ENOMEM) return gs;
+    done = gs == TIM_OK;
+    // no room for the index beside the kept sets: R' again from its keys (the same sets), fitted to the budget
+    if (!done) release_transients(c);
+  }
+  if (!done && c_last > 0) {
     TIM_TRY(collection_greedy(c, g, model, seed, (uint32_t)i_last, c_last, k, expect_nodes, s_prime, nullptr, &cs));
     if (sets) *sets += c_last;
     if (width) *width += cs.width;
-  } else {
+  } else if (c_last == 0) {
     for (int j = 0; j < k; ++j) s_prime[j] = j;
   }
   c->stored.valid = false;

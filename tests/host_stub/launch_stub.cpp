@@ -25,11 +25,34 @@ uint64_t mix(uint64_t x) {
   return x ^ (x >> 31);
 }
 
-// A stand-in set of 1-3 distinct nodes and its width.
+// Most nodes of a stand-in set.
+constexpr int kStubMaxSet = 256;
+
+// With TIM_STUB_GROWTH=1 the sets of KptEstimation round i have up to 2^i
+// nodes (at most kStubMaxSet), so that each round's sets are about twice the
+// size of the previous round's; otherwise every set has 1-3 nodes.
+int stand_in_cap(uint32_t phase) {
+  static const bool growth = [] {
+    const char* e = getenv("TIM_STUB_GROWTH");
+    return e && e[0] == '1';
+  }();
+  if (!growth || phase < 1 || phase > 62) return 3;
+  return phase >= 8 ? kStubMaxSet : std::max(3, 1 << phase);
+}
+
+// A stand-in set of distinct nodes and its width.
 int stand_in_set(const SampleArgs& a, uint64_t id, int32_t* nodes, uint64_t* width) {
   const uint64_t h = mix(a.seed ^ ((uint64_t)a.phase << 40) ^ mix(id));
-  int len = 1 + (int)(h % 3);
+  const int cap = stand_in_cap(a.phase);
+  int len = 1 + (int)(h % (uint64_t)cap);
   if (len > a.g.n) len = (int)a.g.n;
+  *width = std::min<uint64_t>((uint64_t)a.g.m, 1 + (h >> 16) % 12);
+  if (cap > 3) {
+    // consecutive node ids from a random start: distinct while len <= n
+    const uint64_t start = mix(h) % (uint64_t)a.g.n;
+    for (int j = 0; j < len; ++j) nodes[j] = (int32_t)((start + (uint64_t)j) % (uint64_t)a.g.n);
+    return len;
+  }
   int got = 0;
   for (int j = 0; got < len && j < 16; ++j) {
     const int32_t v = (int32_t)(mix(h + (uint64_t)j) % (uint64_t)a.g.n);
@@ -37,7 +60,6 @@ int stand_in_set(const SampleArgs& a, uint64_t id, int32_t* nodes, uint64_t* wid
     for (int t = 0; t < got; ++t) dup = dup || nodes[t] == v;
     if (!dup) nodes[got++] = v;
   }
-  *width = std::min<uint64_t>((uint64_t)a.g.m, 1 + (h >> 16) % 12);
   return got;
 }
 
@@ -56,7 +78,7 @@ void run_sample(int model, int mode, const SampleArgs& a) {
   unsigned long long* c = a.ctr;
   unsigned long long* acc = c + kCtrAcc;
   u128 kap = 0;
-  int32_t nodes[4];
+  int32_t nodes[kStubMaxSet];
   for (uint64_t i = 0; i < a.count; ++i) {
     uint64_t w = 0;
     const int len = stand_in_set(a, a.first + i, nodes, &w);

@@ -1,0 +1,33 @@
+"""Device-memory budgets on the host side of tim_run (api.cpp built on the CPU against the stand-in
+runtime and kernels of tests/host_stub): the same queries on contexts with budgets from a geometric
+sweep.  More memory must never turn a success into a failure, and every success must give the results
+of the run without a budget.
+
+The stand-in sets grow with the KptEstimation round (TIM_STUB_GROWTH=1), so that the round kept in
+device memory for RefineKPT (R' of Algorithm 3) comes out larger than the previous round predicts.
+RefineKPT then has to fall back to generating R' again from its keys where the inverted index does
+not fit beside the kept sets."""
+import os
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+CLANG = "/opt/rocm/llvm/bin/clang++"
+SOURCES = ["paper_1404_0900_amd/csrc/api.cpp", "tests/host_stub/hip_stub.cpp", "tests/host_stub/launch_stub.cpp",
+           "tests/host_stub/budget_driver.cpp"]
+
+
+@pytest.mark.skipif(not os.path.exists(CLANG), reason="clang++ of the ROCm toolchain not found")
+def test_larger_budgets_never_fail(tmp_path):
+    exe = str(tmp_path / "budget_driver")
+    cmd = [CLANG, "-std=c++17", "-O2", "-I", "tests/host_stub", "-I", "include", "-I", "paper_1404_0900_amd/csrc",
+           *SOURCES, "-o", exe, "-lpthread"]
+    subprocess.run(cmd, cwd=ROOT, check=True, capture_output=True, text=True)
+    # budgets from 256 KiB to 256 MiB in steps of 1.2x
+    p = subprocess.run([exe, str(1 << 18), str(1 << 28), "1.2"], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, TIM_STUB_GROWTH="1"))
+    out = p.stdout + p.stderr
+    assert p.returncode == 0 and out.rstrip().endswith("done"), out[-4000:]
+    # the sweep spans the budgets too small for any query and those that run every one
+    assert ": 0 of 4 ok" in out and ": 4 of 4 ok, 0 differ" in out, out[-4000:]
