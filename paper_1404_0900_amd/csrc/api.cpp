@@ -318,6 +318,7 @@ struct Hub {
 // the whole pool and runs its collection in regenerated chunks (A10).  The
 // member's budget is its share plus the grant while NodeSelection runs.
 void release_transients(tim_ctx* c);
+uint64_t transient_bytes(tim_ctx* c);
 
 uint64_t hub_admit(tim_ctx* c, uint64_t need) {
   Hub* h = c->hub;
@@ -569,9 +570,23 @@ uint64_t launch_cap(const tim_ctx* c) {
   return std::max<uint64_t>(4096, std::min<uint64_t>(kMaxLaunchSets, room / 4 / 20));
 }
 
+// Width and coverage passes keep nothing in the node pool or the index, and a
+// round kept for RefineKPT is only a shortcut (its flag falls with it).  On a
+// budget, the buffers that earlier steps or queries left are released before
+// such a pass when they would hold its launches (launch_cap) below 2^20 sets,
+// or below `count` if fewer; kept buffers that leave more room stay for reuse.
+void room_for_counts(tim_ctx* c, uint64_t count) {
+  if (!c->budget) return;
+  const uint64_t want = 4 * 20 * std::min<uint64_t>(count, 1ull << 20);
+  const uint64_t own = c->list1.bytes + c->list2.bytes + c->wbuf.bytes;
+  const uint64_t room = c->budget > c->held ? c->budget - c->held : 0;
+  if (room + own < want && transient_bytes(c) > own) release_transients(c);
+}
+
 // Width or coverage mode over any number of sets, in launches of bounded size.
 tim_status sample_counts(tim_ctx* c, const tim_graph* g, int model, int mode, uint64_t seed, uint32_t phase,
                          uint64_t first, uint64_t count, int k, uint64_t* widths, uint32_t* sizes, Totals* t) {
+  room_for_counts(c, count);
   const uint64_t cap = launch_cap(c);
   for (uint64_t done = 0; done < count;) {
     const uint64_t part = std::min(count - done, cap);
@@ -1071,6 +1086,7 @@ tim_status sample_rounds(tim_ctx* c, const tim_graph* g, int model, uint64_t see
     total += cnt[(size_t)r];
     maxc = std::max(maxc, cnt[(size_t)r]);
   }
+  room_for_counts(c, total);
   if (model == TIM_MODEL_IC) TIM_TRY(ensure_big(c, g->n));
   TIM_TRY(ensure(c, c->list1, total * 8, "deferred-set list"));
   if (model == TIM_MODEL_IC) TIM_TRY(ensure(c, c->list2, total * 8, "deferred-set list"));
@@ -1176,6 +1192,7 @@ tim_status kpt_estimate_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t
   out->i_max = imax;
   out->i_last = imax;
   out->c_last = imax >= 1 ? round_size(g->n, ell, imax) : 0;
+  room_for_counts(c, out->c_last);  // room for the largest round's launches
   out->kpt_star = 1.0;
   u128 prev_sum = 0;
   uint64_t prev_c = 0, prev_nodes = 0;

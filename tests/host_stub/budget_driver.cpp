@@ -10,6 +10,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <random>
+#include <string>
 #include <vector>
 
 #include "tim.h"
@@ -98,7 +99,7 @@ std::vector<Result> run_all(uint64_t budget, const std::vector<Csr>& gs, const s
     memset(&r.rep, 0, sizeof(r.rep));
     r.st = tim_run(ctx, dg[(size_t)q.graph], q.model, q.k, q.eps, 1.0, q.seed, 0, r.seeds.data(), r.gains.data(),
                    &r.rep);
-    if (r.st != TIM_OK && errors) errors->push_back(tim_last_error());
+    if (r.st != TIM_OK && errors) errors->push_back("query " + std::to_string(i) + ": " + tim_last_error());
   }
   for (tim_graph* h : dg) tim_graph_free(h);
   tim_ctx_destroy(ctx);

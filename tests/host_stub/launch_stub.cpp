@@ -26,18 +26,21 @@ uint64_t mix(uint64_t x) {
 }
 
 // Most nodes of a stand-in set.
-constexpr int kStubMaxSet = 256;
+constexpr int kStubMaxSet = 512;
 
 // With TIM_STUB_GROWTH=1 the sets of KptEstimation round i have up to 2^i
-// nodes (at most kStubMaxSet), so that each round's sets are about twice the
-// size of the previous round's; otherwise every set has 1-3 nodes.
+// nodes (at most 256), so that each round's sets are about twice the size of
+// the previous round's; with TIM_STUB_GROWTH=2 the sets of RefineKPT and
+// NodeSelection have up to 512 nodes besides.  Otherwise every set has 1-3
+// nodes.
 int stand_in_cap(uint32_t phase) {
-  static const bool growth = [] {
+  static const int growth = [] {
     const char* e = getenv("TIM_STUB_GROWTH");
-    return e && e[0] == '1';
+    return e ? atoi(e) : 0;
   }();
-  if (!growth || phase < 1 || phase > 62) return 3;
-  return phase >= 8 ? kStubMaxSet : std::max(3, 1 << phase);
+  if (growth >= 2 && phase > 62) return kStubMaxSet;
+  if (growth < 1 || phase < 1 || phase > 62) return 3;
+  return phase >= 8 ? 256 : std::max(3, 1 << phase);
 }
 
 // A stand-in set of distinct nodes and its width.
