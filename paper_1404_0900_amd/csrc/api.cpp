@@ -1731,10 +1731,18 @@ void hub_free_slots(Hub* h) {
 // context itself holds (without a budget: 85% of the device memory that is
 // free or already held by the hub and its members); the last-tier slots for
 // the largest graph come first (one per CU where a quarter of it allows),
-// and every query running at once gets an equal share of the rest.
+// and every query running at once gets an equal share of the rest.  Under a
+// budget, the work buffers and last-tier slots that the context's own calls
+// left are released first: the batch's members and hub have their own.
 tim_status hub_prepare(Hub* h, tim_ctx* parent, int64_t maxn, int workers) {
   uint64_t limit = 0;
   if (parent->budget) {
+    release_transients(parent);
+    release(parent, parent->big_stamp);
+    release(parent, parent->big_queue);
+    release(parent, parent->big_epoch);
+    parent->big_slots = 0;
+    parent->big_n = -1;
     limit = parent->budget > parent->held ? parent->budget - parent->held : 0;
   } else {
     size_t free_b = 0, total_b = 0;

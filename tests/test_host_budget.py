@@ -34,3 +34,19 @@ def test_larger_budgets_never_fail(tmp_path, growth):
     assert p.returncode == 0 and out.rstrip().endswith("done"), out[-4000:]
     # the sweep spans the budgets too small for any query and those that run every one
     assert ": 0 of 4 ok" in out and ": 4 of 4 ok, 0 differ" in out, out[-4000:]
+
+
+@pytest.mark.skipif(not os.path.exists(CLANG), reason="clang++ of the ROCm toolchain not found")
+def test_batch_and_server_under_budget_after_queries_alone(tmp_path):
+    """A batch and a server on a context whose own queries (run alone first, with the larger stand-in
+    sets of growth mode 2) left their work buffers behind: a 150 MB budget holds 12 queries at once
+    only if those buffers make room, and every batched or served query must equal its run alone."""
+    exe = str(tmp_path / "driver")
+    cmd = [CLANG, "-std=c++17", "-O2", "-I", "tests/host_stub", "-I", "include", "-I", "paper_1404_0900_amd/csrc",
+           "paper_1404_0900_amd/csrc/api.cpp", "tests/host_stub/hip_stub.cpp", "tests/host_stub/launch_stub.cpp",
+           "tests/host_stub/driver.cpp", "-o", exe, "-lpthread"]
+    subprocess.run(cmd, cwd=ROOT, check=True, capture_output=True, text=True)
+    p = subprocess.run([exe, "1", str(150_000_000), "12"], capture_output=True, text=True, timeout=600,
+                       env=dict(os.environ, TIM_STUB_GROWTH="2", TIM_RR_POOL_BYTES=str(4 << 20)))
+    out = p.stdout + p.stderr
+    assert p.returncode == 0 and "round 0: batch and server ok" in out, out[-4000:]
