@@ -312,12 +312,12 @@ tim_status tim_sample_widths(tim_ctx *ctx, const tim_graph *g, int model, uint64
 
 /* Generates sets [first, first+count) of (seed, phase) and counts those that
  * contain at least one of the nodes seeds[0..nseeds) (host int32), as in
- * Algorithm 3 lines 9-10.  The count is in stats->covered. */
+ * Algorithm 3's test of fresh sets against S'_k.  The count is in stats->covered. */
 tim_status tim_sample_cover(tim_ctx *ctx, const tim_graph *g, int model, uint64_t seed, uint32_t phase,
                             uint64_t first, uint64_t count, const int32_t *seeds, int nseeds,
                             tim_batch_stats *stats);
 
-/* ---- greedy maximum coverage (Algorithm 1 lines 3-7) -------------------- */
+/* ---- greedy maximum coverage (Algorithm 1) ------------------------------ */
 
 /* Runs the greedy on a caller-supplied collection of nsets sets over nodes
  * [0, n) (d_set_off device int64[nsets+1], d_nodes device int32; sets must not

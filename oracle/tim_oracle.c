@@ -17,7 +17,7 @@
  *     LT-as-triggering description of Section 7.1);
  *   - width w(R): Equation (1);  kappa(R): Equation (8), Lemma 5;
  *   - KptEstimation: Algorithm 2, with c_i from Equation (9);
- *   - greedy maximum coverage: Algorithm 1 lines 3-7 / Algorithm 3 lines 2-6;
+ *   - greedy maximum coverage: Algorithm 1, and its use on R' in Algorithm 3;
  *   - RefineKPT: Algorithm 3 with the epsilon' of Section 4.1;
  *   - lambda: Equation (4);  TIM: Section 3.3;  TIM+: Section 4.1.
  *
@@ -380,7 +380,7 @@ uint64_t orc_c_i(int64_t n, double ell, int i) {
 }
 
 /* ------------------------------------------------------------------------- */
-/* Greedy maximum coverage (Algorithm 1 lines 3-7; Algorithm 3 lines 2-6).   */
+/* Greedy maximum coverage (Algorithm 1; the greedy on R' in Algorithm 3).   */
 /* ------------------------------------------------------------------------- */
 
 int orc_greedy(int64_t n, uint64_t nsets, const int64_t *set_off, const int32_t *set_nodes, int k, int32_t *seeds,
@@ -451,9 +451,9 @@ static int valid_graph(const orc_graph *g) {
   return 1;
 }
 
-/* One round of Algorithm 2 (lines 3-7): sets [first, first+count) of phase
- * `phase`, the exact sum of kappa(R) * 2^53 (Equation (8)) and the widths and
- * sizes of the sets. */
+/* One round of Algorithm 2 (its c_i sets and their kappa sum): sets
+ * [first, first+count) of phase `phase`, the exact sum of kappa(R) * 2^53
+ * (Equation (8)) and the widths and sizes of the sets. */
 static void round_sum(const orc_graph *g, int model, uint64_t seed, uint32_t phase, uint64_t first, uint64_t count,
                       int k, orc_ws *w, u128 *sum, uint64_t *wsum, uint64_t *nsum) {
   *sum = 0;
@@ -554,7 +554,7 @@ int orc_refine_kpt(int64_t n, int64_t m, const int64_t *off, const int32_t *src,
                    int32_t *s_prime, orc_report *rep) {
   orc_graph g = {n, m, off, src, thr};
   if (!valid_graph(&g) || k < 1 || k > n || !(eps > 0.0 && eps <= 1.0)) return -1;
-  /* lines 1-6: greedy on the sets of the last round of Algorithm 2 */
+  /* S'_k: greedy on the sets of the last round of Algorithm 2 */
   int64_t *so = NULL;
   int32_t *nodes = NULL;
   int rc = collect_sets(&g, model, seed, (uint32_t)i_last, c_last, &so, &nodes, NULL);
@@ -564,7 +564,7 @@ int orc_refine_kpt(int64_t n, int64_t m, const int64_t *off, const int32_t *src,
   rc = orc_greedy(n, c_last, so, nodes, k, s_prime, gains);
   free(so); free(nodes); free(gains);
   if (rc) return rc;
-  /* lines 7-10: fresh sets, fraction covered by S'_k */
+  /* eps', lambda', theta': fresh sets, fraction covered by S'_k */
   double eps_p = orc_eps_prime(k, eps, ell);
   double lambda_p = orc_lambda_prime(n, eps_p, ell);
   uint64_t theta_p = (uint64_t)ceil(lambda_p / kpt_star);
@@ -581,7 +581,7 @@ int orc_refine_kpt(int64_t n, int64_t m, const int64_t *off, const int32_t *src,
     }
   }
   free(in_s); ws_free(w);
-  /* lines 11-13 */
+  /* KPT' from that fraction, and KPT+ */
   double f = (double)hit / (double)theta_p;
   double kpt_p = f * (double)n / (1.0 + eps_p);
   rep->eps_prime = eps_p;

@@ -90,7 +90,7 @@ struct tim_ctx {
   uint32_t slice = tim::kPoolChunk;      // slice of the current emit launches
   uint64_t resident_limit = ~0ull;       // most sets a greedy keeps resident
   int emit_kappa_k = 0;                  // emit launches also sum kappa(R) for this k (0: no)
-  // the node pool holds the sets of one KptEstimation round (Algorithm 3, line 1 reuses them)
+  // the node pool holds the sets of one KptEstimation round (Algorithm 3 reuses them as R')
   struct Stored {
     bool valid = false;
     const void* graph = nullptr;
@@ -820,7 +820,7 @@ tim_status for_chunks(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, 
 }
 
 // Sets of phase `phase` with ids [0, count): the greedy of Algorithm 1
-// (lines 3-7) on them, keeping as many as the budget allows resident.
+// on them, keeping as many as the budget allows resident.
 // expect_nodes estimates their total size.
 tim_status collection_greedy(tim_ctx* c, const tim_graph* g, int model, uint64_t seed, uint32_t phase,
                              uint64_t count, int k, uint64_t expect_nodes, int32_t* seeds, uint64_t* gains,
@@ -1308,7 +1308,7 @@ tim_status refine_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed,
                        double kpt_star, int i_last, uint64_t c_last, uint64_t expect_nodes, int32_t* s_prime,
                        tim_refine_result* out, uint64_t* sets, uint64_t* width) {
   memset(out, 0, sizeof(*out));
-  // lines 1-6: greedy on the sets of the last round of Algorithm 2 - still in
+  // S'_k: greedy on the sets of the last round of Algorithm 2 - still in
   // the node pool when KptEstimation kept them, else generated again
   CollectionStats cs;
   const tim_ctx::Stored& kept = c->stored;
@@ -1330,7 +1330,7 @@ tim_status refine_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed,
     for (int j = 0; j < k; ++j) s_prime[j] = j;
   }
   c->stored.valid = false;
-  // lines 7-10
+  // eps', lambda', theta': fresh sets and the fraction that meets S'_k
   const double nd = (double)g->n;
   const double eps_p = 5.0 * std::cbrt(ell * eps * eps / ((double)k + ell));
   const double lambda_p = ((2.0 + eps_p) * ell * nd * std::log(nd)) / (eps_p * eps_p);
@@ -1339,7 +1339,7 @@ tim_status refine_impl(tim_ctx* c, const tim_graph* g, int model, uint64_t seed,
   Totals tc;
   TIM_TRY(sample_counts(c, g, model, tim::kModeCover, seed, TIM_PHASE_REFINE, 0, theta_p, 0, nullptr, nullptr, &tc));
   if (sets) *sets += theta_p;
-  // lines 11-13
+  // KPT' from that fraction, and KPT+
   const double f = (double)tc.covered / (double)theta_p;
   const double kpt_p = f * nd / (1.0 + eps_p);
   out->eps_prime = eps_p;

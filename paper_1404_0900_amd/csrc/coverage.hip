@@ -4,7 +4,7 @@
 // the samplers into a flat CSR of sets in set-id order.  A counting sort of
 // that CSR (histogram, scan, scatter) builds the node -> sets inverted index;
 // its histogram is also the initial coverage count of every node.  The greedy
-// of Algorithm 1 (lines 3-7) then runs on the device without host round
+// of Algorithm 1 then runs on the device without host round
 // trips: per step one argmax kernel packs (count, ~id) into a 64-bit key so
 // that a single atomicMax selects the largest count with ties to the lowest
 // id, and one cover kernel marks the chosen node's uncovered sets and

@@ -11,7 +11,7 @@ namespace tim {
 enum SampleMode : int {
   kModeWidth = 0,  // w(R), |R| and kappa(R) only (Algorithm 2)
   kModeEmit = 1,   // store the nodes of R (Algorithms 1 and 3)
-  kModeCover = 2   // does R meet a seed set? (Algorithm 3, lines 9-10)
+  kModeCover = 2   // does R meet a seed set? (Algorithm 3, RefineKPT's test)
 };
 
 // Device counters of one sampling launch (zeroed before it).  Sets flow

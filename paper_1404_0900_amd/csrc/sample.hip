@@ -26,7 +26,7 @@
 // cycle search over the walk, which is a fixed function of the set's keys).
 //
 // Every launch also reduces what the phase needs: the widths (Equation (1)),
-// the set sizes, the number of sets meeting a seed set (Algorithm 3, line 10)
+// the set sizes, the number of sets meeting a seed set (Algorithm 3, RefineKPT's test)
 // and, in width mode, the exact 128-bit sum of kappa(R) * 2^53 (Equation (8)),
 // computed by a separate pass over the widths so that the binary64 kappa
 // arithmetic runs one set per lane instead of inside the traversal loop.
