@@ -12,7 +12,7 @@
  *
  * What is computed, and where the paper defines it:
  *   - random RR set: Definitions 1-2 (Section 2.3); built by the randomized
- *     reverse BFS of Section 3.1 ("Implementation") for IC and by the
+ *     reverse BFS of Section 3.1 (its implementation paragraph) for IC and by the
  *     triggering-set BFS of Section 4.2 for LT (one in-edge per node, the
  *     LT-as-triggering description of Section 7.1);
  *   - width w(R): Equation (1);  kappa(R): Equation (8), Lemma 5;
