@@ -1,0 +1,68 @@
+"""TIM+ end to end against the oracle on seeded random small cases: graph size and density, the
+model (IC with weighted cascade or per-edge trivalency probabilities, LT), k, eps and ell are drawn
+per case, so that the runs stop in different KptEstimation rounds (from the first to the last),
+keep or regenerate R', and take theta from KPT* or KPT'.  Seeds, gains and every scalar of
+Algorithms 1-3 must match the oracle exactly."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+
+pytestmark = pytest.mark.gpu
+
+KEYS = ("ell_used", "lambda", "i_max", "i_last", "c_last", "kpt_star", "round_sums", "theta", "ns_nodes", "ns_width",
+        "ns_covered", "eps_prime", "lambda_prime", "theta_prime", "covered_prime", "kpt_prime", "kpt_plus")
+
+
+def _case(cs):
+    r = np.random.default_rng(1000 + cs)
+    n = int(r.integers(30, 5000))
+    m = int(min(n * (n - 1), n * r.uniform(1.5, 12.0)))
+    model = int(r.integers(0, 2))
+    k = int(r.integers(1, min(n, 40) + 1))
+    eps = float(r.choice([0.4, 0.5, 0.7, 1.0]))
+    ell = float(r.choice([0.5, 1.0, 2.0]))
+    use_thr = model == 0 and bool(r.integers(0, 2))
+    return n, m, model, k, eps, ell, use_thr
+
+
+def _graph(n, m, seed):
+    # m distinct random edges u -> v, u != v
+    r = np.random.default_rng(seed)
+    u = r.integers(0, n, size=3 * m + 16)
+    v = r.integers(0, n, size=3 * m + 16)
+    keep = u != v
+    u, v = u[keep], v[keep]
+    _, first = np.unique(u.astype(np.int64) * n + v, return_index=True)
+    pick = np.sort(first)[:m]
+    return synth.from_edges(n, [(int(a), int(b)) for a, b in zip(u[pick], v[pick])], name=f"rand_n{n}_s{seed}")
+
+
+@pytest.fixture(scope="module")
+def eng():
+    import paper_1404_0900_amd as tim
+    e = tim.Engine(0)
+    yield e
+    e.close()
+
+
+@pytest.mark.parametrize("cs", range(24))
+def test_tim_plus_random_case_equals_oracle(eng, cs):
+    import paper_1404_0900_amd as tim
+    n, m, model, k, eps, ell, use_thr = _case(cs)
+    print(f"case {cs}: n={n} m={m} model={model} k={k} eps={eps} ell={ell} thresholds={use_thr}", file=sys.stderr,
+          flush=True)
+    g = _graph(n, m, cs)
+    thr = synth.random_thresholds(g.m, cs, [synth.threshold_of(p) for p in synth.TRIVALENCY_P]) if use_thr else None
+    seed = 77 + cs
+    seeds, gains, rep = eng.run(eng.upload(g, thr=thr), model, k, eps, ell, seed)
+    got = tim.report_dict(rep, k)
+    want = oracle.tim_run(g, model, k, eps, ell, seed, thr=thr)
+    assert np.array_equal(seeds, want["seeds"])
+    assert np.array_equal(gains, want["gains"])
+    for key in KEYS:
+        assert got[key] == want[key], key
+    assert np.array_equal(got["s_prime"], want["s_prime"][:128])
