@@ -66,3 +66,35 @@ def test_tim_plus_random_case_equals_oracle(eng, cs):
     for key in KEYS:
         assert got[key] == want[key], key
     assert np.array_equal(got["s_prime"], want["s_prime"][:128])
+
+
+def _check_equal(seeds, gains, rep, k, want):
+    import paper_1404_0900_amd as tim
+    got = tim.report_dict(rep, k)
+    assert np.array_equal(seeds, want["seeds"])
+    assert np.array_equal(gains, want["gains"])
+    for key in KEYS:
+        assert got[key] == want[key], key
+
+
+@pytest.mark.parametrize("concurrent", [5, 0])
+def test_random_cases_as_one_batch_and_served(eng, concurrent):
+    """The 24 cases as one batch (5 at a time, or all at once), then through a server with 6 slots:
+    every query equals the oracle."""
+    cases = [_case(cs) for cs in range(24)]
+    graphs, thrs, wants, queries = [], [], [], []
+    for cs, (n, m, model, k, eps, ell, use_thr) in enumerate(cases):
+        g = _graph(n, m, cs)
+        thr = synth.random_thresholds(g.m, cs, [synth.threshold_of(p) for p in synth.TRIVALENCY_P]) if use_thr else None
+        wants.append(oracle.tim_run(g, model, k, eps, ell, 77 + cs, thr=thr))
+        queries.append((eng.upload(g, thr=thr), model, k, eps, ell, 77 + cs))
+    print(f"batch of 24 random cases, {concurrent} at a time", file=sys.stderr, flush=True)
+    res, _ = eng.run_batch(queries, max_concurrent=concurrent)
+    for (seeds, gains, rep), q, want in zip(res, queries, wants):
+        _check_equal(seeds, gains, rep, q[2], want)
+    print("server with 6 slots over the 24 random cases", file=sys.stderr, flush=True)
+    with eng.serve(6) as srv:
+        tickets = [srv.submit(*q) for q in queries]
+        got = [srv.wait(t) for t in tickets]
+    for (seeds, gains, rep, _lat), q, want in zip(got, queries, wants):
+        _check_equal(seeds, gains, rep, q[2], want)
