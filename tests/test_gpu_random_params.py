@@ -98,3 +98,29 @@ def test_random_cases_as_one_batch_and_served(eng, concurrent):
         got = [srv.wait(t) for t in tickets]
     for (seeds, gains, rep, _lat), q, want in zip(got, queries, wants):
         _check_equal(seeds, gains, rep, q[2], want)
+
+
+@pytest.mark.parametrize("cs", range(10))
+def test_triggering_random_case_equals_oracle(eng, cs):
+    """The general triggering model (Section 4.2) on seeded random graphs and random per-node
+    distributions over in-edge subsets (synth.random_triggering), with random k, eps and ell."""
+    import paper_1404_0900_amd as tim
+    r = np.random.default_rng(2000 + cs)
+    n = int(r.integers(30, 3000))
+    m = int(min(n * (n - 1), n * r.uniform(1.5, 10.0)))
+    k = int(r.integers(1, min(n, 30) + 1))
+    eps = float(r.choice([0.5, 0.7, 1.0]))
+    ell = float(r.choice([0.5, 1.0, 2.0]))
+    outcomes, size = int(r.integers(1, 6)), int(r.integers(1, 5))
+    p_full = float(r.choice([0.0, 0.25, 1.0]))
+    print(f"triggering case {cs}: n={n} m={m} k={k} eps={eps} ell={ell} outcomes<={outcomes} size<={size} "
+          f"p_full={p_full}", file=sys.stderr, flush=True)
+    g = _graph(n, m, 500 + cs)
+    trig = synth.random_triggering(g, 600 + cs, max_outcomes=outcomes, max_size=size, p_full=p_full)
+    dg = eng.upload(g)
+    eng.set_triggering(dg, g, trig)
+    seed = 91 + cs
+    seeds, gains, rep = eng.run(dg, tim.TRIGGER, k, eps, ell, seed)
+    want = oracle.tim_run(g, tim.TRIGGER, k, eps, ell, seed, thr=trig)
+    _check_equal(seeds, gains, rep, k, want)
+    eng.free(dg)
