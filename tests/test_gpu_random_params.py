@@ -124,3 +124,27 @@ def test_triggering_random_case_equals_oracle(eng, cs):
     want = oracle.tim_run(g, tim.TRIGGER, k, eps, ell, seed, thr=trig)
     _check_equal(seeds, gains, rep, k, want)
     eng.free(dg)
+
+
+@pytest.mark.parametrize("cs", range(8))
+def test_lt_weights_random_case_equals_oracle(eng, cs):
+    """LT with random in-weights (Section 7.1), normalized or summing to less than one, on seeded
+    random graphs with random k, eps and ell."""
+    import paper_1404_0900_amd as tim
+    r = np.random.default_rng(3000 + cs)
+    n = int(r.integers(30, 4000))
+    m = int(min(n * (n - 1), n * r.uniform(1.5, 12.0)))
+    k = int(r.integers(1, min(n, 40) + 1))
+    eps = float(r.choice([0.4, 0.5, 0.7, 1.0]))
+    ell = float(r.choice([0.5, 1.0, 2.0]))
+    total = [None, 0.5, 0.9][int(r.integers(0, 3))]
+    print(f"LT weights case {cs}: n={n} m={m} k={k} eps={eps} ell={ell} total={total}", file=sys.stderr, flush=True)
+    g = _graph(n, m, 700 + cs)
+    lthr = synth.random_lt_thresholds(g, 800 + cs, total=total)
+    dg = eng.upload(g)
+    eng.set_lt_weights(dg, g, lthr)
+    seed = 31 + cs
+    seeds, gains, rep = eng.run(dg, tim.LT, k, eps, ell, seed)
+    want = oracle.tim_run(g, tim.LT, k, eps, ell, seed, thr=lthr)
+    _check_equal(seeds, gains, rep, k, want)
+    eng.free(dg)
