@@ -148,3 +148,42 @@ def test_lt_weights_random_case_equals_oracle(eng, cs):
     want = oracle.tim_run(g, tim.LT, k, eps, ell, seed, thr=lthr)
     _check_equal(seeds, gains, rep, k, want)
     eng.free(dg)
+
+
+@pytest.mark.parametrize("cs", range(10))
+def test_spread_random_case_equals_oracle(eng, cs):
+    """Forward Monte-Carlo spread (the live-edge view of Section 2.2) run by run on seeded random
+    graphs: model (IC with weighted cascade or trivalency, LT with 1/indeg or random in-weights, the
+    general triggering model), seed-set size, number of runs and first run id are drawn per case."""
+    import paper_1404_0900_amd as tim
+    r = np.random.default_rng(4000 + cs)
+    n = int(r.integers(20, 3000))
+    m = int(min(n * (n - 1), n * r.uniform(1.0, 10.0)))
+    kind = ["ic-wc", "ic-trivalency", "lt", "lt-weighted", "trigger"][cs % 5]
+    size = int(r.integers(0, min(n, 60) + 1))
+    runs = int(r.integers(1, 2500))
+    first = int(r.integers(0, 1 << 40))
+    seed = int(r.integers(1, 1 << 62))
+    print(f"spread case {cs}: {kind} n={n} m={m} |S|={size} runs={runs} first={first}", file=sys.stderr, flush=True)
+    g = _graph(n, m, 900 + cs)
+    S = r.choice(n, size=size, replace=False).astype(np.int32)
+    thr, model = None, tim.IC
+    if kind == "ic-trivalency":
+        thr = synth.random_thresholds(g.m, cs, [synth.threshold_of(p) for p in synth.TRIVALENCY_P])
+        dg = eng.upload(g, thr=thr)
+    else:
+        dg = eng.upload(g)
+    if kind.startswith("lt"):
+        model = tim.LT
+        if kind == "lt-weighted":
+            thr = synth.random_lt_thresholds(g, 950 + cs, total=0.8)
+            eng.set_lt_weights(dg, g, thr)
+    if kind == "trigger":
+        model = tim.TRIGGER
+        thr = synth.random_triggering(g, 960 + cs, max_outcomes=3, max_size=3)
+        eng.set_triggering(dg, g, thr)
+    mean, total, counts = eng.spread(dg, model, seed, S, runs, first=first, per_run=True)
+    want = oracle.forward_spread(g, model, seed, first, runs, S, thr=thr)
+    assert np.array_equal(counts.cpu().numpy().astype(np.uint64), want)
+    assert total == int(want.sum())
+    eng.free(dg)
