@@ -187,3 +187,55 @@ def test_spread_random_case_equals_oracle(eng, cs):
     assert np.array_equal(counts.cpu().numpy().astype(np.uint64), want)
     assert total == int(want.sum())
     eng.free(dg)
+
+
+def _sorted_sets(so, nodes):
+    out = nodes.copy()
+    for i in range(len(so) - 1):
+        out[so[i]:so[i + 1]] = np.sort(nodes[so[i]:so[i + 1]])
+    return so, out
+
+
+@pytest.mark.parametrize("cs", range(10))
+def test_rr_sets_random_case_equal_oracle(eng, cs):
+    """Every RR set (sorted), its width and the launch totals on seeded random graphs: the model and
+    its weights, the phase, the first set id (up to 2^45) and the count are drawn per case, so that
+    launches take the 64-lane or the 8-lane first tier and sets of every size reach every tier."""
+    import paper_1404_0900_amd as tim
+    r = np.random.default_rng(5000 + cs)
+    n = int(r.integers(10, 6000))
+    m = int(min(n * (n - 1), n * r.uniform(1.0, 14.0)))
+    kind = ["ic-wc", "ic-trivalency", "ic-high", "lt", "lt-weighted", "trigger"][cs % 6]
+    phase = int(r.integers(1, 65))
+    first = int(r.integers(0, 1 << 45))
+    count = int(r.integers(1, 300_000))
+    if kind in ("ic-high", "trigger"):
+        count = count % 5000 + 1  # sets of thousands of nodes (a giant reverse-reachable component)
+    seed = int(r.integers(1, 1 << 62))
+    print(f"sets case {cs}: {kind} n={n} m={m} phase={phase} first={first} count={count}", file=sys.stderr,
+          flush=True)
+    g = _graph(n, m, 1100 + cs)
+    thr, model = None, tim.IC
+    if kind in ("ic-trivalency", "ic-high"):
+        ps = synth.TRIVALENCY_P if kind == "ic-trivalency" else (0.5, 0.25, 0.1)
+        thr = synth.random_thresholds(g.m, cs, [synth.threshold_of(p) for p in ps])
+        dg = eng.upload(g, thr=thr)
+    else:
+        dg = eng.upload(g)
+    if kind.startswith("lt"):
+        model = tim.LT
+        if kind == "lt-weighted":
+            thr = synth.random_lt_thresholds(g, 1150 + cs)
+            eng.set_lt_weights(dg, g, thr)
+    if kind == "trigger":
+        model = tim.TRIGGER
+        thr = synth.random_triggering(g, 1160 + cs, max_outcomes=4, max_size=4)
+        eng.set_triggering(dg, g, thr)
+    so, nodes, widths, st = eng.sample_rr(dg, model, seed, phase, first, count)
+    so, nd = _sorted_sets(so.cpu().numpy(), nodes.cpu().numpy())
+    wso, wnd, ww = oracle.sample_sets(g, model, seed, phase, first, count, thr=thr)
+    assert np.array_equal(so, wso)
+    assert np.array_equal(nd, wnd)
+    assert np.array_equal(widths.cpu().numpy().astype(np.uint64), ww)
+    assert st.node_sum == len(wnd) and st.width_sum == int(ww.sum())
+    eng.free(dg)
