@@ -132,6 +132,17 @@ __global__ void set_sizes_kernel(const int64_t* set_off, uint32_t* sizes, uint64
     sizes[s] = (uint32_t)(set_off[s + 1] - set_off[s]);
 }
 
+// Counters that many blocks update with device atomics sit one per 128-byte
+// line (32 words apart): atomics on different words of one line wait for each
+// other.  The counting sort's per-bucket counts and cursors took 0.45 ms more
+// per TIM+ step on the 1M-node graph packed 32 to a line.
+constexpr int kLinePad = 32;
+
+__global__ void unpad_u32(const uint32_t* in, uint32_t* out, int n) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) out[i] = in[(size_t)i * kLinePad];
+}
+
 __global__ void zero_u32(uint32_t* p, uint64_t len) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < len; i += stride) p[i] = 0u;
@@ -401,7 +412,7 @@ constexpr int kBucketShiftMin = 13, kBucketShiftMax = 13;
 constexpr int kBucketMax = 8192;             // buckets (LDS counters per tile of sets)
 constexpr uint32_t kBucketChunk = 1u << 16;  // entries per block of the per-bucket passes
 
-// bcnt[b] += entries of the collection in bucket b.
+// bcnt[b * kLinePad] += entries of the collection in bucket b.
 template <class V>
 __global__ __launch_bounds__(kThreads) void bucket_hist_kernel(V sets, uint64_t nsets, int shift, int nb,
                                                                uint32_t* bcnt) {
@@ -427,7 +438,7 @@ __global__ __launch_bounds__(kThreads) void bucket_hist_kernel(V sets, uint64_t 
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += kThreads)
-      if (h[i]) atomicAdd(&bcnt[i], h[i]);
+      if (h[i]) atomicAdd(&bcnt[(size_t)i * kLinePad], h[i]);
     __syncthreads();
   }
 }
@@ -481,7 +492,7 @@ __global__ __launch_bounds__(kThreads) void bucket_scatter_kernel(V sets, uint64
     }
     __syncthreads();
     for (int i = threadIdx.x; i < nb; i += kThreads)
-      if (h[i]) h[i] = (uint32_t)boff[i] + atomicAdd(&bfill[i], h[i]);
+      if (h[i]) h[i] = (uint32_t)boff[i] + atomicAdd(&bfill[(size_t)i * kLinePad], h[i]);
     __syncthreads();
     for (int64_t e = threadIdx.x; e < tot; e += kThreads) {
       const int j = tile_set_of(s_pre, TS, e);
@@ -733,7 +744,7 @@ size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 struct BucketLayout {
   int shift = 0, nb = 0;
   uint64_t max_chunks = 0;
-  size_t bcnt = 0, bfill = 0, boff = 0, cstart = 0, cb = 0, temp = 0, bu = 0, bs = 0, bytes = 0;
+  size_t bcnt = 0, bcnt_s = 0, bfill = 0, boff = 0, cstart = 0, cb = 0, temp = 0, bu = 0, bs = 0, bytes = 0;
 };
 
 // Offsets of the workspace's arrays; bytes == 0 where the collection does not
@@ -747,8 +758,10 @@ BucketLayout bucket_layout(int64_t n, uint64_t total, bool index) {
   size_t at = 0;
   L.bcnt = at;
   at += align256((size_t)L.nb * 4);
+  L.bcnt_s = at;
+  at += align256((size_t)L.nb * 4 * kLinePad);
   L.bfill = at;
-  at += align256((size_t)L.nb * 4);
+  at += align256((size_t)L.nb * 4 * kLinePad);
   L.boff = at;
   at += align256((size_t)(L.nb + 1) * 8);
   L.cstart = at;
@@ -775,16 +788,18 @@ T* at_offset(void* base, size_t off) {
 template <class V>
 void bucket_counts(const GreedyArgs& a, V sets, const BucketLayout& L, bool index, hipStream_t s) {
   uint32_t* bcnt = at_offset<uint32_t>(a.bkt, L.bcnt);
+  uint32_t* bcnt_s = at_offset<uint32_t>(a.bkt, L.bcnt_s);
   int64_t* boff = at_offset<int64_t>(a.bkt, L.boff);
   uint32_t* cstart = at_offset<uint32_t>(a.bkt, L.cstart);
   uint32_t* cb = at_offset<uint32_t>(a.bkt, L.cb);
   uint32_t* bu = at_offset<uint32_t>(a.bkt, L.bu);
   uint32_t* bs = index ? at_offset<uint32_t>(a.bkt, L.bs) : nullptr;
-  // bcnt and bfill are adjacent: one clear
-  hipLaunchKernelGGL(zero_u32, dim3(grid_for((uint64_t)(L.bfill - L.bcnt) / 4 + (uint64_t)L.nb, 64)), dim3(kThreads),
-                     0, s, bcnt, (uint64_t)(L.bfill - L.bcnt) / 4 + (uint64_t)L.nb);
+  // the padded counts and cursors are adjacent: one clear; the scan reads the counts unpadded
+  const uint64_t zlen = (uint64_t)(L.bfill - L.bcnt_s) / 4 + (uint64_t)L.nb * kLinePad;
+  hipLaunchKernelGGL(zero_u32, dim3(grid_for(zlen, 64)), dim3(kThreads), 0, s, bcnt_s, zlen);
   const unsigned grid = tile_grid(a.nsets, kHistTileSets);
-  hipLaunchKernelGGL(bucket_hist_kernel<V>, dim3(grid), dim3(kThreads), 0, s, sets, a.nsets, L.shift, L.nb, bcnt);
+  hipLaunchKernelGGL(bucket_hist_kernel<V>, dim3(grid), dim3(kThreads), 0, s, sets, a.nsets, L.shift, L.nb, bcnt_s);
+  hipLaunchKernelGGL(unpad_u32, dim3(grid_for((uint64_t)L.nb, 64)), dim3(kThreads), 0, s, bcnt_s, bcnt, L.nb);
   launch_scan_u32_to_i64(bcnt, boff, (uint64_t)L.nb, at_offset<void>(a.bkt, L.temp), s);
   hipLaunchKernelGGL(bucket_chunks_kernel, dim3(1), dim3(kThreads), 0, s, boff, L.nb, cstart, cb);
   uint32_t* bfill = at_offset<uint32_t>(a.bkt, L.bfill);
