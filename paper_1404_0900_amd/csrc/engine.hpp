@@ -23,15 +23,22 @@ enum SampleMode : int {
 // kAccStride * tier.  The cursors and list lengths, which every wavefront
 // updates with device atomics, sit in 128-byte lines of their own: atomics on
 // different words of one line wait for each other (a 4M-set stored-set launch
-// took 6% longer with them packed into one line).
+// took 6% longer with them packed into one line).  The first two tiers of the
+// single-job IC launches split their range into kCtrParts parts, each with
+// a cursor of its own: block b starts on part b mod kCtrParts (blocks take
+// turns over the XCDs) and moves on to the next part when its part is spent,
+// so that the wavefronts' refills meet on eight cursors instead of one (a TIM+
+// step on the 1M-node graph took 5% longer with one).
 enum Counter : int {
-  kCtrNext0 = 0,        // tier-0 cursor over the range
-  kCtrList1 = 16,       // length of list 1
-  kCtrNext1 = 32,       // tier-1 cursor over list 1
-  kCtrList2 = 48,       // length of list 2
-  kCtrNext2 = 64,       // last-tier cursor
-  kCtrPoolCursor = 80,  // node-pool entries reserved
-  kCtrAcc = 96,
+  kCtrParts = 8,         // cursors of tiers 0 and 1: one per part of their range
+  kCtrPartStride = 16,   // words between them
+  kCtrNext0 = 0,         // tier-0 cursors over the range (kCtrParts of them)
+  kCtrList1 = 128,       // length of list 1
+  kCtrNext1 = 144,       // tier-1 cursors over list 1 (kCtrParts of them)
+  kCtrList2 = 272,       // length of list 2
+  kCtrNext2 = 288,       // last-tier cursor
+  kCtrPoolCursor = 304,  // node-pool entries reserved
+  kCtrAcc = 320,
   kAccKappaLo = 0,     // exact sum of kappa * 2^53 (128 bits)
   kAccKappaHi = 1,
   kAccWidth = 2,       // sum of w(R): edges examined
@@ -49,6 +56,7 @@ struct TierIO {
   uint64_t* out_list;       // deferred sets (relative ids), capacity = count
   int out_len_ctr;
   int acc;                  // accumulator block (tier number)
+  int parts;                // 0 or 1: one cursor at next_ctr; else `parts` cursors kCtrPartStride apart, one per part
 };
 
 // Node-pool entries a wavefront reserves at a time when it stores sets (the

@@ -340,6 +340,7 @@ __device__ __forceinline__ unsigned long long list_len(const SampleArgs& a, int 
 // Wave-uniform reservoir of work items [cur, end), refilled `chunk` at a time.
 struct Reservoir {
   unsigned long long cur = 0, end = 0, chunk = 1;
+  int part = 0, tried = 0;  // the part of the range being taken, and parts found spent
 };
 
 // Items per refill: about 4 refills per wavefront over the launch (each is a
@@ -413,18 +414,31 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
                                          bool& exhausted, unsigned long long& rel, int32_t& root) {
   bool got = false;
   unsigned long long item = 0;
+  const int parts = io.parts > 1 ? io.parts : 1;
   uint64_t wmask = __ballot(want && is_leader);
   while (wmask) {
     if (r.cur >= r.end) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&a.ctr[io.next_ctr], r.chunk);
-      base = __shfl(base, 0);
-      if (base >= total) {
+      // refill from the current part; a spent part sends the wavefront on to the next one
+      bool refilled = false;
+      while (r.tried < parts) {
+        const unsigned long long pb = total * (unsigned long long)r.part / (unsigned long long)parts;
+        const unsigned long long pe = total * (unsigned long long)(r.part + 1) / (unsigned long long)parts;
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&a.ctr[io.next_ctr + kCtrPartStride * r.part], r.chunk);
+        base = __shfl(base, 0);
+        if (pb + base < pe) {
+          r.cur = pb + base;
+          r.end = min(pb + base + r.chunk, pe);
+          refilled = true;
+          break;
+        }
+        r.tried += 1;
+        r.part = r.part + 1 == parts ? 0 : r.part + 1;
+      }
+      if (!refilled) {
         if (want) exhausted = true;
         break;
       }
-      r.cur = base;
-      r.end = min(base + r.chunk, total);
     }
     const unsigned long long avail = r.end - r.cur;
     const unsigned long long nw = (unsigned long long)__popcll(wmask);
@@ -495,6 +509,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
+  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);  // blocks take turns over the XCDs
   RootBuffer rb;
   unsigned long long pool_next = 0, pool_end = 0;  // wavefront's slice of the node pool
 
@@ -2006,9 +2021,9 @@ void launch_kappa_reduce(const SampleArgs& a, hipStream_t s) {
 template <int MODE, bool WC>
 void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, hipEvent_t after0) {
   const dim3 blk(kSegThreads);
-  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
-  const TierIO t1 = {a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1};
-  const TierIO t2 = {a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2};
+  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0, kCtrParts};
+  const TierIO t1 = {a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1, kCtrParts};
+  const TierIO t2 = {a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2, 1};
   switch (S) {
     case 4: hipLaunchKernelGGL((SegKernel<MODE, WC, 4>::fn), dim3(grid0), blk, 0, s, a, t0); break;
     case 8: hipLaunchKernelGGL((SegKernel<MODE, WC, 8>::fn), dim3(grid0), blk, 0, s, a, t0); break;
