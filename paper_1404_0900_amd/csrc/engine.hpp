@@ -24,11 +24,12 @@ enum SampleMode : int {
 // updates with device atomics, sit in 128-byte lines of their own: atomics on
 // different words of one line wait for each other (a 4M-set stored-set launch
 // took 6% longer with them packed into one line).  The first two tiers of the
-// single-job IC launches split their range into kCtrParts parts, each with
-// a cursor of its own: block b starts on part b mod kCtrParts (blocks take
-// turns over the XCDs) and moves on to the next part when its part is spent,
-// so that the wavefronts' refills meet on eight cursors instead of one (a TIM+
-// step on the 1M-node graph took 5% longer with one).
+// single-job launches (IC, triggering; the LT lane tier) split their range
+// into kCtrParts parts, each with a cursor of its own: block b starts on part
+// b mod kCtrParts (blocks take turns over the XCDs) and moves on to the next
+// part when its part is spent, so that the wavefronts' refills meet on eight
+// cursors instead of one (with one, a TIM+ step on the 1M-node graph took 5%
+// longer under IC and 18% longer under LT).
 enum Counter : int {
   kCtrParts = 8,         // cursors of tiers 0 and 1: one per part of their range
   kCtrPartStride = 16,   // words between them

@@ -354,25 +354,42 @@ __device__ __forceinline__ unsigned long long chunk_for(unsigned long long total
   return c > 64ull * per_wave ? 64ull * per_wave : c;
 }
 
+// Refills a wavefront's reservoir from its part of [0, total) (parts > 1:
+// the range is split into `parts` parts with a cursor each, kCtrPartStride
+// words apart from next_ctr); a spent part sends the wavefront on to the next
+// one.  False once every part is spent.
+__device__ __forceinline__ bool refill(const SampleArgs& a, int next_ctr, int parts, unsigned long long total,
+                                       Reservoir& r, int lane) {
+  if (parts < 1) parts = 1;
+  while (r.tried < parts) {
+    const unsigned long long pb = total * (unsigned long long)r.part / (unsigned long long)parts;
+    const unsigned long long pe = total * (unsigned long long)(r.part + 1) / (unsigned long long)parts;
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&a.ctr[next_ctr + kCtrPartStride * r.part], r.chunk);
+    base = __shfl(base, 0);
+    if (pb + base < pe) {
+      r.cur = pb + base;
+      r.end = min(pb + base + r.chunk, pe);
+      return true;
+    }
+    r.tried += 1;
+    r.part = r.part + 1 == parts ? 0 : r.part + 1;
+  }
+  return false;
+}
+
 // Hands one work item to every requester (lanes with want && is_leader); all
 // lanes of a segment see their leader's result through below_leader.  Lanes
 // that get nothing because the work is gone set exhausted.
-__device__ __forceinline__ bool take(const SampleArgs& a, int next_ctr, unsigned long long total, Reservoir& r,
-                                     bool want, bool is_leader, uint64_t below_leader, int lane, bool& exhausted,
-                                     unsigned long long& item) {
+__device__ __forceinline__ bool take(const SampleArgs& a, int next_ctr, int parts, unsigned long long total,
+                                     Reservoir& r, bool want, bool is_leader, uint64_t below_leader, int lane,
+                                     bool& exhausted, unsigned long long& item) {
   bool got = false;
   uint64_t wmask = __ballot(want && is_leader);
   while (wmask) {
-    if (r.cur >= r.end) {
-      unsigned long long base = 0;
-      if (lane == 0) base = atomicAdd(&a.ctr[next_ctr], r.chunk);
-      base = __shfl(base, 0);
-      if (base >= total) {
-        if (want) exhausted = true;
-        break;
-      }
-      r.cur = base;
-      r.end = min(base + r.chunk, total);
+    if (r.cur >= r.end && !refill(a, next_ctr, parts, total, r, lane)) {
+      if (want) exhausted = true;
+      break;
     }
     const unsigned long long avail = r.end - r.cur;
     const unsigned long long rank = (unsigned long long)__popcll(wmask & below_leader);
@@ -414,31 +431,11 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
                                          bool& exhausted, unsigned long long& rel, int32_t& root) {
   bool got = false;
   unsigned long long item = 0;
-  const int parts = io.parts > 1 ? io.parts : 1;
   uint64_t wmask = __ballot(want && is_leader);
   while (wmask) {
-    if (r.cur >= r.end) {
-      // refill from the current part; a spent part sends the wavefront on to the next one
-      bool refilled = false;
-      while (r.tried < parts) {
-        const unsigned long long pb = total * (unsigned long long)r.part / (unsigned long long)parts;
-        const unsigned long long pe = total * (unsigned long long)(r.part + 1) / (unsigned long long)parts;
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&a.ctr[io.next_ctr + kCtrPartStride * r.part], r.chunk);
-        base = __shfl(base, 0);
-        if (pb + base < pe) {
-          r.cur = pb + base;
-          r.end = min(pb + base + r.chunk, pe);
-          refilled = true;
-          break;
-        }
-        r.tried += 1;
-        r.part = r.part + 1 == parts ? 0 : r.part + 1;
-      }
-      if (!refilled) {
-        if (want) exhausted = true;
-        break;
-      }
+    if (r.cur >= r.end && !refill(a, io.next_ctr, io.parts, total, r, lane)) {
+      if (want) exhausted = true;
+      break;
     }
     const unsigned long long avail = r.end - r.cur;
     const unsigned long long nw = (unsigned long long)__popcll(wmask);
@@ -862,6 +859,7 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(a.count, kLtWaves, kWave);
+  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);
   unsigned long long pool_next = 0, pool_end = 0;
 
   bool active = false, exhausted = false, hit = false;
@@ -873,7 +871,7 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
   for (;;) {
     {
       unsigned long long item = 0;
-      if (take(a, io.next_ctr, a.count, res, !active && !exhausted, true, below, lane, exhausted, item)) {
+      if (take(a, io.next_ctr, io.parts, a.count, res, !active && !exhausted, true, below, lane, exhausted, item)) {
         rel = item;
         st = make_set_stream(a.phase, a.first + rel);
         v = draw_root(key, st, g.n);
@@ -1176,11 +1174,12 @@ __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO&
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kTrigWaves, 1);
+  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);
   unsigned long long pool_next = 0, pool_end = 0;
   bool exhausted = false;
   for (;;) {
     unsigned long long item = 0;
-    if (!take(a, io.next_ctr, total, res, !exhausted, lane == 0, 0ull, lane, exhausted, item)) break;
+    if (!take(a, io.next_ctr, io.parts, total, res, !exhausted, lane == 0, 0ull, lane, exhausted, item)) break;
     const unsigned long long rel = io.in_list ? io.in_list[item] : item;
     const SetStream st = make_set_stream(a.phase, a.first + rel);
     const int32_t root = draw_root(key, st, g.n);
@@ -1294,6 +1293,7 @@ __global__ __launch_bounds__(kSegThreads) void trig_seg_kernel(SampleArgs a, Tie
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
+  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);
   RootBuffer rb;
   unsigned long long pool_next = 0, pool_end = 0;
   // segment state (the same in every lane of a segment)
@@ -1606,7 +1606,7 @@ __device__ __forceinline__ void lt_chain_run(const SampleArgs& a, const TierIO& 
   for (;;) {
     {
       unsigned long long item = 0;
-      if (take(a, io.next_ctr, total, res, phase == kIdle && !exhausted, true, below, lane, exhausted, item)) {
+      if (take(a, io.next_ctr, 1, total, res, phase == kIdle && !exhausted, true, below, lane, exhausted, item)) {
         rel = io.in_list[item];
         st = make_set_stream(a.phase, a.first + rel);
         x0 = draw_root(key, st, g.n);
@@ -2039,9 +2039,9 @@ void launch_ic(const SampleArgs& a, int S, int grid0, int grid1, hipStream_t s, 
 
 template <int MODE>
 void launch_trig(const SampleArgs& a, int grid0, int grid1, hipStream_t s, hipEvent_t after0) {
-  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
-  const TierIO t1 = {a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1};
-  const TierIO t2 = {a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2};
+  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0, kCtrParts};
+  const TierIO t1 = {a.list1, kCtrList1, kCtrNext1, a.list2, kCtrList2, 1, kCtrParts};
+  const TierIO t2 = {a.list2, kCtrList2, kCtrNext2, nullptr, 0, 2, 1};
   hipLaunchKernelGGL((trig_seg_kernel<MODE>), dim3(grid0), dim3(kSegThreads), 0, s, a, t0);
   if (after0) (void)hipEventRecord(after0, s);
   hipLaunchKernelGGL((trig_wave_kernel<MODE>), dim3(grid1), dim3(kTrigWaves * kWave), 0, s, a, t1);
@@ -2051,8 +2051,8 @@ void launch_trig(const SampleArgs& a, int grid0, int grid1, hipStream_t s, hipEv
 
 template <int MODE>
 void launch_lt(const SampleArgs& a, int grid0, int grid2, hipStream_t s, hipEvent_t after0) {
-  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0};
-  const TierIO t2 = {a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2};
+  const TierIO t0 = {nullptr, 0, kCtrNext0, a.list1, kCtrList1, 0, kCtrParts};
+  const TierIO t2 = {a.list1, kCtrList1, kCtrNext2, nullptr, 0, 2, 1};
   hipLaunchKernelGGL((lt_lane_kernel<MODE>), dim3(grid0), dim3(kLtWaves * kWave), 0, s, a, t0);
   if (after0) (void)hipEventRecord(after0, s);
   hipLaunchKernelGGL((lt_chain_kernel<MODE>), dim3(grid2), dim3(kChainWaves * kWave), 0, s, a, t2);
