@@ -237,7 +237,7 @@ __device__ __forceinline__ unsigned long long pool_place(const SampleArgs& a, un
   const bool fits = (unsigned long long)winc <= room;
   const uint64_t fm = __ballot(fits);  // a prefix of the lanes: winc grows with the lane
   const int nfit = __popcll(fm);
-  const uint32_t used = nfit ? __shfl(winc, nfit - 1) : 0u;
+  const uint32_t used = nfit ? (uint32_t)__builtin_amdgcn_readlane((int)winc, nfit - 1) : 0u;
   unsigned long long pos = pool_next + (unsigned long long)(winc - mine);
   if (used == tot) {
     pool_next += tot;
@@ -247,7 +247,8 @@ __device__ __forceinline__ unsigned long long pool_place(const SampleArgs& a, un
   const unsigned long long want = max(slice, rest);
   unsigned long long got = 0;
   if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want);
-  got = __shfl(got, 0);
+  got = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(got >> 32)) << 32) |
+        (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)got);
   if (!fits) pos = got + (unsigned long long)(winc - mine - used);
   pool_next = got + rest;
   pool_end = got + want;
@@ -354,28 +355,42 @@ __device__ __forceinline__ unsigned long long chunk_for(unsigned long long total
   return c > 64ull * per_wave ? 64ull * per_wave : c;
 }
 
-// Refills a wavefront's reservoir from its part of [0, total) (parts > 1:
-// the range is split into `parts` parts with a cursor each, kCtrPartStride
-// words apart from next_ctr); a spent part sends the wavefront on to the next
-// one.  False once every part is spent.
-__device__ __forceinline__ bool refill(const SampleArgs& a, int next_ctr, int parts, unsigned long long total,
-                                       Reservoir& r, int lane) {
-  if (parts < 1) parts = 1;
-  while (r.tried < parts) {
-    const unsigned long long pb = total * (unsigned long long)r.part / (unsigned long long)parts;
-    const unsigned long long pe = total * (unsigned long long)(r.part + 1) / (unsigned long long)parts;
+// Refills a wavefront's reservoir from its part of [0, total).  SPLIT: the
+// range is split into kCtrParts parts (a power of two, so the bounds are
+// shifts) with a cursor each, kCtrPartStride words apart from next_ctr, and a
+// spent part sends the wavefront on to the next one; else one cursor at
+// next_ctr.  False once every part is spent.  Cursor values and the part
+// reach the wavefront through readfirstlane, which keeps the reservoir in
+// scalar registers (with __shfl they took vector registers, and the stored-
+// set kernel fell from 6 to 5 wavefronts per SIMD).
+template <bool SPLIT>
+__device__ __forceinline__ bool refill_parts(const SampleArgs& a, int next_ctr, unsigned long long total, Reservoir& r,
+                                             int lane) {
+  constexpr int np = SPLIT ? (int)kCtrParts : 1;
+  r.part = __builtin_amdgcn_readfirstlane(r.part);
+  r.tried = __builtin_amdgcn_readfirstlane(r.tried);
+  while (r.tried < np) {
+    const unsigned long long pb = SPLIT ? total * (unsigned long long)r.part / kCtrParts : 0ull;
+    const unsigned long long pe = SPLIT ? total * (unsigned long long)(r.part + 1) / kCtrParts : total;
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(&a.ctr[next_ctr + kCtrPartStride * r.part], r.chunk);
-    base = __shfl(base, 0);
+    base = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(base >> 32)) << 32) |
+           (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)base);
     if (pb + base < pe) {
       r.cur = pb + base;
       r.end = min(pb + base + r.chunk, pe);
       return true;
     }
     r.tried += 1;
-    r.part = r.part + 1 == parts ? 0 : r.part + 1;
+    r.part = r.part + 1 == np ? 0 : r.part + 1;
   }
   return false;
+}
+
+// refill_parts for a part count given at run time (TierIO::parts: 0, 1 or kCtrParts).
+__device__ __forceinline__ bool refill(const SampleArgs& a, int next_ctr, int parts, unsigned long long total,
+                                       Reservoir& r, int lane) {
+  return parts > 1 ? refill_parts<true>(a, next_ctr, total, r, lane) : refill_parts<false>(a, next_ctr, total, r, lane);
 }
 
 // Hands one work item to every requester (lanes with want && is_leader); all
@@ -426,6 +441,7 @@ __device__ __forceinline__ void fill_roots(const SampleArgs& a, const TierIO& io
 
 // take() for the IC kernels: hands one item to every requesting segment and
 // returns its set id and root from the wavefront's root buffer.
+template <bool SPLIT>
 __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, unsigned long long total, Reservoir& r,
                                          RootBuffer& rb, bool want, bool is_leader, uint64_t below_leader, int lane,
                                          bool& exhausted, unsigned long long& rel, int32_t& root) {
@@ -433,7 +449,7 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
   unsigned long long item = 0;
   uint64_t wmask = __ballot(want && is_leader);
   while (wmask) {
-    if (r.cur >= r.end && !refill(a, io.next_ctr, io.parts, total, r, lane)) {
+    if (r.cur >= r.end && !refill_parts<SPLIT>(a, io.next_ctr, total, r, lane)) {
       if (want) exhausted = true;
       break;
     }
@@ -473,7 +489,7 @@ __device__ __forceinline__ bool take_set(const SampleArgs& a, const TierIO& io, 
 // first_only: a launch of its own over one deferred list, whose wavefronts
 // beyond the first ones the list needs leave at once instead of each taking
 // a turn at the list's cursor.
-template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
+template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R, bool SPLIT = false>
 __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io, bool first_only,
                                            BlockAcc* blk = nullptr) {
   constexpr bool kHash = HLOG > 0;
@@ -506,7 +522,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
-  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);  // blocks take turns over the XCDs
+  if (SPLIT) res.part = (int)(blockIdx.x % (unsigned)kCtrParts);  // blocks take turns over the XCDs
   RootBuffer rb;
   unsigned long long pool_next = 0, pool_end = 0;  // wavefront's slice of the node pool
 
@@ -558,7 +574,8 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
       if (dm) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(&a.ctr[io.out_len_ctr], (unsigned long long)__popcll(dm));
-        base = __shfl(base, 0);
+        base = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(base >> 32)) << 32) |
+               (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)base);
         if (dl) {
           const unsigned long long pos = base + (unsigned long long)__popcll(dm & below);
           if (pos < a.count) io.out_list[pos] = rel;
@@ -597,7 +614,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
     {
       int32_t root = 0;
       const bool want = !has && !exhausted;
-      if (take_set(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
+      if (take_set<SPLIT>(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
         st = make_set_stream(a.phase, a.first + rel);
         if (kHash) {
           uint4* h4 = reinterpret_cast<uint4*>(h);
@@ -796,11 +813,12 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
   flush_acc(a, blk, acc, io.acc, lane);
 }
 
+// Single launches only (launch_ic): their tiers 0 and 1 take sets from kCtrParts cursors.
 template <int MODE, bool WC, int S, int Q, int HLOG, int GMAX, int R>
 __global__ __launch_bounds__(kSegThreads) void ic_seg_kernel(SampleArgs a, TierIO io) {
   __shared__ BlockAcc blk;
   block_acc_init(blk);
-  ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R>(a, io, true, &blk);
+  ic_seg_run<MODE, WC, S, Q, HLOG, GMAX, R, true>(a, io, true, &blk);
 }
 
 // Exact sum of kappa(R) * 2^53 over the widths a width-mode launch wrote
@@ -859,7 +877,7 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(a.count, kLtWaves, kWave);
-  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);
+  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)kCtrParts);
   unsigned long long pool_next = 0, pool_end = 0;
 
   bool active = false, exhausted = false, hit = false;
@@ -1174,7 +1192,7 @@ __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO&
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kTrigWaves, 1);
-  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);
+  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)kCtrParts);
   unsigned long long pool_next = 0, pool_end = 0;
   bool exhausted = false;
   for (;;) {
@@ -1293,7 +1311,7 @@ __global__ __launch_bounds__(kSegThreads) void trig_seg_kernel(SampleArgs a, Tie
   Acc acc;
   Reservoir res;
   res.chunk = chunk_for(total, kSegThreads / kWave, kWave / S);
-  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)io.parts);
+  if (io.parts > 1) res.part = (int)(blockIdx.x % (unsigned)kCtrParts);
   RootBuffer rb;
   unsigned long long pool_next = 0, pool_end = 0;
   // segment state (the same in every lane of a segment)
@@ -1372,7 +1390,7 @@ __global__ __launch_bounds__(kSegThreads) void trig_seg_kernel(SampleArgs a, Tie
     {
       int32_t root = 0;
       const bool want = !has && !exhausted;
-      if (take_set(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
+      if (take_set<true>(a, io, total, res, rb, want, is_leader, below_leader, lane, exhausted, rel, root)) {
         st = make_set_stream(a.phase, a.first + rel);
         uint4* h4 = reinterpret_cast<uint4*>(h);
         for (int i = sl; i < H / 4; i += S) h4[i] = make_uint4(0u, 0u, 0u, 0u);
