@@ -56,6 +56,15 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Lane 0's value in every lane, as a wave-uniform (scalar-register) value:
+// device-atomic results that lane 0 fetched for the whole wavefront.  Through
+// __shfl the compiler keeps them, and what is derived from them, in vector
+// registers.
+__device__ __forceinline__ unsigned long long lane0_u64(unsigned long long x) {
+  return ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(x >> 32)) << 32) |
+         (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)x);
+}
+
 // x from the lane O below in the same 16-lane DPP row (0 where that leaves the row).
 template <int O>
 __device__ __forceinline__ uint32_t dpp_row_shr(uint32_t x) {
@@ -247,8 +256,7 @@ __device__ __forceinline__ unsigned long long pool_place(const SampleArgs& a, un
   const unsigned long long want = max(slice, rest);
   unsigned long long got = 0;
   if (lane == 0) got = atomicAdd(&a.ctr[kCtrPoolCursor], want);
-  got = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(got >> 32)) << 32) |
-        (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)got);
+  got = lane0_u64(got);
   if (!fits) pos = got + (unsigned long long)(winc - mine - used);
   pool_next = got + rest;
   pool_end = got + want;
@@ -374,8 +382,7 @@ __device__ __forceinline__ bool refill_parts(const SampleArgs& a, int next_ctr, 
     const unsigned long long pe = SPLIT ? total * (unsigned long long)(r.part + 1) / kCtrParts : total;
     unsigned long long base = 0;
     if (lane == 0) base = atomicAdd(&a.ctr[next_ctr + kCtrPartStride * r.part], r.chunk);
-    base = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(base >> 32)) << 32) |
-           (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)base);
+    base = lane0_u64(base);
     if (pb + base < pe) {
       r.cur = pb + base;
       r.end = min(pb + base + r.chunk, pe);
@@ -574,8 +581,7 @@ __device__ __forceinline__ void ic_seg_run(const SampleArgs& a, const TierIO& io
       if (dm) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(&a.ctr[io.out_len_ctr], (unsigned long long)__popcll(dm));
-        base = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(base >> 32)) << 32) |
-               (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)base);
+        base = lane0_u64(base);
         if (dl) {
           const unsigned long long pos = base + (unsigned long long)__popcll(dm & below);
           if (pos < a.count) io.out_list[pos] = rel;
@@ -948,7 +954,7 @@ __device__ __forceinline__ void lt_lane_run(const SampleArgs& a, const TierIO& i
       if (dm) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(&a.ctr[io.out_len_ctr], (unsigned long long)__popcll(dm));
-        base = __shfl(base, 0);
+        base = lane0_u64(base);
         if (bad) {
           const unsigned long long pos = base + (unsigned long long)__popcll(dm & below);
           if (pos < a.count) io.out_list[pos] = rel;
@@ -1258,7 +1264,7 @@ __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO&
       // tier 0 reserves slices; the deferral tiers (few sets) exactly what they store
       const unsigned long long slice = io.acc == 0 ? (unsigned long long)a.pool_chunk : 0ull;
       const unsigned long long my_base = pool_place(a, slice, mine, len, len, pool_next, pool_end, lane);
-      const unsigned long long base = __shfl(my_base, 0);
+      const unsigned long long base = lane0_u64(my_base);
       if (base + len <= a.pool_cap)
         for (uint32_t i = lane; i < len; i += kWave) a.pool[base + i] = q[i];
       if (lane == 0) {
@@ -1354,7 +1360,7 @@ __global__ __launch_bounds__(kSegThreads) void trig_seg_kernel(SampleArgs a, Tie
       if (dm) {
         unsigned long long base = 0;
         if (lane == 0) base = atomicAdd(&a.ctr[io.out_len_ctr], (unsigned long long)__popcll(dm));
-        base = __shfl(base, 0);
+        base = lane0_u64(base);
         if (dl) {
           const unsigned long long pos = base + (unsigned long long)__popcll(dm & below);
           if (pos < a.count) io.out_list[pos] = rel;
