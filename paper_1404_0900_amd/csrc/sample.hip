@@ -353,8 +353,8 @@ struct Reservoir {
 };
 
 // Items per refill: about 4 refills per wavefront over the launch (each is a
-// device atomic on the one work cursor, and those serialize), at least one
-// item per requester, at most 64 per requester.
+// device atomic on a work cursor, and those on one cursor serialize), at
+// least one item per requester, at most 64 per requester.
 __device__ __forceinline__ unsigned long long chunk_for(unsigned long long total, int waves_per_block,
                                                         int per_wave) {
   const unsigned long long waves = (unsigned long long)gridDim.x * (unsigned long long)waves_per_block;
