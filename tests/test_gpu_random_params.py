@@ -239,3 +239,32 @@ def test_rr_sets_random_case_equal_oracle(eng, cs):
     assert np.array_equal(widths.cpu().numpy().astype(np.uint64), ww)
     assert st.node_sum == len(wnd) and st.width_sum == int(ww.sum())
     eng.free(dg)
+
+
+@pytest.mark.parametrize("kind", ["ic-high", "lt", "trigger"])
+def test_rr_sets_few_sets_per_launch_equal_oracle(eng, kind):
+    """Launches of 1 to 65 sets: fewer sets than work-cursor parts (eight per tier), ragged part
+    sizes, and sets large enough to be deferred to the later tiers."""
+    import paper_1404_0900_amd as tim
+    g = _graph(1500, 12000, 77)
+    thr, model = None, tim.IC
+    if kind == "ic-high":
+        thr = synth.random_thresholds(g.m, 78, [synth.threshold_of(p) for p in (0.5, 0.25, 0.1)])
+        dg = eng.upload(g, thr=thr)
+    else:
+        dg = eng.upload(g)
+    if kind == "lt":
+        model = tim.LT
+    if kind == "trigger":
+        model = tim.TRIGGER
+        thr = synth.random_triggering(g, 79, max_outcomes=4, max_size=4, p_full=1.0)
+        eng.set_triggering(dg, g, thr)
+    for count in (1, 2, 3, 7, 8, 9, 15, 16, 17, 63, 64, 65):
+        print(f"few sets: {kind} count={count}", file=sys.stderr, flush=True)
+        so, nodes, widths, st = eng.sample_rr(dg, model, 5, 9, 1000 + count, count)
+        so, nd = _sorted_sets(so.cpu().numpy(), nodes.cpu().numpy())
+        wso, wnd, ww = oracle.sample_sets(g, model, 5, 9, 1000 + count, count, thr=thr)
+        assert np.array_equal(so, wso), count
+        assert np.array_equal(nd, wnd), count
+        assert np.array_equal(widths.cpu().numpy().astype(np.uint64), ww), count
+    eng.free(dg)
