@@ -67,9 +67,9 @@ MODES = ("widths", "store", "cover")
 # picks on this graph.  Valid only for the kernel sources they were taken on.
 TRAFFIC = {
     "ic_seg_kernel<1, true, 8, 128, 0, 512, 1> (store)": {
-        "sources_sha256_16": "87cd8b5ff7bcc7d4", "taken": "2026-12-03", "fetch_bytes": 2906416891, "write_bytes": 572453424},
+        "sources_sha256_16": "f04a4aa503ad565e", "taken": "2026-12-03", "fetch_bytes": 2906637862, "write_bytes": 571520432},
     "ic_seg_kernel<0, true, 8, 128, 0, 512, 1> (widths)": {
-        "sources_sha256_16": "87cd8b5ff7bcc7d4", "taken": "2026-12-03", "fetch_bytes": 2644685652, "write_bytes": 104169899},
+        "sources_sha256_16": "f04a4aa503ad565e", "taken": "2026-12-03", "fetch_bytes": 2645093577, "write_bytes": 104174699},
 }
 KERNEL_SOURCES = ("paper_1404_0900_amd/csrc/sample.hip", "paper_1404_0900_amd/csrc/rng.hpp",
                   "paper_1404_0900_amd/csrc/pick.hpp", "paper_1404_0900_amd/csrc/engine.hpp")

@@ -1295,9 +1295,12 @@ __device__ __forceinline__ void trig_wave_run(const SampleArgs& a, const TierIO&
   flush_acc(a, blk, acc, io.acc, lane);
 }
 
-// Tier 0 of the triggering model (see above).
+// Tier 0 of the triggering model (see above).  Its LDS admits 6 blocks of 4 wavefronts per
+// CU; the request for 6 wavefronts per SIMD brings the storing mode from 81 to 79 VGPRs (it
+// ran 5) without spilling, and TIM+ on this model about 1% faster.
 template <int MODE>
-__global__ __launch_bounds__(kSegThreads) void trig_seg_kernel(SampleArgs a, TierIO io) {
+__global__ __launch_bounds__(kSegThreads) __attribute__((amdgpu_waves_per_eu(6, 8)))
+void trig_seg_kernel(SampleArgs a, TierIO io) {
   constexpr int S = kTrigSegLanes, Q = kTrigSegQ, H = 1 << kTrigSegHlog;
   constexpr int NSEG = kSegThreads / S;
   __shared__ int32_t s_q[NSEG][Q];
